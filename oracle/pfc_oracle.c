@@ -1,0 +1,494 @@
+/*
+ * pfc_oracle.c -- plain FP64 CPU oracle for the pseudo-spectral phase-field-crystal (PFC) step.
+ *
+ * TEST INFRASTRUCTURE ONLY.  Only the test suite, the smoke check and the CPU-baseline leg of the
+ * benchmark load this library.  It shares no code, header, table or helper with the HIP library.
+ *
+ * What it computes (arxiv 2603.26818, "Multi-GPU fast Fourier transforms in MATLAB for large-scale
+ * phase-field crystal simulations"):
+ *   - the discrete Fourier transform used by the Fourier pseudo-spectral method (section "Fourier
+ *     pseudo-spectral method", Eq. (2) and the paragraph after it): forward e^{-ikx} unnormalised,
+ *     inverse with 1/N, computed by a textbook recursive radix-2 Cooley-Tukey FFT applied
+ *     row-column along every axis;
+ *   - the PFC free energy, Eq. (3), and the PFC dynamics, Eq. (4), with the correlation operator
+ *     written as a polynomial in q = |k|^2 (Eq. (2): a derivative of order n becomes (ik)^n);
+ *   - the semi-implicit step of Listing 1 (the update of psiF): the cubic term is evaluated
+ *     pointwise in real space and transformed, the linear part is treated implicitly,
+ *         psiF <- (psiF + dt*lap*FFT(psi^3)) / (1 - dt*lin),   lap = -q,   lin = -q (eps + L(q)),
+ *     followed by the inverse transform back to real space;
+ *   - the discrete adjoint (transpose of the Jacobian) of that step, used for gradients.
+ *
+ * Readings where the paper is silent (each is listed with its reason in the design notes):
+ *   - fields are real, so the spectral state is the half spectrum [n0][n1][n2/2+1]; after every
+ *     forward transform and every update the two self-conjugate planes kx = 0 and kx = n2/2 are
+ *     projected onto Hermitian symmetry, X(k) <- (X(k) + conj X(-k))/2.  In exact arithmetic this
+ *     changes nothing; without it a half-spectrum state drifts away from any real field;
+ *   - the correlation operator is parameterised as L(q) = (1-q)^2 for the one-mode model and
+ *     L(q) = (1-q)^2 ((Q1^2 - q)^2 + R1) for the two-mode model (the paper's FCC operator is
+ *     Q1^2 = 4/3, R1 = 0); the paper's undercooling eps is called r here;
+ *   - wavenumbers k_j = 2 pi m_j / (n_j dx_j) with m_j in {0..n/2, -n/2+1..-1}.
+ *
+ * Arrays are C-order, last index fastest (x).  Complex arrays are interleaved (re, im) doubles.
+ * Parallelism: OpenMP over independent lines and points only.
+ */
+#include <complex.h>
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+typedef double complex cplx;
+
+/* pi to double precision (PI is not part of strict ISO C). */
+static const double PI = 3.14159265358979323846264338327950288;
+
+#define OR_OK 0
+#define OR_ERR_ARG 1
+#define OR_ERR_MEM 2
+
+typedef struct {
+    int ndim;          /* 1, 2 or 3 */
+    int64_t n[3];      /* sizes, slowest axis first; n[ndim-1] is x */
+    double dx[3];      /* grid spacing per axis */
+    int model;         /* 0: one-mode, 1: two-mode */
+    double r;          /* undercooling (the paper's epsilon) */
+    double dt;         /* time step */
+    double q1sq;       /* Q1^2 of the two-mode operator */
+    double R1;         /* R1 of the two-mode operator */
+    int linear_only;   /* 1: drop the cubic term (N = 0) */
+    int no_projection; /* 1: skip the Hermitian projection (demonstrates the drift) */
+} or_params;
+
+static int is_pow2(int64_t v) { return v >= 1 && (v & (v - 1)) == 0; }
+
+static int check_dims(int ndim, const int64_t *n)
+{
+    if (ndim < 1 || ndim > 3) return 0;
+    for (int a = 0; a < ndim; ++a)
+        if (!is_pow2(n[a]) || n[a] < 2) return 0;
+    return 1;
+}
+
+static int64_t total_size(int ndim, const int64_t *n)
+{
+    int64_t t = 1;
+    for (int a = 0; a < ndim; ++a) t *= n[a];
+    return t;
+}
+
+/* ---------------------------------------------------------------- 1D FFT (recursive radix-2) */
+
+/* w[j] = exp(sign * 2 pi i j / N), j < N/2.  Each entry from cos/sin of its own angle. */
+static cplx *twiddles(int64_t N, int sign)
+{
+    int64_t h = N / 2 > 0 ? N / 2 : 1;
+    cplx *w = (cplx *)malloc(sizeof(cplx) * (size_t)h);
+    if (!w) return NULL;
+    for (int64_t j = 0; j < h; ++j) {
+        double ang = 2.0 * PI * (double)j / (double)N;
+        w[j] = cos(ang) + (double)sign * sin(ang) * I;
+    }
+    return w;
+}
+
+/* Decimation in time: out[0..n) = DFT of in[0], in[stride], ..., in[(n-1) stride].
+ * W_n^k = w[k * wstep] where wstep = N/n for the top-level length N. */
+static void fft_rec(const cplx *in, int64_t stride, cplx *out, int64_t n, const cplx *w, int64_t wstep)
+{
+    if (n == 1) {
+        out[0] = in[0];
+        return;
+    }
+    int64_t h = n / 2;
+    fft_rec(in, 2 * stride, out, h, w, 2 * wstep);          /* even samples -> out[0..h)  */
+    fft_rec(in + stride, 2 * stride, out + h, h, w, 2 * wstep); /* odd samples -> out[h..n) */
+    for (int64_t k = 0; k < h; ++k) {
+        cplx e = out[k];
+        cplx t = w[k * wstep] * out[k + h];
+        out[k] = e + t;
+        out[k + h] = e - t;
+    }
+}
+
+/* In-place complex FFT along one axis of an nd complex array. sign = -1 forward, +1 inverse
+ * (unnormalised). */
+static int fft_axis(cplx *data, int ndim, const int64_t *n, int axis, int sign)
+{
+    int64_t len = n[axis];
+    int64_t inner = 1;
+    for (int a = axis + 1; a < ndim; ++a) inner *= n[a];
+    int64_t lines = total_size(ndim, n) / len;
+    cplx *w = twiddles(len, sign);
+    if (!w) return OR_ERR_MEM;
+    int err = 0;
+#pragma omp parallel
+    {
+        cplx *src = (cplx *)malloc(sizeof(cplx) * (size_t)len);
+        cplx *dst = (cplx *)malloc(sizeof(cplx) * (size_t)len);
+        if (!src || !dst) {
+#pragma omp atomic write
+            err = 1;
+        } else {
+#pragma omp for schedule(static)
+            for (int64_t l = 0; l < lines; ++l) {
+                int64_t outer = l / inner, in = l % inner;
+                cplx *base = data + outer * len * inner + in;
+                for (int64_t j = 0; j < len; ++j) src[j] = base[j * inner];
+                fft_rec(src, 1, dst, len, w, 1);
+                for (int64_t j = 0; j < len; ++j) base[j * inner] = dst[j];
+            }
+        }
+        free(src);
+        free(dst);
+    }
+    free(w);
+    return err ? OR_ERR_MEM : OR_OK;
+}
+
+static int fft_all_axes(cplx *data, int ndim, const int64_t *n, int sign)
+{
+    for (int a = 0; a < ndim; ++a) {
+        int e = fft_axis(data, ndim, n, a, sign);
+        if (e) return e;
+    }
+    return OR_OK;
+}
+
+/* Full complex nd FFT, in place on interleaved doubles.  sign = -1 forward, +1 inverse (no 1/N). */
+int or_fft_c2c(int ndim, const int64_t *n, double *data, int sign)
+{
+    if (!check_dims(ndim, n) || (sign != 1 && sign != -1)) return OR_ERR_ARG;
+    return fft_all_axes((cplx *)data, ndim, n, sign);
+}
+
+/* ---------------------------------------------------------------- half spectrum helpers */
+
+/* Half-spectrum shape: same as n except the last axis, which has n/2+1 entries. */
+static void half_dims(int ndim, const int64_t *n, int64_t *h)
+{
+    for (int a = 0; a < ndim; ++a) h[a] = n[a];
+    h[ndim - 1] = n[ndim - 1] / 2 + 1;
+}
+
+/* Split a flat index over dims d into per-axis indices (C order). */
+static void unflatten(int64_t idx, int ndim, const int64_t *d, int64_t *m)
+{
+    for (int a = ndim - 1; a >= 0; --a) {
+        m[a] = idx % d[a];
+        idx /= d[a];
+    }
+}
+
+static int64_t flatten(int ndim, const int64_t *d, const int64_t *m)
+{
+    int64_t idx = 0;
+    for (int a = 0; a < ndim; ++a) idx = idx * d[a] + m[a];
+    return idx;
+}
+
+/* Hermitian projection of the planes kx = 0 and kx = n/2 of a half spectrum:
+ * X(k) <- (X(k) + conj X(-k)) / 2, where -k negates every index modulo its axis length. */
+static void project_hermitian(cplx *half, int ndim, const int64_t *n)
+{
+    int64_t h[3];
+    half_dims(ndim, n, h);
+    int64_t plane = total_size(ndim, n) / n[ndim - 1]; /* points per kx plane */
+    int64_t kxs[2] = {0, n[ndim - 1] / 2};
+    for (int s = 0; s < 2; ++s) {
+        int64_t kx = kxs[s];
+        /* Pair each point with its mirror once: visit p and compute its partner. */
+        for (int64_t p = 0; p < plane; ++p) {
+            int64_t m[3] = {0, 0, 0}, mm[3] = {0, 0, 0};
+            unflatten(p * h[ndim - 1] + kx, ndim, h, m);
+            for (int a = 0; a < ndim - 1; ++a) mm[a] = (n[a] - m[a]) % n[a];
+            mm[ndim - 1] = kx;
+            int64_t i0 = flatten(ndim, h, m), i1 = flatten(ndim, h, mm);
+            if (i1 < i0) continue;
+            cplx a = half[i0], b = half[i1];
+            cplx v = 0.5 * (a + conj(b));
+            half[i0] = v;
+            half[i1] = conj(v);
+        }
+    }
+}
+
+/* Real-to-complex: full complex FFT of the real field, keep kx = 0..n/2, project. */
+static int rfftn_impl(int ndim, const int64_t *n, const double *real, cplx *half, int project)
+{
+    int64_t N = total_size(ndim, n);
+    cplx *full = (cplx *)malloc(sizeof(cplx) * (size_t)N);
+    if (!full) return OR_ERR_MEM;
+#pragma omp parallel for schedule(static)
+    for (int64_t i = 0; i < N; ++i) full[i] = real[i];
+    int e = fft_all_axes(full, ndim, n, -1);
+    if (e) {
+        free(full);
+        return e;
+    }
+    int64_t nx = n[ndim - 1], hx = nx / 2 + 1;
+    int64_t rows = N / nx;
+#pragma omp parallel for schedule(static)
+    for (int64_t row = 0; row < rows; ++row)
+        for (int64_t kx = 0; kx < hx; ++kx) half[row * hx + kx] = full[row * nx + kx];
+    free(full);
+    if (project) project_hermitian(half, ndim, n);
+    return OR_OK;
+}
+
+/* Complex-to-real: rebuild the full spectrum by X(k) = conj X(-k) for kx > n/2, inverse FFT,
+ * keep the real part, scale by 1/N. */
+static int irfftn_impl(int ndim, const int64_t *n, const cplx *half, double *real)
+{
+    int64_t N = total_size(ndim, n);
+    int64_t h[3];
+    half_dims(ndim, n, h);
+    cplx *full = (cplx *)malloc(sizeof(cplx) * (size_t)N);
+    if (!full) return OR_ERR_MEM;
+    int64_t nx = n[ndim - 1];
+#pragma omp parallel for schedule(static)
+    for (int64_t i = 0; i < N; ++i) {
+        int64_t m[3] = {0, 0, 0}, mm[3] = {0, 0, 0};
+        unflatten(i, ndim, n, m);
+        if (m[ndim - 1] <= nx / 2) {
+            full[i] = half[flatten(ndim, h, m)];
+        } else {
+            for (int a = 0; a < ndim; ++a) mm[a] = (n[a] - m[a]) % n[a];
+            full[i] = conj(half[flatten(ndim, h, mm)]);
+        }
+    }
+    int e = fft_all_axes(full, ndim, n, +1);
+    if (e) {
+        free(full);
+        return e;
+    }
+    double inv = 1.0 / (double)N;
+#pragma omp parallel for schedule(static)
+    for (int64_t i = 0; i < N; ++i) real[i] = creal(full[i]) * inv;
+    free(full);
+    return OR_OK;
+}
+
+int or_rfftn(int ndim, const int64_t *n, const double *real, double *half)
+{
+    if (!check_dims(ndim, n)) return OR_ERR_ARG;
+    return rfftn_impl(ndim, n, real, (cplx *)half, 1);
+}
+
+int or_irfftn(int ndim, const int64_t *n, const double *half, double *real)
+{
+    if (!check_dims(ndim, n)) return OR_ERR_ARG;
+    return irfftn_impl(ndim, n, (const cplx *)half, real);
+}
+
+/* ---------------------------------------------------------------- PFC operator */
+
+static int check_params(const or_params *p)
+{
+    if (!p || !check_dims(p->ndim, p->n)) return 0;
+    if (p->model != 0 && p->model != 1) return 0;
+    for (int a = 0; a < p->ndim; ++a)
+        if (!(p->dx[a] > 0)) return 0;
+    return 1;
+}
+
+/* Wavenumber of index m on an axis of length n with spacing dx. */
+static double wavenumber(int64_t m, int64_t n, double dx)
+{
+    int64_t s = (m <= n / 2) ? m : m - n;
+    return 2.0 * PI * (double)s / ((double)n * dx);
+}
+
+/* q = |k|^2 at half-spectrum point idx. */
+static double q_at(const or_params *p, int64_t idx)
+{
+    int64_t h[3], m[3] = {0, 0, 0};
+    half_dims(p->ndim, p->n, h);
+    unflatten(idx, p->ndim, h, m);
+    double q = 0.0;
+    for (int a = 0; a < p->ndim; ++a) {
+        double k = wavenumber(m[a], p->n[a], p->dx[a]);
+        q += k * k;
+    }
+    return q;
+}
+
+/* Correlation operator as a polynomial in q (Eq. (3) with the derivative rule of Eq. (2)). */
+static double corr_op(const or_params *p, double q)
+{
+    double a = (1.0 - q) * (1.0 - q);
+    if (p->model == 0) return a;
+    double b = (p->q1sq - q) * (p->q1sq - q);
+    return a * (b + p->R1);
+}
+
+static int64_t half_size(int ndim, const int64_t *n)
+{
+    return total_size(ndim, n) / n[ndim - 1] * (n[ndim - 1] / 2 + 1);
+}
+
+int or_state_init(const or_params *p, const double *psi0, double *state)
+{
+    if (!check_params(p)) return OR_ERR_ARG;
+    return rfftn_impl(p->ndim, p->n, psi0, (cplx *)state, !p->no_projection);
+}
+
+/* nsteps semi-implicit steps (Listing 1).  psi: real field psi^n in, psi^{n+nsteps} out.
+ * state: half spectrum psiF, updated in place. */
+int or_step(const or_params *p, double *psi, double *state, int64_t nsteps)
+{
+    if (!check_params(p) || nsteps < 0) return OR_ERR_ARG;
+    int ndim = p->ndim;
+    int64_t N = total_size(ndim, p->n), H = half_size(ndim, p->n);
+    cplx *S = (cplx *)state;
+    double *cube = (double *)malloc(sizeof(double) * (size_t)N);
+    cplx *NF = (cplx *)malloc(sizeof(cplx) * (size_t)H);
+    if (!cube || !NF) {
+        free(cube);
+        free(NF);
+        return OR_ERR_MEM;
+    }
+    int e = OR_OK;
+    for (int64_t s = 0; s < nsteps && !e; ++s) {
+        /* nonlinear term, pointwise in real space, then transformed */
+#pragma omp parallel for schedule(static)
+        for (int64_t i = 0; i < N; ++i) cube[i] = p->linear_only ? 0.0 : psi[i] * psi[i] * psi[i];
+        e = rfftn_impl(ndim, p->n, cube, NF, !p->no_projection);
+        if (e) break;
+        /* semi-implicit update: psiF = (psiF + dt*lap.*FFT(psi^3)) ./ (1 - dt*lin) */
+#pragma omp parallel for schedule(static)
+        for (int64_t i = 0; i < H; ++i) {
+            double q = q_at(p, i);
+            double lap = -q;
+            double lin = -q * (p->r + corr_op(p, q));
+            S[i] = (S[i] + p->dt * lap * NF[i]) / (1.0 - p->dt * lin);
+        }
+        if (!p->no_projection) project_hermitian(S, ndim, p->n);
+        e = irfftn_impl(ndim, p->n, S, psi);
+    }
+    free(cube);
+    free(NF);
+    return e;
+}
+
+/* Free energy, Eq. (3), on the grid (dV = prod dx):
+ *   out[0] = F with the quadratic part from the spectrum: (1/(2N)) sum_k w_k (r + L(q_k)) |S_k|^2,
+ *            w_k = 1 on the planes kx = 0 and kx = n/2, else 2 (the missing half of the spectrum);
+ *   out[1] = F with the quadratic part in real space: sum_x psi/2 * [(r + L) psi](x), where the
+ *            operator is applied spectrally to the transform of psi itself;
+ *   out[2] = mean of psi from the k = 0 mode, S_0 / N.
+ * The quartic part sum_x psi^4/4 is in both. */
+int or_energy(const or_params *p, const double *psi, const double *state, double *out)
+{
+    if (!check_params(p) || !out) return OR_ERR_ARG;
+    int ndim = p->ndim;
+    int64_t N = total_size(ndim, p->n), H = half_size(ndim, p->n);
+    int64_t nx = p->n[ndim - 1], hx = nx / 2 + 1;
+    const cplx *S = (const cplx *)state;
+    double dV = 1.0;
+    for (int a = 0; a < ndim; ++a) dV *= p->dx[a];
+
+    double quad = 0.0, quart = 0.0, quad_real = 0.0;
+#pragma omp parallel for reduction(+ : quad) schedule(static)
+    for (int64_t i = 0; i < H; ++i) {
+        int64_t kx = i % hx;
+        double w = (kx == 0 || kx == nx / 2) ? 1.0 : 2.0;
+        double q = q_at(p, i);
+        double a = creal(S[i]), b = cimag(S[i]);
+        quad += w * (p->r + corr_op(p, q)) * (a * a + b * b);
+    }
+    quad /= 2.0 * (double)N;
+#pragma omp parallel for reduction(+ : quart) schedule(static)
+    for (int64_t i = 0; i < N; ++i) {
+        double v = psi[i] * psi[i];
+        quart += 0.25 * v * v;
+    }
+    cplx *P = (cplx *)malloc(sizeof(cplx) * (size_t)H);
+    double *g = (double *)malloc(sizeof(double) * (size_t)N);
+    if (!P || !g) {
+        free(P);
+        free(g);
+        return OR_ERR_MEM;
+    }
+    int e = rfftn_impl(ndim, p->n, psi, P, 1);
+    if (!e) {
+        for (int64_t i = 0; i < H; ++i) P[i] *= (p->r + corr_op(p, q_at(p, i)));
+        e = irfftn_impl(ndim, p->n, P, g);
+    }
+    if (!e) {
+#pragma omp parallel for reduction(+ : quad_real) schedule(static)
+        for (int64_t i = 0; i < N; ++i) quad_real += 0.5 * psi[i] * g[i];
+    }
+    free(P);
+    free(g);
+    if (e) return e;
+    out[0] = dV * (quad + quart);
+    out[1] = dV * (quad_real + quart);
+    out[2] = creal(S[0]) / (double)N;
+    return OR_OK;
+}
+
+/* Adjoint of one step.  The step, as a map of the real field, is
+ *   psi^{n+1} = F^{-1}[ A .* (F psi^n - dt q .* F (psi^n)^3) ],   A = 1/(1 + dt q (r + L(q))),
+ * whose Jacobian is S_A - dt S_A S_K diag(3 (psi^n)^2) with the real symmetric Fourier multipliers
+ * S_A = F^{-1} A F and S_K = F^{-1} q F.  Its transpose applied to lam = lam^{n+1}:
+ *   mu = S_A lam,  nu = S_K S_A lam,  lam^n = mu - 3 dt (psi^n)^2 .* nu.
+ * The derivative of psi^{n+1} with respect to r is -dt S_K S_A psi^{n+1}, so the contribution of
+ * this step to dL/dr is -dt <nu, psi^{n+1}>, added to *dLdr. */
+int or_step_backward(const or_params *p, const double *psi_n, const double *psi_np1,
+                     const double *lam_np1, double *lam_n, double *dLdr)
+{
+    if (!check_params(p)) return OR_ERR_ARG;
+    int ndim = p->ndim;
+    int64_t N = total_size(ndim, p->n), H = half_size(ndim, p->n);
+    cplx *Lh = (cplx *)malloc(sizeof(cplx) * (size_t)H);
+    cplx *Kh = (cplx *)malloc(sizeof(cplx) * (size_t)H);
+    double *mu = (double *)malloc(sizeof(double) * (size_t)N);
+    double *nu = (double *)malloc(sizeof(double) * (size_t)N);
+    int e = OR_OK;
+    if (!Lh || !Kh || !mu || !nu) e = OR_ERR_MEM;
+    if (!e) e = rfftn_impl(ndim, p->n, lam_np1, Lh, !p->no_projection);
+    if (!e) {
+        for (int64_t i = 0; i < H; ++i) {
+            double q = q_at(p, i);
+            double A = 1.0 / (1.0 + p->dt * q * (p->r + corr_op(p, q)));
+            Lh[i] *= A;
+            Kh[i] = q * Lh[i];
+        }
+        e = irfftn_impl(ndim, p->n, Lh, mu);
+    }
+    if (!e) e = irfftn_impl(ndim, p->n, Kh, nu);
+    if (!e) {
+        double acc = 0.0;
+        const double c = p->linear_only ? 0.0 : 3.0 * p->dt;
+#pragma omp parallel for reduction(+ : acc) schedule(static)
+        for (int64_t i = 0; i < N; ++i) {
+            lam_n[i] = mu[i] - c * psi_n[i] * psi_n[i] * nu[i];
+            acc += nu[i] * psi_np1[i];
+        }
+        if (dLdr) *dLdr += -p->dt * acc;
+    }
+    free(Lh);
+    free(Kh);
+    free(mu);
+    free(nu);
+    return e;
+}
+
+/* Number of OpenMP threads the oracle would use (reported with the CPU baseline). */
+int or_num_threads(void)
+{
+    int t = 1;
+#pragma omp parallel
+    {
+#pragma omp single
+        {
+#ifdef _OPENMP
+            t = omp_get_num_threads();
+#endif
+        }
+    }
+    return t;
+}

@@ -1,0 +1,144 @@
+"""Seeded synthetic inputs shared by the tests, the oracle runs and the benchmark.
+
+This module holds no arithmetic of the PFC method.  It only draws seeded random fields.
+
+Generator: SplitMix64 (Steele, Lea and Flood, "Fast splittable pseudorandom number generators",
+OOPSLA 2014), the 64-bit state version with Stafford's "variant 13" output mix.  The generator
+seeded with ``seed`` adds the golden-ratio increment GAMMA to its state before each output, so
+its i-th output (0-based) is ``mix64(seed + (i + 1) * GAMMA mod 2^64)``.  That closed form makes
+the stream counter-based: element i of a C-order field is the i-th output, so any slice of a field
+can be drawn independently and the numpy and torch versions agree bit for bit.
+
+Doubles: ``u = (x >> 11) * 2^-53`` in [0, 1).  U(a, b) = a + (b - a) * u.  N(0, 1) by the
+Box-Muller transform of the pair (u_{2i}, u_{2i+1}): sqrt(-2 ln(1 - u_{2i})) cos(2 pi u_{2i+1}).
+"""
+from __future__ import annotations
+
+import math
+
+import numpy as np
+
+GAMMA = 0x9E3779B97F4A7C15
+M1 = 0xBF58476D1CE4E5B9
+M2 = 0x94D049BB133111EB
+MASK64 = (1 << 64) - 1
+TWO_M53 = 2.0 ** -53
+
+
+def splitmix64_sequential(seed: int, count: int) -> list[int]:
+    """The generator as published: a running state, advanced by GAMMA before each output."""
+    state = seed & MASK64
+    out = []
+    for _ in range(count):
+        state = (state + GAMMA) & MASK64
+        z = state
+        z = ((z ^ (z >> 30)) * M1) & MASK64
+        z = ((z ^ (z >> 27)) * M2) & MASK64
+        out.append(z ^ (z >> 31))
+    return out
+
+
+def _mix64_np(z: np.ndarray) -> np.ndarray:
+    z = (z ^ (z >> np.uint64(30))) * np.uint64(M1)
+    z = (z ^ (z >> np.uint64(27))) * np.uint64(M2)
+    return z ^ (z >> np.uint64(31))
+
+
+def splitmix64(seed: int, start: int, count: int) -> np.ndarray:
+    """Outputs start .. start+count-1 of the stream seeded with ``seed`` (uint64 array)."""
+    idx = np.arange(start + 1, start + 1 + count, dtype=np.uint64)
+    with np.errstate(over="ignore"):
+        state = np.uint64(seed & MASK64) + idx * np.uint64(GAMMA)
+        return _mix64_np(state)
+
+
+def unit_uniform(seed: int, start: int, count: int) -> np.ndarray:
+    """Doubles in [0, 1) from outputs start .. start+count-1."""
+    x = splitmix64(seed, start, count)
+    return (x >> np.uint64(11)).astype(np.float64) * TWO_M53
+
+
+def derive_seed(seed: int, index: int) -> int:
+    """Seed of sub-stream ``index`` of ``seed``: that output of the parent stream."""
+    return int(splitmix64(seed, index, 1)[0])
+
+
+def uniform(seed: int, shape, lo: float, hi: float) -> np.ndarray:
+    """C-order float64 field with entries U(lo, hi)."""
+    count = int(np.prod(shape))
+    return (lo + (hi - lo) * unit_uniform(seed, 0, count)).reshape(shape)
+
+
+def normal(seed: int, shape) -> np.ndarray:
+    """C-order float64 field with entries N(0, 1) (Box-Muller on consecutive output pairs)."""
+    count = int(np.prod(shape))
+    u = unit_uniform(seed, 0, 2 * count)
+    a, b = u[0::2], u[1::2]
+    return (np.sqrt(-2.0 * np.log1p(-a)) * np.cos(2.0 * math.pi * b)).reshape(shape)
+
+
+def pfc_initial_field(seed: int, shape, mean: float, amplitude: float = 0.1) -> np.ndarray:
+    """psi0 = mean + U(-amplitude, amplitude), the initial-condition recipe of the PFC runs."""
+    return mean + uniform(seed, shape, -amplitude, amplitude)
+
+
+# ---------------------------------------------------------------------------- torch (device) form
+# Used where a field is too large to draw on the host (e.g. 2048^3).  Same stream, same values:
+# int64 arithmetic wraps modulo 2^64 like uint64, and logical right shifts are arithmetic shifts
+# with the sign-extended bits masked off.
+
+
+def _as_i64(v: int) -> int:
+    v &= MASK64
+    return v - (1 << 64) if v >= (1 << 63) else v
+
+
+def _lsr(z, s: int):
+    return (z >> s) & ((1 << (64 - s)) - 1)
+
+
+def _unit_uniform_torch(seed: int, start: int, count: int, device):
+    import torch
+
+    idx = torch.arange(start + 1, start + 1 + count, dtype=torch.int64, device=device)
+    z = idx * _as_i64(GAMMA) + _as_i64(seed)
+    z = (z ^ _lsr(z, 30)) * _as_i64(M1)
+    z = (z ^ _lsr(z, 27)) * _as_i64(M2)
+    z = z ^ _lsr(z, 31)
+    return _lsr(z, 11).to(torch.float64) * TWO_M53
+
+
+def uniform_torch(seed: int, shape, lo: float, hi: float, dtype, device, offset: float = 0.0,
+                  chunk: int = 1 << 26):
+    """Same values as ``offset + uniform(...)`` (float64, rounded once to ``dtype``), drawn on
+    ``device`` in chunks."""
+    import torch
+
+    count = int(np.prod(shape))
+    out = torch.empty(count, dtype=dtype, device=device)
+    for s in range(0, count, chunk):
+        c = min(chunk, count - s)
+        u = _unit_uniform_torch(seed, s, c, device)
+        out[s : s + c] = (offset + (lo + (hi - lo) * u)).to(dtype)
+        del u
+    return out.view(*shape)
+
+
+def normal_torch(seed: int, shape, dtype, device, chunk: int = 1 << 25):
+    """Same values as ``normal`` (rounded once to ``dtype``), drawn on ``device`` in chunks."""
+    import torch
+
+    count = int(np.prod(shape))
+    out = torch.empty(count, dtype=dtype, device=device)
+    for s in range(0, count, chunk):
+        c = min(chunk, count - s)
+        u = _unit_uniform_torch(seed, 2 * s, 2 * c, device)
+        a, b = u[0::2], u[1::2]
+        out[s : s + c] = (torch.sqrt(-2.0 * torch.log1p(-a)) * torch.cos(2.0 * math.pi * b)).to(dtype)
+        del u, a, b
+    return out.view(*shape)
+
+
+def pfc_initial_field_torch(seed: int, shape, mean: float, dtype, device, amplitude: float = 0.1):
+    """Same values as ``pfc_initial_field`` (rounded once to ``dtype``), drawn on ``device``."""
+    return uniform_torch(seed, shape, -amplitude, amplitude, dtype, device, offset=mean)
