@@ -1,0 +1,140 @@
+/*
+ * pfc.h -- C ABI of the MI355X (gfx950) pseudo-spectral phase-field-crystal (PFC) library.
+ *
+ * The library advances the PFC equation of arxiv 2603.26818 (free energy Eq. (3), dynamics
+ * Eq. (4)) with the Fourier pseudo-spectral method and the semi-implicit update of Listing 1:
+ * each step transforms psi^3 to Fourier space (real-to-complex FFT), updates every mode with
+ *     psi_hat <- (psi_hat - dt q FFT(psi^3)) / (1 + dt q (r + L(q))),   q = |k|^2,
+ * and transforms back (complex-to-real FFT).  L(q) = (1-q)^2 (one-mode) or
+ * (1-q)^2 ((Q1^2-q)^2 + R1) (two-mode; the paper's FCC operator is Q1^2 = 4/3, R1 = 0), r is the
+ * paper's undercooling epsilon, and k_j = 2 pi m_j / (n_j dx_j) with m_j in {0..n/2, -n/2+1..-1}.
+ *
+ * Conventions shared by every entry point
+ * - Arrays are C-order with x (the last index) fastest.  Real fields hold n0*n1*n2 (3D) or n0*n1
+ *   (2D, x = n1) values of the plan's dtype.  Complex values are interleaved (re, im).
+ * - "Natural" half spectra are [..][n_x/2+1] complex, unnormalised, forward sign e^{-ikx}.
+ * - The spectral "state" carried between steps is in the library's own layout ("native"): the
+ *   half spectrum with the self-conjugate planes kx = 0 and kx = n_x/2 folded into one complex
+ *   plane, n0*n1*n2/2 complex values in all (the same byte count as the real field).  Because any
+ *   complex array in that layout corresponds to exactly one pair of Hermitian planes, the state
+ *   always satisfies the symmetry of a real field.  Use pfc_state_export to read it.
+ * - Device buffers and streams are owned by the caller; the plan owns only host metadata.  All
+ *   device pointers must be 16-byte aligned and must not overlap unless an entry point says so.
+ * - Every call is asynchronous on `stream` (a hipStream_t passed as void*, NULL = null stream) and
+ *   runs on the plan's device.  Argument errors are returned synchronously and nothing is
+ *   launched; kernel faults surface as PFC_ERR_HIP on a later call or synchronisation.
+ * - No C++ exception crosses this interface.  pfc_last_error() gives a detail string for the
+ *   calling thread's last failure.
+ */
+#ifndef PFC_H
+#define PFC_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    PFC_OK = 0,
+    PFC_ERR_INVALID_ARG = 1, /* bad value, NULL pointer, unstable dt, ...           */
+    PFC_ERR_UNSUPPORTED = 2, /* size not a power of two in [4, 2048], ndim not 2/3 */
+    PFC_ERR_ALIGNMENT = 3,   /* device pointer not 16-byte aligned                 */
+    PFC_ERR_WORKSPACE = 4,   /* workspace missing or too small                     */
+    PFC_ERR_HIP = 5,         /* a HIP runtime call failed                          */
+    PFC_ERR_DIVERGED = 6,    /* non-finite energy or field detected                */
+    PFC_ERR_INTERNAL = 7
+} pfc_status;
+
+typedef enum { PFC_F32 = 0, PFC_F64 = 1 } pfc_dtype;
+typedef enum { PFC_ONE_MODE = 0, PFC_TWO_MODE = 1 } pfc_model;
+
+/* flags */
+#define PFC_FLAG_LINEAR_ONLY 1u /* drop the cubic term (FFT(psi^3) := 0): the linear PDE */
+
+typedef struct pfc_plan pfc_plan;
+
+typedef struct {
+    int ndim;        /* 2 or 3                                                    */
+    int64_t n[3];    /* grid, slowest axis first; n[ndim-1] is x; powers of two   */
+    double dx[3];    /* grid spacing per axis (> 0)                               */
+    pfc_dtype dtype; /* arithmetic of fields, spectra and FFTs                    */
+    pfc_model model; /* correlation operator L(q)                                 */
+    double r;        /* undercooling (the paper's epsilon)                        */
+    double dt;       /* time step (> 0)                                           */
+    double q1sq;     /* Q1^2 of the two-mode operator (ignored for one-mode)      */
+    double R1;       /* R1 of the two-mode operator (ignored for one-mode)        */
+    int device;      /* HIP device ordinal the plan runs on                       */
+    uint32_t flags;  /* PFC_FLAG_*                                                */
+} pfc_plan_desc;
+
+/* Validate `d` and create a plan (host memory only; no device allocation, no kernel).
+ * Rejects: ndim not in {2,3}, a size that is not a power of two in [4, 2048] (UNSUPPORTED), dx <= 0,
+ * dt <= 0, non-finite parameters, and any (r, dt) for which 1 + dt q (r + L(q)) <= 0 at some grid
+ * wavevector (INVALID_ARG: the implicit denominator would vanish or change sign). */
+pfc_status pfc_plan_create(pfc_plan **out, const pfc_plan_desc *d);
+
+/* Bytes of device workspace the plan needs: one native spectrum (n0*n1*n2/2 complex), the
+ * twiddle table and the reduction partials.  The caller allocates it (>= 256-byte aligned). */
+size_t pfc_plan_workspace_bytes(const pfc_plan *p);
+
+/* Attach a caller-owned workspace and fill its twiddle table (host-computed in extended precision,
+ * rounded once to the plan's dtype; one synchronous host-to-device copy).  Must be called before
+ * any transform.  The workspace must stay valid, and unshared with concurrent calls, while the
+ * plan uses it. */
+pfc_status pfc_plan_set_workspace(pfc_plan *p, void *dev_ptr, size_t bytes);
+
+/* Change r and dt (re-validated as in pfc_plan_create). */
+pfc_status pfc_plan_set_params(pfc_plan *p, double r, double dt);
+
+pfc_status pfc_plan_destroy(pfc_plan *p);
+
+/* Sizes in bytes of a real field, of a natural half spectrum and of a native state. */
+size_t pfc_plan_real_bytes(const pfc_plan *p);
+size_t pfc_plan_half_bytes(const pfc_plan *p);
+size_t pfc_plan_state_bytes(const pfc_plan *p);
+
+/* Forward real-to-complex FFT of `real_in` into the natural half spectrum `half_out`
+ * (unnormalised; the kx = 0 and kx = n_x/2 planes are exactly Hermitian).  Input preserved. */
+pfc_status pfc_fft_r2c(pfc_plan *p, const void *real_in, void *half_out, void *stream);
+
+/* Inverse complex-to-real FFT of the natural half spectrum `half_in` into `real_out`, scaled by
+ * 1/(total points).  The kx = 0 and kx = n_x/2 planes are first projected onto Hermitian symmetry,
+ * X(k) <- (X(k) + conj X(-k))/2, so anti-Hermitian content is discarded.  Input preserved. */
+pfc_status pfc_fft_c2r(pfc_plan *p, const void *half_in, void *real_out, void *stream);
+
+/* Spectral state of psi0 (its forward transform, native layout).  The k = 0 (mass) mode is
+ * overwritten with an FP64 sum of psi0 rounded once to the dtype. */
+pfc_status pfc_state_init(pfc_plan *p, const void *psi0, void *state, void *stream);
+
+/* Copy the native state into a natural half spectrum [..][n_x/2+1]. */
+pfc_status pfc_state_export(pfc_plan *p, const void *state, void *half_natural, void *stream);
+
+/* Advance `nsteps` >= 0 semi-implicit steps (Listing 1).  psi: real field psi^n in, psi^{n+nsteps}
+ * out.  state: native spectrum of psi^n in, updated in place.  The psi that enters a step is the
+ * one the cube is taken of; the state is the one the update is applied to. */
+pfc_status pfc_step(pfc_plan *p, void *psi, void *state, int64_t nsteps, void *stream);
+
+/* Transpose of the Jacobian of one step, applied to lambda_np1 (the adjoint of psi^{n+1}):
+ *     lambda_n = S_A lambda - 3 dt (psi_n)^2 .* S_K S_A lambda,
+ * where S_A and S_K are the real symmetric Fourier multipliers A = 1/(1 + dt q (r + L(q))) and q.
+ * Also adds this step's contribution to dL/dr, -dt <S_K S_A lambda, psi_np1>, to the FP64 device
+ * scalar *dLdr_accum_dev.  lambda_n may be the same buffer as lambda_np1 (updated in place); it must
+ * not overlap psi_n or psi_np1.  With PFC_FLAG_LINEAR_ONLY the cubic term is dropped. */
+pfc_status pfc_step_backward(pfc_plan *p, const void *psi_n, const void *psi_np1, const void *lambda_np1,
+                             void *lambda_n, double *dLdr_accum_dev, void *stream);
+
+/* Free energy, Eq. (3), on the grid: out_dev[0] = dV [ (1/(2N)) sum_k (r + L(q_k)) |psi_hat_k|^2
+ * + sum_x psi^4/4 ] (sum over the full spectrum, dV = product of dx), out_dev[1] = mean of psi
+ * from the k = 0 mode.  Accumulation in FP64 in both dtypes.  out_dev: 2 device doubles. */
+pfc_status pfc_energy(pfc_plan *p, const void *psi, const void *state, double *out_dev, void *stream);
+
+const char *pfc_status_string(pfc_status st);
+const char *pfc_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PFC_H */

@@ -1,0 +1,243 @@
+// dispatch_impl.hpp -- length dispatch of the kernel templates; included once per dtype.
+#pragma once
+
+#include "kernels.hpp"
+#include "launch.hpp"
+
+namespace pfc {
+
+// Pencils per workgroup of the strided passes: 128-byte rows (16 FP32 / 8 FP64 complex) as long as
+// the workgroup's LDS tile stays within 128 KB.
+template <typename T, int L>
+struct WMax {
+    static constexpr int pref = 128 / (int)sizeof(cx<T>);
+    static constexpr int cap = (131072 / (L * (int)sizeof(cx<T>))) < 2 ? 2 : (131072 / (L * (int)sizeof(cx<T>)));
+    static constexpr int value = pref < cap ? pref : cap;
+};
+
+template <class F>
+static hipError_t by_length(int64_t L, F &&f)
+{
+    switch (L) {
+    case 2: return f(std::integral_constant<int, 2>{});
+    case 4: return f(std::integral_constant<int, 4>{});
+    case 8: return f(std::integral_constant<int, 8>{});
+    case 16: return f(std::integral_constant<int, 16>{});
+    case 32: return f(std::integral_constant<int, 32>{});
+    case 64: return f(std::integral_constant<int, 64>{});
+    case 128: return f(std::integral_constant<int, 128>{});
+    case 256: return f(std::integral_constant<int, 256>{});
+    case 512: return f(std::integral_constant<int, 512>{});
+    case 1024: return f(std::integral_constant<int, 1024>{});
+    case 2048: return f(std::integral_constant<int, 2048>{});
+    default: return hipErrorInvalidValue;
+    }
+}
+
+static inline int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
+
+template <typename T>
+hipError_t launch_x_r2c(const Geom &g, const T *in, cx<T> *out, bool cube, const cx<T> *tw, hipStream_t s)
+{
+    if (g.M > 1024) return hipErrorInvalidValue;
+    return by_length(g.M, [&](auto Mc) -> hipError_t {
+        constexpr int M = decltype(Mc)::value;
+        if constexpr (M > 1024) {
+            return hipErrorInvalidValue;
+        } else {
+            using PL = typename DefaultPlan<M>::type;
+            constexpr int ROWS = XRows<M>::value;
+            const dim3 grid((unsigned)cdiv(g.xrows, ROWS)), block(ROWS * PL::Tp);
+            if (cube)
+                hipLaunchKernelGGL((x_r2c_kernel<T, PL, ROWS, true>), grid, block, 0, s, in, out, g.xrows, tw, g.lt_shift);
+            else
+                hipLaunchKernelGGL((x_r2c_kernel<T, PL, ROWS, false>), grid, block, 0, s, in, out, g.xrows, tw, g.lt_shift);
+            return hipGetLastError();
+        }
+    });
+}
+
+template <typename T>
+hipError_t launch_x_c2r(const Geom &g, const cx<T> *in, T *out, const cx<T> *tw, hipStream_t s)
+{
+    return by_length(g.M, [&](auto Mc) -> hipError_t {
+        constexpr int M = decltype(Mc)::value;
+        if constexpr (M > 1024) {
+            return hipErrorInvalidValue;
+        } else {
+            using PL = typename DefaultPlan<M>::type;
+            constexpr int ROWS = XRows<M>::value;
+            const dim3 grid((unsigned)cdiv(g.xrows, ROWS)), block(ROWS * PL::Tp);
+            const T sc = (T)(1.0 / ((double)g.M * (double)g.n0 * (double)g.nrows));
+            AdjEpi<T> ea{};
+            hipLaunchKernelGGL((x_c2r_kernel<T, PL, ROWS, EPI_PLAIN>), grid, block, 0, s, in, out, g.xrows, tw,
+                               g.lt_shift, sc, ea);
+            return hipGetLastError();
+        }
+    });
+}
+
+template <typename T>
+hipError_t launch_x_c2r_adjoint(const Geom &g, const cx<T> *mu, const cx<T> *nu, const T *psi_n, const T *psi_np1,
+                                T *out, T c3, double *partial, int64_t *nblocks, const cx<T> *tw, hipStream_t s)
+{
+    return by_length(g.M, [&](auto Mc) -> hipError_t {
+        constexpr int M = decltype(Mc)::value;
+        if constexpr (M > 1024) {
+            return hipErrorInvalidValue;
+        } else {
+            using PL = typename DefaultPlan<M>::type;
+            constexpr int ROWS = XRows<M>::value;
+            const int64_t nb = cdiv(g.xrows, ROWS);
+            *nblocks = nb;
+            const dim3 grid((unsigned)nb), block(ROWS * PL::Tp);
+            const T sc = (T)(1.0 / ((double)g.M * (double)g.n0 * (double)g.nrows));
+            AdjEpi<T> ea{nu, psi_n, psi_np1, c3, partial};
+            hipLaunchKernelGGL((x_c2r_kernel<T, PL, ROWS, EPI_ADJOINT>), grid, block, 0, s, mu, out, g.xrows, tw,
+                               g.lt_shift, sc, ea);
+            return hipGetLastError();
+        }
+    });
+}
+
+template <typename T>
+hipError_t launch_y_c2c(const Geom &g, cx<T> *data, int dir, const cx<T> *tw, hipStream_t s)
+{
+    return by_length(g.n1, [&](auto Lc) -> hipError_t {
+        constexpr int L = decltype(Lc)::value;
+        if constexpr (L < 4) {
+            return hipErrorInvalidValue;
+        } else {
+            using PL = typename DefaultPlan<L>::type;
+            constexpr int WM = WMax<T, L>::value;
+            const int W = (int)(g.M < WM ? g.M : WM);
+            const int64_t tiles = cdiv(g.M, W);
+            const dim3 grid((unsigned)(tiles * g.n0)), block(WM * PL::Tp);
+            if (dir < 0)
+                hipLaunchKernelGGL((axis_c2c_kernel<T, PL, WM, -1>), grid, block, 0, s, data, data, W, g.M, g.M,
+                                   g.n1 * g.M, tiles, tw, g.lt_shift);
+            else
+                hipLaunchKernelGGL((axis_c2c_kernel<T, PL, WM, +1>), grid, block, 0, s, data, data, W, g.M, g.M,
+                                   g.n1 * g.M, tiles, tw, g.lt_shift);
+            return hipGetLastError();
+        }
+    });
+}
+
+template <typename T>
+hipError_t launch_last_fwd(const Geom &g, const cx<T> *src, cx<T> *dst, const cx<T> *tw, hipStream_t s)
+{
+    return by_length(g.n0, [&](auto Lc) -> hipError_t {
+        constexpr int L = decltype(Lc)::value;
+        if constexpr (L < 4) {
+            return hipErrorInvalidValue;
+        } else {
+            using PL = typename DefaultPlan<L>::type;
+            constexpr int WM = WMax<T, L>::value;
+            const int64_t ncols = g.nrows * g.M;
+            const int W = (int)(ncols < WM ? ncols : WM);
+            const int64_t tiles = cdiv(ncols, W);
+            const dim3 grid((unsigned)tiles), block(WM * PL::Tp);
+            hipLaunchKernelGGL((axis_c2c_kernel<T, PL, WM, -1>), grid, block, 0, s, src, dst, W, ncols, ncols,
+                               (int64_t)0, tiles, tw, g.lt_shift);
+            return hipGetLastError();
+        }
+    });
+}
+
+template <typename T>
+hipError_t launch_last(const Geom &g, int mode, const cx<T> *src, cx<T> *dst, cx<T> *dst2, cx<T> *state,
+                       const ModelParams<T> &mp, const cx<T> *tw, hipStream_t s)
+{
+    return by_length(g.n0, [&](auto Lc) -> hipError_t {
+        constexpr int L = decltype(Lc)::value;
+        if constexpr (L < 4) {
+            return hipErrorInvalidValue;
+        } else {
+            using PL = typename DefaultPlan<L>::type;
+            constexpr int WM = WMax<T, L>::value;
+            LastAxisArgs<T> a;
+            a.src = src;
+            a.dst = dst;
+            a.dst2 = dst2;
+            a.state = state;
+            a.nrows = g.nrows;
+            a.M = (int)g.M;
+            a.W = (int)(g.M < WM ? g.M : WM);
+            a.tiles_per_row = (int)(g.M / a.W);
+            a.tw = tw;
+            a.lt_shift = g.lt_shift;
+            a.mp = mp;
+            const int64_t nblocks = (g.nrows == 1) ? a.tiles_per_row : g.nrows * a.tiles_per_row;
+            const dim3 grid((unsigned)nblocks), block(WM * PL::Tp);
+            switch (mode) {
+            case LAST_STEP:
+                hipLaunchKernelGGL((last_axis_kernel<T, PL, WM, LA_STEP>), grid, block, 0, s, a);
+                break;
+            case LAST_R2C_NATURAL:
+                hipLaunchKernelGGL((last_axis_kernel<T, PL, WM, LA_R2C_NATURAL>), grid, block, 0, s, a);
+                break;
+            case LAST_C2R_NATURAL:
+                hipLaunchKernelGGL((last_axis_kernel<T, PL, WM, LA_C2R_NATURAL>), grid, block, 0, s, a);
+                break;
+            case LAST_ADJOINT:
+                hipLaunchKernelGGL((last_axis_kernel<T, PL, WM, LA_ADJOINT>), grid, block, 0, s, a);
+                break;
+            default: return hipErrorInvalidValue;
+            }
+            return hipGetLastError();
+        }
+    });
+}
+
+template <typename T>
+hipError_t launch_set_mass(const T *psi, int64_t n, double *partial, cx<T> *state, hipStream_t s)
+{
+    hipLaunchKernelGGL((sum_kernel<T>), dim3(kReduceBlocks), dim3(256), 0, s, psi, n, partial);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL((set_mass_kernel<T>), dim3(1), dim3(64), 0, s, partial, kReduceBlocks, state);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_energy(const Geom &g, const T *psi, const cx<T> *state, const double fk[3], double r, double q1sq,
+                         double R1, int model, double dV, double *partial, double *out, hipStream_t s)
+{
+    hipLaunchKernelGGL((energy_spec_kernel<T>), dim3(kReduceBlocks), dim3(256), 0, s, state, g.n0, g.nrows, g.M,
+                       fk[0], fk[1], fk[2], r, q1sq, R1, model, partial);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    const int64_t ntot = g.n0 * g.nrows * g.nx;
+    hipLaunchKernelGGL((quartic_kernel<T>), dim3(kReduceBlocks), dim3(256), 0, s, psi, ntot, partial + kReduceBlocks);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL((energy_final_kernel<T>), dim3(1), dim3(64), 0, s, partial, partial + kReduceBlocks,
+                       kReduceBlocks, dV, (double)ntot, state, out);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_export(const Geom &g, const cx<T> *state, cx<T> *out, hipStream_t s)
+{
+    const int64_t n = g.n0 * g.nrows * (g.M + 1);
+    const int64_t blocks = cdiv(n, 256) < 65536 ? cdiv(n, 256) : 65536;
+    hipLaunchKernelGGL((export_kernel<T>), dim3((unsigned)blocks), dim3(256), 0, s, state, out, g.n0, g.nrows, g.M);
+    return hipGetLastError();
+}
+
+#define PFC_INSTANTIATE(T)                                                                                            \
+    template hipError_t launch_x_r2c<T>(const Geom &, const T *, cx<T> *, bool, const cx<T> *, hipStream_t);          \
+    template hipError_t launch_x_c2r<T>(const Geom &, const cx<T> *, T *, const cx<T> *, hipStream_t);                \
+    template hipError_t launch_x_c2r_adjoint<T>(const Geom &, const cx<T> *, const cx<T> *, const T *, const T *, T *, \
+                                                T, double *, int64_t *, const cx<T> *, hipStream_t);                  \
+    template hipError_t launch_y_c2c<T>(const Geom &, cx<T> *, int, const cx<T> *, hipStream_t);                      \
+    template hipError_t launch_last_fwd<T>(const Geom &, const cx<T> *, cx<T> *, const cx<T> *, hipStream_t);         \
+    template hipError_t launch_last<T>(const Geom &, int, const cx<T> *, cx<T> *, cx<T> *, cx<T> *,                   \
+                                       const ModelParams<T> &, const cx<T> *, hipStream_t);                           \
+    template hipError_t launch_set_mass<T>(const T *, int64_t, double *, cx<T> *, hipStream_t);                       \
+    template hipError_t launch_energy<T>(const Geom &, const T *, const cx<T> *, const double *, double, double,      \
+                                         double, int, double, double *, double *, hipStream_t);                       \
+    template hipError_t launch_export<T>(const Geom &, const cx<T> *, cx<T> *, hipStream_t);
+
+}  // namespace pfc

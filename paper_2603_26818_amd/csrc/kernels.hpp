@@ -1,0 +1,631 @@
+// kernels.hpp -- HIP kernels of the PFC hot path (gfx950).
+//
+// Layouts (C-order, x fastest; M = n_x / 2):
+//   real field      [rows][2M]                      rows = n0 n1 (3D) or n0 (2D)
+//   packed spectrum [n0][nrows][M] complex           nrows = n1 (3D) or 1 (2D)
+//     column kx in 1..M-1 holds X(kx); column 0 holds X(0) + i X(M): the planes kx = 0 and
+//     kx = n_x/2 are spectra of real data and share one complex plane.  After the transforms along
+//     the other axes, column 0 holds Z = X0_hat + i XN_hat, and the two Hermitian planes are
+//         X0_hat(k) = (Z(k) + conj Z(-k)) / 2,   XN_hat(k) = -i (Z(k) - conj Z(-k)) / 2.
+//   natural half    [n0][nrows][M+1] complex
+//
+// Pass schedule of one step (arxiv 2603.26818, Listing 1: cube, forward transform, update of
+// psiF, inverse transform), 3D:
+//   x_r2c (cube prologue) -> y forward -> last-axis (z forward, update, z inverse) -> y inverse
+//   -> x_c2r (1/N epilogue);   2D: x_r2c -> last-axis along y -> x_c2r.
+#pragma once
+
+#include "fft_core.hpp"
+
+namespace pfc {
+
+// ------------------------------------------------------------------------------------------------
+// L(q) and the implicit multiplier, in the kernel's precision (ModelParams in types.hpp).
+template <typename T>
+__device__ __forceinline__ T corr_op(const ModelParams<T> &m, T q)
+{
+    T a = (T(1) - q) * (T(1) - q);
+    if (m.model == 0) return a;
+    T b = m.q1sq - q;
+    return a * (b * b + m.R1);
+}
+
+// A(q) = 1 / (1 + dt q (r + L(q))); exactly 1 at q = 0.
+template <typename T>
+__device__ __forceinline__ T amult(const ModelParams<T> &m, T q)
+{
+    return T(1) / (T(1) + m.dt * q * (m.r + corr_op(m, q)));
+}
+
+__device__ __forceinline__ int signed_index(int64_t i, int64_t n) { return (int)(i <= n / 2 ? i : i - n); }
+
+// ------------------------------------------------------------------------------------------------
+// Block-wide FP64 sum; the result is valid in thread 0.  red: >= blockDim.x/64 doubles of LDS.
+__device__ __forceinline__ double block_sum(double v, double *red)
+{
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o, 64);
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    __syncthreads();
+    if (lane == 0) red[w] = v;
+    __syncthreads();
+    double s = 0.0;
+    if (threadIdx.x == 0)
+        for (int i = 0; i < (int)(blockDim.x + 63) / 64; ++i) s += red[i];
+    return s;
+}
+
+// ------------------------------------------------------------------------------------------------
+// x axis, forward: one row of 2M reals -> M packed complex values.
+// z[m] = x[2m] + i x[2m+1] (cubed first when CUBE), Z = FFT_M(z), then for k = 1..M-1
+//   X(k) = E + W_{2M}^k O,  E = (Z(k) + conj Z(M-k)) / 2,  O = -i (Z(k) - conj Z(M-k)) / 2,
+// and slot 0 = (Re Z0 + Im Z0) + i (Re Z0 - Im Z0) = X(0) + i X(M).
+template <int M>
+struct XRows {
+    static constexpr int Tp = DefaultPlan<M>::type::Tp;
+    static constexpr int value = (256 / Tp) > 64 ? 64 : ((256 / Tp) < 1 ? 1 : 256 / Tp);
+};
+
+template <typename T, class PL, int ROWS, bool CUBE>
+__global__ __launch_bounds__(ROWS *PL::Tp) void x_r2c_kernel(const T *__restrict__ in, cx<T> *__restrict__ out,
+                                                              int64_t nrows, const cx<T> *__restrict__ tw,
+                                                              int lt_shift)
+{
+    constexpr int M = PL::L, Tp = PL::Tp, R0 = PL::first, Rl = PL::last, Rmax = PL::Rmax;
+    constexpr int LD = M;  // row pitch in LDS
+    __shared__ cx<T> sh[ROWS * LD];
+    const int tid = threadIdx.x, p = tid / Tp, t = tid - p * Tp;
+    const int64_t row = (int64_t)blockIdx.x * ROWS + p;
+    const bool valid = row < nrows;
+    const cx<T> *src = reinterpret_cast<const cx<T> *>(in) + (valid ? row : 0) * M;
+    cx<T> v[Rmax];
+#pragma unroll
+    for (int b = 0; b < Rmax / R0; ++b)
+#pragma unroll
+        for (int r = 0; r < R0; ++r) {
+            cx<T> z = valid ? src[t + b * Tp + r * (M / R0)] : cx<T>{T(0), T(0)};
+            if constexpr (CUBE) z = {z.x * z.x * z.x, z.y * z.y * z.y};
+            v[b * R0 + r] = z;
+        }
+    auto lds = [&](int e) -> cx<T> & { return sh[p * LD + e]; };
+    fft_stages<T, PL, -1>(v, t, lds, tw, lt_shift);
+    __syncthreads();
+#pragma unroll
+    for (int b = 0; b < Rmax / Rl; ++b)
+#pragma unroll
+        for (int r = 0; r < Rl; ++r) lds(t + b * Tp + r * (M / Rl)) = v[b * Rl + r];
+    __syncthreads();
+    cx<T> *dst = out + (valid ? row : 0) * M;
+    constexpr int tshift = ilog2c(2 * M);
+    const T h = T(0.5);
+#pragma unroll
+    for (int b = 0; b < Rmax / Rl; ++b)
+#pragma unroll
+        for (int r = 0; r < Rl; ++r) {
+            const int k = t + b * Tp + r * (M / Rl);
+            const cx<T> Zk = v[b * Rl + r];
+            cx<T> X;
+            if (k == 0) {
+                X = {Zk.x + Zk.y, Zk.x - Zk.y};
+            } else {
+                const cx<T> Zp = lds(M - k);
+                const cx<T> E = {(Zk.x + Zp.x) * h, (Zk.y - Zp.y) * h};
+                const cx<T> O = {(Zk.y + Zp.y) * h, (Zp.x - Zk.x) * h};
+                X = E + cmul(tw[k << (lt_shift - tshift)], O);
+            }
+            if (valid) dst[k] = X;
+        }
+}
+
+// ------------------------------------------------------------------------------------------------
+// x axis, inverse: M packed complex -> 2M reals (times `scale`).  For k = 1..M-1
+//   E = (X(k) + conj X(M-k)) / 2,  O = conj(W_{2M}^k) (X(k) - conj X(M-k)) / 2,  Z(k) = E + i O,
+// Z(0) = ((X0 + XM) + i (X0 - XM)) / 2 from the packed slot; z = IFFT_M(Z) (unnormalised);
+// x[2m] = Re z[m] * scale, x[2m+1] = Im z[m] * scale.
+//
+// EPI_PLAIN stores x.  EPI_ADJOINT transforms two spectra (mu from `in`, nu from `in2`) and stores
+//   out = mu - c3 * psi_n^2 * nu,   and writes the block's FP64 sum of nu * psi_np1 to partial[].
+// `in2` and `out` may be the same buffer: each block reads its rows completely before writing.
+enum { EPI_PLAIN = 0, EPI_ADJOINT = 1 };
+
+template <typename T>
+struct AdjEpi {
+    const cx<T> *in2;
+    const T *psi_n;
+    const T *psi_np1;
+    T c3;
+    double *partial;
+};
+
+template <typename T, class PL, int ROWS>
+__device__ __forceinline__ void x_c2r_row(cx<T> *v, const cx<T> *src, bool valid, int t, cx<T> *rowlds,
+                                          const cx<T> *__restrict__ tw, int lt_shift)
+{
+    constexpr int M = PL::L, Tp = PL::Tp, R0 = PL::first, Rmax = PL::Rmax;
+    constexpr int tshift = ilog2c(2 * M);
+    __syncthreads();
+#pragma unroll
+    for (int b = 0; b < Rmax / R0; ++b)
+#pragma unroll
+        for (int r = 0; r < R0; ++r) {
+            const int k = t + b * Tp + r * (M / R0);
+            v[b * R0 + r] = valid ? src[k] : cx<T>{T(0), T(0)};
+            rowlds[k] = v[b * R0 + r];
+        }
+    __syncthreads();
+    const T h = T(0.5);
+#pragma unroll
+    for (int b = 0; b < Rmax / R0; ++b)
+#pragma unroll
+        for (int r = 0; r < R0; ++r) {
+            const int k = t + b * Tp + r * (M / R0);
+            const cx<T> a = v[b * R0 + r];
+            if (k == 0) {
+                v[b * R0 + r] = {(a.x + a.y) * h, (a.x - a.y) * h};
+            } else {
+                const cx<T> c = rowlds[M - k];  // X(M-k); conj taken below
+                const cx<T> E = {(a.x + c.x) * h, (a.y - c.y) * h};
+                const cx<T> D = {(a.x - c.x) * h, (a.y + c.y) * h};
+                const cx<T> O = cmul(conj(tw[k << (lt_shift - tshift)]), D);
+                v[b * R0 + r] = {E.x - O.y, E.y + O.x};
+            }
+        }
+}
+
+template <typename T, class PL, int ROWS, int EPI>
+__global__ __launch_bounds__(ROWS *PL::Tp) void x_c2r_kernel(const cx<T> *in, T *out, int64_t nrows,
+                                                              const cx<T> *__restrict__ tw, int lt_shift, T sc,
+                                                              AdjEpi<T> ea)
+{
+    constexpr int M = PL::L, Tp = PL::Tp, Rl = PL::last, Rmax = PL::Rmax;
+    constexpr int LD = M;
+    __shared__ cx<T> sh[ROWS * LD];
+    const int tid = threadIdx.x, p = tid / Tp, t = tid - p * Tp;
+    const int64_t row = (int64_t)blockIdx.x * ROWS + p;
+    const bool valid = row < nrows;
+    const int64_t r0 = valid ? row : 0;
+    auto lds = [&](int e) -> cx<T> & { return sh[p * LD + e]; };
+    cx<T> v[Rmax];
+    x_c2r_row<T, PL, ROWS>(v, in + r0 * M, valid, t, &sh[p * LD], tw, lt_shift);
+    fft_stages<T, PL, +1>(v, t, lds, tw, lt_shift);
+    cx<T> *dst = reinterpret_cast<cx<T> *>(out) + r0 * M;
+    if constexpr (EPI == EPI_PLAIN) {
+        if (valid) {
+#pragma unroll
+            for (int b = 0; b < Rmax / Rl; ++b)
+#pragma unroll
+                for (int r = 0; r < Rl; ++r)
+                    dst[t + b * Tp + r * (M / Rl)] = scale(v[b * Rl + r], sc);
+        }
+    } else {
+        cx<T> w[Rmax];
+        x_c2r_row<T, PL, ROWS>(w, ea.in2 + r0 * M, valid, t, &sh[p * LD], tw, lt_shift);
+        fft_stages<T, PL, +1>(w, t, lds, tw, lt_shift);
+        const cx<T> *pn = reinterpret_cast<const cx<T> *>(ea.psi_n) + r0 * M;
+        const cx<T> *pn1 = reinterpret_cast<const cx<T> *>(ea.psi_np1) + r0 * M;
+        double acc = 0.0;
+        if (valid) {
+#pragma unroll
+            for (int b = 0; b < Rmax / Rl; ++b)
+#pragma unroll
+                for (int r = 0; r < Rl; ++r) {
+                    const int m = t + b * Tp + r * (M / Rl);
+                    const cx<T> mu = scale(v[b * Rl + r], sc), nu = scale(w[b * Rl + r], sc);
+                    const cx<T> a = pn[m], c = pn1[m];
+                    dst[m] = {mu.x - ea.c3 * a.x * a.x * nu.x, mu.y - ea.c3 * a.y * a.y * nu.y};
+                    acc += (double)nu.x * (double)c.x + (double)nu.y * (double)c.y;
+                }
+        }
+        __shared__ double red[16];
+        const double s = block_sum(acc, red);
+        if (threadIdx.x == 0) ea.partial[blockIdx.x] = s;
+    }
+}
+
+// ------------------------------------------------------------------------------------------------
+// Strided complex FFT along one axis, out of place or in place (src == dst).
+// Pencil (batch, col) has element e at  batch*bstride + e*estride + col,  col < ncols contiguous.
+// A workgroup handles W adjacent columns (W <= WMAX); its threads are laid out column-fastest so
+// each load/store instruction moves W * sizeof(cx) contiguous bytes per element row.
+template <typename T, class PL, int WMAX, int DIR>
+__global__ __launch_bounds__(WMAX *PL::Tp) void axis_c2c_kernel(const cx<T> *src, cx<T> *dst, int W,
+                                                                 int64_t ncols, int64_t estride, int64_t bstride,
+                                                                 int64_t tiles_per_batch,
+                                                                 const cx<T> *__restrict__ tw, int lt_shift)
+{
+    constexpr int L = PL::L, Tp = PL::Tp, R0 = PL::first, Rl = PL::last, Rmax = PL::Rmax;
+    __shared__ cx<T> sh[L * WMAX];
+    const int tid = threadIdx.x, p = tid % WMAX, t = tid / WMAX;
+    const int64_t batch = blockIdx.x / tiles_per_batch, tile = blockIdx.x - batch * tiles_per_batch;
+    const int64_t col = tile * W + p;
+    const bool valid = p < W && col < ncols;
+    const int64_t base = batch * bstride + (valid ? col : 0);
+    cx<T> v[Rmax];
+#pragma unroll
+    for (int b = 0; b < Rmax / R0; ++b)
+#pragma unroll
+        for (int r = 0; r < R0; ++r)
+            v[b * R0 + r] = valid ? src[base + (int64_t)(t + b * Tp + r * (L / R0)) * estride] : cx<T>{T(0), T(0)};
+    auto lds = [&](int e) -> cx<T> & { return sh[e * WMAX + p]; };
+    fft_stages<T, PL, DIR>(v, t, lds, tw, lt_shift);
+    if (valid) {
+#pragma unroll
+        for (int b = 0; b < Rmax / Rl; ++b)
+#pragma unroll
+            for (int r = 0; r < Rl; ++r) dst[base + (int64_t)(t + b * Tp + r * (L / Rl)) * estride] = v[b * Rl + r];
+    }
+}
+
+// ------------------------------------------------------------------------------------------------
+// Last-axis pass (z in 3D, y in 2D): FFT length L = n0 along the slowest axis, rows = n1 (3D) or 1
+// (2D), M columns per row.  Element e of pencil (row, kx) sits at e*nrows*M + row*M + kx.
+//
+// Column kx = 0 pencils need their mirror pencil (row' = -row mod nrows, element -e mod L) to
+// separate the two folded planes.  Tiles: W adjacent columns of one row for column tiles >= 1;
+// column tile 0 is covered by "pair tiles" that take W/2 columns of row a and the same W/2 columns
+// of its mirror row b (pairs (0, nrows/2) and (i, nrows-i)), so a pencil and its mirror always
+// share a workgroup.  With nrows == 1 every kx = 0 pencil is its own mirror.
+enum { LA_STEP = 0, LA_R2C_NATURAL = 1, LA_C2R_NATURAL = 2, LA_ADJOINT = 3 };
+
+template <typename T>
+struct LastAxisArgs {
+    const cx<T> *src;  // packed (STEP, R2C_NATURAL, ADJOINT) or natural (C2R_NATURAL) input
+    cx<T> *dst;        // packed (STEP, C2R_NATURAL, ADJOINT: mu) or natural (R2C_NATURAL) output
+    cx<T> *dst2;       // ADJOINT: nu
+    cx<T> *state;      // STEP: native state, updated in place
+    int64_t nrows;
+    int M;
+    int W;
+    int tiles_per_row;
+    const cx<T> *tw;
+    int lt_shift;
+    ModelParams<T> mp;
+};
+
+struct SlotInfo {
+    int64_t row;
+    int kx;
+    int partner;  // partner slot for kx == 0 pencils, -1 otherwise
+    bool has_pairs;
+};
+
+__device__ __forceinline__ SlotInfo la_slot(int64_t nrows, int TR, int W, int p)
+{
+    SlotInfo s;
+    const int64_t bid = blockIdx.x;
+    if (nrows == 1) {
+        s.row = 0;
+        s.kx = (int)bid * W + p;
+        s.partner = (s.kx == 0) ? p : -1;
+        s.has_pairs = (bid == 0);
+        return s;
+    }
+    const int64_t n_normal = nrows * (TR - 1);
+    if (bid < n_normal) {
+        s.row = bid / (TR - 1);
+        s.kx = (int)(1 + bid % (TR - 1)) * W + p;
+        s.partner = -1;
+        s.has_pairs = false;
+        return s;
+    }
+    const int64_t k = bid - n_normal, i = k >> 1;
+    const int h = (int)(k & 1), hw = W >> 1;
+    const int64_t ra = (i == 0) ? 0 : i, rb = (i == 0) ? nrows / 2 : nrows - i;
+    const bool first = p < hw;
+    s.row = first ? ra : rb;
+    s.kx = h * hw + (first ? p : p - hw);
+    s.partner = (s.kx == 0) ? ((i == 0) ? p : (first ? p + hw : p - hw)) : -1;
+    s.has_pairs = (h == 0);
+    return s;
+}
+
+template <typename T, class PL, int WMAX, int MODE>
+__global__ __launch_bounds__(WMAX *PL::Tp) void last_axis_kernel(LastAxisArgs<T> a)
+{
+    constexpr int L = PL::L, Tp = PL::Tp, Rmax = PL::Rmax;
+    using PR = typename PL::Reverse;  // inverse schedule: its first radix is PL's last
+    constexpr int Rl = PL::last;
+    __shared__ cx<T> sh[L * WMAX];
+    const int tid = threadIdx.x, p = tid % WMAX, t = tid / WMAX;
+    const int W = a.W;
+    const int64_t nrows = a.nrows, M = a.M, estride = nrows * M;
+    const SlotInfo si = la_slot(nrows, a.tiles_per_row, W, p < W ? p : 0);
+    const bool valid = p < W;
+    const int64_t coloff = si.row * M + si.kx;
+    auto lds = [&](int e) -> cx<T> & { return sh[e * WMAX + p]; };
+    const ModelParams<T> &mp = a.mp;
+    const T ky = mp.fk[1] * (T)signed_index(si.row, nrows);
+    const T kx = mp.fk[2] * (T)si.kx;
+    const T kxn = mp.fk[2] * (T)M;  // x Nyquist wavenumber
+    cx<T> v[Rmax];
+
+    if constexpr (MODE == LA_C2R_NATURAL) {
+        // natural half spectrum in: fold kx = 0 and kx = M (projected) into one plane, inverse FFT
+        constexpr int R0 = PR::first;
+        const int64_t prow = (si.partner >= 0) ? la_slot(nrows, a.tiles_per_row, W, si.partner).row : 0;
+        const int64_t pitch = M + 1;
+#pragma unroll
+        for (int b = 0; b < Rmax / R0; ++b)
+#pragma unroll
+            for (int r = 0; r < R0; ++r) {
+                const int e = t + b * Tp + r * (L / R0);
+                cx<T> z = {T(0), T(0)};
+                if (valid) {
+                    const int64_t i0 = ((int64_t)e * nrows + si.row) * pitch;
+                    if (si.partner < 0) {
+                        z = a.src[i0 + si.kx];
+                    } else {
+                        const int ep = (L - e) & (L - 1);
+                        const int64_t i1 = ((int64_t)ep * nrows + prow) * pitch;
+                        const cx<T> x0 = a.src[i0], x0p = a.src[i1], xn = a.src[i0 + M], xnp = a.src[i1 + M];
+                        const T h = T(0.5);
+                        const cx<T> P0 = {(x0.x + x0p.x) * h, (x0.y - x0p.y) * h};
+                        const cx<T> PN = {(xn.x + xnp.x) * h, (xn.y - xnp.y) * h};
+                        z = {P0.x - PN.y, P0.y + PN.x};
+                    }
+                }
+                v[b * R0 + r] = z;
+            }
+        fft_stages<T, PR, +1>(v, t, lds, a.tw, a.lt_shift);
+        if (valid) {
+            constexpr int Rf = PR::last;
+#pragma unroll
+            for (int b = 0; b < Rmax / Rf; ++b)
+#pragma unroll
+                for (int r = 0; r < Rf; ++r)
+                    a.dst[(int64_t)(t + b * Tp + r * (L / Rf)) * estride + coloff] = v[b * Rf + r];
+        }
+        return;
+    } else {
+        // packed input, forward FFT
+        constexpr int R0 = PL::first;
+#pragma unroll
+        for (int b = 0; b < Rmax / R0; ++b)
+#pragma unroll
+            for (int r = 0; r < R0; ++r)
+                v[b * R0 + r] =
+                    valid ? a.src[(int64_t)(t + b * Tp + r * (L / R0)) * estride + coloff] : cx<T>{T(0), T(0)};
+        fft_stages<T, PL, -1>(v, t, lds, a.tw, a.lt_shift);
+        // forward spectrum in natural order: v[b*Rl + r] = X(e), e = t + b*Tp + r*L/Rl
+        if (si.has_pairs) {  // uniform per workgroup
+            __syncthreads();
+#pragma unroll
+            for (int b = 0; b < Rmax / Rl; ++b)
+#pragma unroll
+                for (int r = 0; r < Rl; ++r) lds(t + b * Tp + r * (L / Rl)) = v[b * Rl + r];
+            __syncthreads();
+        }
+        auto partner_val = [&](int e) -> cx<T> { return sh[((L - e) & (L - 1)) * WMAX + si.partner]; };
+        const int64_t prow_off =
+            (si.partner >= 0) ? la_slot(nrows, a.tiles_per_row, W, si.partner).row * M : 0;  // partner's kx = 0
+
+        if constexpr (MODE == LA_R2C_NATURAL) {
+            const int64_t pitch = M + 1;
+            if (valid) {
+#pragma unroll
+                for (int b = 0; b < Rmax / Rl; ++b)
+#pragma unroll
+                    for (int r = 0; r < Rl; ++r) {
+                        const int e = t + b * Tp + r * (L / Rl);
+                        const int64_t i0 = ((int64_t)e * nrows + si.row) * pitch;
+                        const cx<T> z = v[b * Rl + r];
+                        if (si.partner < 0) {
+                            a.dst[i0 + si.kx] = z;
+                        } else {
+                            const cx<T> zp = partner_val(e);
+                            const T h = T(0.5);
+                            a.dst[i0] = {(z.x + zp.x) * h, (z.y - zp.y) * h};
+                            a.dst[i0 + M] = {(z.y + zp.y) * h, (zp.x - z.x) * h};
+                        }
+                    }
+            }
+            return;
+        } else if constexpr (MODE == LA_STEP) {
+            const T dt = mp.dt, nl = mp.nl;
+#pragma unroll
+            for (int b = 0; b < Rmax / Rl; ++b)
+#pragma unroll
+                for (int r = 0; r < Rl; ++r) {
+                    const int e = t + b * Tp + r * (L / Rl);
+                    const T kz = mp.fk[0] * (T)signed_index(e, L);
+                    const int64_t gi = (int64_t)e * estride + coloff;
+                    cx<T> N = v[b * Rl + r];
+                    N = {N.x * nl, N.y * nl};
+                    cx<T> S = valid ? a.state[gi] : cx<T>{T(0), T(0)};
+                    cx<T> Snew;
+                    if (si.partner < 0) {
+                        const T q = kz * kz + ky * ky + kx * kx;
+                        const T A = amult(mp, q), dq = dt * q;
+                        Snew = {(S.x - dq * N.x) * A, (S.y - dq * N.y) * A};
+                    } else {
+                        const int ep = (L - e) & (L - 1);
+                        cx<T> Np = partner_val(e);
+                        Np = {Np.x * nl, Np.y * nl};
+                        const cx<T> Sp = valid ? a.state[(int64_t)ep * estride + prow_off] : cx<T>{T(0), T(0)};
+                        const T h = T(0.5);
+                        // the two Hermitian planes of state and cube spectrum
+                        const cx<T> S0 = {(S.x + Sp.x) * h, (S.y - Sp.y) * h};
+                        const cx<T> SN = {(S.y + Sp.y) * h, (Sp.x - S.x) * h};
+                        const cx<T> N0 = {(N.x + Np.x) * h, (N.y - Np.y) * h};
+                        const cx<T> NN = {(N.y + Np.y) * h, (Np.x - N.x) * h};
+                        const T q0 = kz * kz + ky * ky, qn = q0 + kxn * kxn;
+                        const T A0 = amult(mp, q0), AN = amult(mp, qn);
+                        const T d0 = dt * q0, dn = dt * qn;
+                        const cx<T> U0 = {(S0.x - d0 * N0.x) * A0, (S0.y - d0 * N0.y) * A0};
+                        const cx<T> UN = {(SN.x - dn * NN.x) * AN, (SN.y - dn * NN.y) * AN};
+                        Snew = {U0.x - UN.y, U0.y + UN.x};  // U0 + i UN
+                    }
+                    if (valid) a.state[gi] = Snew;
+                    v[b * Rl + r] = Snew;
+                }
+            fft_stages<T, PR, +1>(v, t, lds, a.tw, a.lt_shift);
+            if (valid) {
+                constexpr int Rf = PR::last;
+#pragma unroll
+                for (int b = 0; b < Rmax / Rf; ++b)
+#pragma unroll
+                    for (int r = 0; r < Rf; ++r)
+                        a.dst[(int64_t)(t + b * Tp + r * (L / Rf)) * estride + coloff] = v[b * Rf + r];
+            }
+        } else if constexpr (MODE == LA_ADJOINT) {
+            cx<T> w[Rmax];
+#pragma unroll
+            for (int b = 0; b < Rmax / Rl; ++b)
+#pragma unroll
+                for (int r = 0; r < Rl; ++r) {
+                    const int e = t + b * Tp + r * (L / Rl);
+                    const T kz = mp.fk[0] * (T)signed_index(e, L);
+                    const cx<T> z = v[b * Rl + r];
+                    cx<T> mu, nu;
+                    if (si.partner < 0) {
+                        const T q = kz * kz + ky * ky + kx * kx;
+                        const T A = amult(mp, q);
+                        mu = {z.x * A, z.y * A};
+                        nu = {mu.x * q, mu.y * q};
+                    } else {
+                        const cx<T> zp = partner_val(e);
+                        const T h = T(0.5);
+                        const cx<T> U = {(z.x + zp.x) * h, (z.y - zp.y) * h};
+                        const cx<T> V = {(z.y + zp.y) * h, (zp.x - z.x) * h};
+                        const T q0 = kz * kz + ky * ky, qn = q0 + kxn * kxn;
+                        const T A0 = amult(mp, q0), AN = amult(mp, qn);
+                        const cx<T> mU = {U.x * A0, U.y * A0}, mV = {V.x * AN, V.y * AN};
+                        mu = {mU.x - mV.y, mU.y + mV.x};
+                        nu = {mU.x * q0 - mV.y * qn, mU.y * q0 + mV.x * qn};
+                    }
+                    v[b * Rl + r] = mu;
+                    w[b * Rl + r] = nu;
+                }
+            constexpr int Rf = PR::last;
+            fft_stages<T, PR, +1>(v, t, lds, a.tw, a.lt_shift);
+            if (valid) {
+#pragma unroll
+                for (int b = 0; b < Rmax / Rf; ++b)
+#pragma unroll
+                    for (int r = 0; r < Rf; ++r)
+                        a.dst[(int64_t)(t + b * Tp + r * (L / Rf)) * estride + coloff] = v[b * Rf + r];
+            }
+            fft_stages<T, PR, +1>(w, t, lds, a.tw, a.lt_shift);
+            if (valid) {
+#pragma unroll
+                for (int b = 0; b < Rmax / Rf; ++b)
+#pragma unroll
+                    for (int r = 0; r < Rf; ++r)
+                        a.dst2[(int64_t)(t + b * Tp + r * (L / Rf)) * estride + coloff] = w[b * Rf + r];
+            }
+        }
+    }
+}
+
+// ------------------------------------------------------------------------------------------------
+// Reductions (FP64 accumulation, fixed grid and order: deterministic).
+
+// partial[block] = sum of x over a grid-stride range.
+template <typename T>
+__global__ __launch_bounds__(256) void sum_kernel(const T *__restrict__ x, int64_t n, double *partial)
+{
+    double acc = 0.0;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        acc += (double)x[i];
+    __shared__ double red[4];
+    const double s = block_sum(acc, red);
+    if (threadIdx.x == 0) partial[blockIdx.x] = s;
+}
+
+// state[0].x = (T) sum(partial[0..np)) -- the mass mode from an FP64 sum of the field.
+template <typename T>
+__global__ void set_mass_kernel(const double *partial, int np, cx<T> *state)
+{
+    if (threadIdx.x == 0 && blockIdx.x == 0) {
+        double s = 0.0;
+        for (int i = 0; i < np; ++i) s += partial[i];
+        state[0].x = (T)s;
+    }
+}
+
+// *acc += coef * sum(partial[0..np))
+__global__ void accumulate_kernel(const double *partial, int np, double coef, double *acc);
+
+// Spectral quadratic part of the energy: sum over the full spectrum of (r + L(q)) |psi_hat|^2,
+// from the native state (FP64 throughout).  Geometry as in the last-axis pass.
+template <typename T>
+__global__ __launch_bounds__(256) void energy_spec_kernel(const cx<T> *__restrict__ state, int64_t L, int64_t nrows,
+                                                          int64_t M, double fk0, double fk1, double fk2, double r,
+                                                          double q1sq, double R1, int model, double *partial)
+{
+    const int64_t n = L * nrows * M;
+    auto corr = [&](double q) {
+        double a = (1.0 - q) * (1.0 - q);
+        if (model == 0) return a;
+        double b = q1sq - q;
+        return a * (b * b + R1);
+    };
+    double acc = 0.0;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t kx = i % M, rest = i / M, row = rest % nrows, e = rest / nrows;
+        const double kz = fk0 * signed_index(e, L), ky = fk1 * signed_index(row, nrows);
+        const cx<T> s = state[i];
+        if (kx != 0) {
+            const double k = fk2 * (double)kx, q = kz * kz + ky * ky + k * k;
+            acc += 2.0 * (r + corr(q)) * ((double)s.x * s.x + (double)s.y * s.y);
+        } else {
+            const int64_t ep = (L - e) % L, rp = (nrows - row) % nrows;
+            const cx<T> sp = state[(ep * nrows + rp) * M];
+            const double ax = 0.5 * ((double)s.x + sp.x), ay = 0.5 * ((double)s.y - sp.y);
+            const double bx = 0.5 * ((double)s.y + sp.y), by = 0.5 * ((double)sp.x - s.x);
+            const double q0 = kz * kz + ky * ky, kn = fk2 * (double)M, qn = q0 + kn * kn;
+            acc += (r + corr(q0)) * (ax * ax + ay * ay) + (r + corr(qn)) * (bx * bx + by * by);
+        }
+    }
+    __shared__ double red[4];
+    const double s = block_sum(acc, red);
+    if (threadIdx.x == 0) partial[blockIdx.x] = s;
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void quartic_kernel(const T *__restrict__ psi, int64_t n, double *partial)
+{
+    double acc = 0.0;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        const double v = (double)psi[i] * (double)psi[i];
+        acc += 0.25 * v * v;
+    }
+    __shared__ double red[4];
+    const double s = block_sum(acc, red);
+    if (threadIdx.x == 0) partial[blockIdx.x] = s;
+}
+
+// out[0] = dV (sum(ps)/(2N) + sum(pq)), out[1] = state[0].x / N.
+template <typename T>
+__global__ void energy_final_kernel(const double *ps, const double *pq, int np, double dV, double ntot,
+                                    const cx<T> *state, double *out)
+{
+    if (threadIdx.x == 0 && blockIdx.x == 0) {
+        double a = 0.0, b = 0.0;
+        for (int i = 0; i < np; ++i) a += ps[i];
+        for (int i = 0; i < np; ++i) b += pq[i];
+        out[0] = dV * (a / (2.0 * ntot) + b);
+        out[1] = (double)state[0].x / ntot;
+    }
+}
+
+// Native state -> natural half spectrum [L][nrows][M+1].
+template <typename T>
+__global__ __launch_bounds__(256) void export_kernel(const cx<T> *__restrict__ state, cx<T> *__restrict__ out,
+                                                     int64_t L, int64_t nrows, int64_t M)
+{
+    const int64_t n = L * nrows * (M + 1);
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t kx = i % (M + 1), rest = i / (M + 1), row = rest % nrows, e = rest / nrows;
+        if (kx > 0 && kx < M) {
+            out[i] = state[rest * M + kx];
+        } else {
+            const int64_t ep = (L - e) % L, rp = (nrows - row) % nrows;
+            const cx<T> s = state[rest * M], sp = state[(ep * nrows + rp) * M];
+            const T h = T(0.5);
+            out[i] = (kx == 0) ? cx<T>{(s.x + sp.x) * h, (s.y - sp.y) * h} : cx<T>{(s.y + sp.y) * h, (sp.x - s.x) * h};
+        }
+    }
+}
+
+}  // namespace pfc

@@ -1,0 +1,59 @@
+// launch.hpp -- host-side launchers of the PFC kernels, one set per dtype (float, double).
+// Each returns the HIP error of its launch; shapes are validated by the caller (pfc_api.cpp).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "types.hpp"
+
+namespace pfc {
+
+// Geometry of a 2D/3D grid as the kernels see it.
+struct Geom {
+    int ndim;
+    int64_t n0, n1, nx;  // 2D: n0 = y, n1 = 1 (unused), nx = x; 3D: z, y, x
+    int64_t M;           // nx / 2
+    int64_t nrows;       // rows of the last-axis pass: n1 (3D) or 1 (2D)
+    int64_t xrows;       // rows of the x pass: n0 * nrows
+    int lt_shift;        // log2 of the twiddle table length
+};
+
+template <typename T>
+hipError_t launch_x_r2c(const Geom &g, const T *in, cx<T> *out, bool cube, const cx<T> *tw, hipStream_t s);
+
+template <typename T>
+hipError_t launch_x_c2r(const Geom &g, const cx<T> *in, T *out, const cx<T> *tw, hipStream_t s);
+
+// adjoint epilogue: out = mu - c3 psi_n^2 nu; partial[block] = sum nu psi_np1.  Returns the number
+// of partials through *nblocks.
+template <typename T>
+hipError_t launch_x_c2r_adjoint(const Geom &g, const cx<T> *mu, const cx<T> *nu, const T *psi_n, const T *psi_np1,
+                                T *out, T c3, double *partial, int64_t *nblocks, const cx<T> *tw, hipStream_t s);
+
+// y-axis (3D middle axis) complex FFT, in place; dir = -1 forward, +1 inverse.
+template <typename T>
+hipError_t launch_y_c2c(const Geom &g, cx<T> *data, int dir, const cx<T> *tw, hipStream_t s);
+
+// last-axis complex FFT, forward, out of place, packed in and out (no update).
+template <typename T>
+hipError_t launch_last_fwd(const Geom &g, const cx<T> *src, cx<T> *dst, const cx<T> *tw, hipStream_t s);
+
+enum LastMode { LAST_STEP = 0, LAST_R2C_NATURAL = 1, LAST_C2R_NATURAL = 2, LAST_ADJOINT = 3 };
+
+template <typename T>
+hipError_t launch_last(const Geom &g, int mode, const cx<T> *src, cx<T> *dst, cx<T> *dst2, cx<T> *state,
+                       const ModelParams<T> &mp, const cx<T> *tw, hipStream_t s);
+
+// reductions; every launcher uses exactly kReduceBlocks partials
+constexpr int kReduceBlocks = 1024;
+template <typename T>
+hipError_t launch_set_mass(const T *psi, int64_t n, double *partial, cx<T> *state, hipStream_t s);
+template <typename T>
+hipError_t launch_energy(const Geom &g, const T *psi, const cx<T> *state, const double fk[3], double r, double q1sq,
+                         double R1, int model, double dV, double *partial, double *out, hipStream_t s);
+template <typename T>
+hipError_t launch_export(const Geom &g, const cx<T> *state, cx<T> *out, hipStream_t s);
+hipError_t launch_accumulate(const double *partial, int np, double coef, double *acc, hipStream_t s);
+
+}  // namespace pfc

@@ -1,0 +1,540 @@
+// pfc_api.cpp -- C ABI of the PFC library: plan validation, workspace, and the pass sequences of
+// each entry point (see include/pfc.h for the contract of every call).
+#include "../../include/pfc.h"
+
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "launch.hpp"
+#include "types.hpp"
+
+using pfc::cx;
+using pfc::Geom;
+
+struct pfc_plan {
+    pfc_plan_desc d;
+    Geom g;
+    double fk[3];  // 2 pi / (n dx) for axes (last-axis, rows, x)
+    double dV;
+    size_t tw_off, partial_off, scratch_off, ws_need;
+    size_t n_partials;
+    char *ws = nullptr;
+    size_t ws_bytes = 0;
+};
+
+namespace {
+
+thread_local std::string g_last_error;
+
+pfc_status fail(pfc_status st, const char *fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_last_error = buf;
+    return st;
+}
+
+pfc_status hip_fail(hipError_t e, const char *what)
+{
+    return fail(PFC_ERR_HIP, "%s: %s", what, hipGetErrorString(e));
+}
+
+bool is_pow2(int64_t v) { return v > 0 && (v & (v - 1)) == 0; }
+
+size_t align256(size_t v) { return (v + 255) & ~size_t(255); }
+
+size_t cx_size(const pfc_plan *p) { return p->d.dtype == PFC_F64 ? 16 : 8; }
+
+double corr_op(const pfc_plan_desc &d, double q)
+{
+    double a = (1.0 - q) * (1.0 - q);
+    if (d.model == PFC_ONE_MODE) return a;
+    double b = d.q1sq - q;
+    return a * (b * b + d.R1);
+}
+
+// The implicit denominator 1 + dt q (r + L(q)) must stay positive for every q in [0, qmax]
+// (qmax = |k|^2 at the corner of the grid).  Checked on a dense sampling of the interval.
+pfc_status check_denominator(const pfc_plan_desc &d)
+{
+    double qmax = 0.0;
+    for (int a = 0; a < d.ndim; ++a) {
+        double k = M_PI / d.dx[a];
+        qmax += k * k;
+    }
+    const int ns = 1 << 18;
+    double worst = INFINITY, worst_q = 0.0;
+    for (int i = 0; i <= ns; ++i) {
+        double q = qmax * (double)i / ns;
+        double den = 1.0 + d.dt * q * (d.r + corr_op(d, q));
+        if (!(den > worst)) {
+            worst = den;
+            worst_q = q;
+        }
+    }
+    if (!(worst > 0.0))
+        return fail(PFC_ERR_INVALID_ARG, "1 + dt q (r + L(q)) = %g <= 0 at q = %g: dt too large for this r", worst,
+                    worst_q);
+    return PFC_OK;
+}
+
+pfc_status validate_desc(const pfc_plan_desc *d)
+{
+    if (!d) return fail(PFC_ERR_INVALID_ARG, "desc is NULL");
+    if (d->ndim != 2 && d->ndim != 3) return fail(PFC_ERR_UNSUPPORTED, "ndim must be 2 or 3 (got %d)", d->ndim);
+    for (int a = 0; a < d->ndim; ++a) {
+        if (!is_pow2(d->n[a]) || d->n[a] < 4 || d->n[a] > 2048)
+            return fail(PFC_ERR_UNSUPPORTED, "n[%d] = %lld: sizes must be powers of two in [4, 2048]", a,
+                        (long long)d->n[a]);
+        if (!(d->dx[a] > 0.0) || !std::isfinite(d->dx[a])) return fail(PFC_ERR_INVALID_ARG, "dx[%d] must be > 0", a);
+    }
+    if (d->dtype != PFC_F32 && d->dtype != PFC_F64) return fail(PFC_ERR_INVALID_ARG, "unknown dtype %d", (int)d->dtype);
+    if (d->model != PFC_ONE_MODE && d->model != PFC_TWO_MODE)
+        return fail(PFC_ERR_INVALID_ARG, "unknown model %d", (int)d->model);
+    if (!std::isfinite(d->r) || !std::isfinite(d->q1sq) || !std::isfinite(d->R1))
+        return fail(PFC_ERR_INVALID_ARG, "non-finite model parameter");
+    if (!(d->dt > 0.0) || !std::isfinite(d->dt)) return fail(PFC_ERR_INVALID_ARG, "dt must be > 0 and finite");
+    if (d->flags & ~PFC_FLAG_LINEAR_ONLY) return fail(PFC_ERR_INVALID_ARG, "unknown flag bits 0x%x", d->flags);
+    if (d->device < 0) return fail(PFC_ERR_INVALID_ARG, "device must be >= 0");
+    return check_denominator(*d);
+}
+
+// exp(-2 pi i e / Lt) in extended precision, by octant symmetry so that the table is exactly
+// symmetric, then rounded once to the dtype.
+void twiddle_value(int64_t e, int64_t Lt, long double *c, long double *s)
+{
+    const long double two_pi = 6.283185307179586476925286766559005768L;
+    const int64_t q4 = Lt / 4;
+    e %= Lt;
+    int64_t quad = e / q4, rem = e % q4;
+    long double cc, ss;
+    if (2 * rem <= q4) {
+        long double a = two_pi * (long double)rem / (long double)Lt;
+        cc = cosl(a);
+        ss = sinl(a);
+    } else {
+        long double b = two_pi * (long double)(q4 - rem) / (long double)Lt;
+        cc = sinl(b);
+        ss = cosl(b);
+    }
+    // rotate by quad quarter turns: angle + quad * pi/2
+    for (int64_t k = 0; k < quad; ++k) {
+        long double t = cc;
+        cc = -ss;
+        ss = t;
+    }
+    *c = cc;
+    *s = -ss;  // forward sign
+}
+
+struct DeviceGuard {
+    int prev = -1;
+    hipError_t err = hipSuccess;
+    explicit DeviceGuard(int dev)
+    {
+        err = hipGetDevice(&prev);
+        if (err == hipSuccess && prev != dev) err = hipSetDevice(dev);
+    }
+    ~DeviceGuard()
+    {
+        int cur = -1;
+        if (prev >= 0 && hipGetDevice(&cur) == hipSuccess && cur != prev) (void)hipSetDevice(prev);
+    }
+};
+
+bool aligned16(const void *p) { return ((uintptr_t)p & 15u) == 0; }
+
+pfc_status check_ready(const pfc_plan *p)
+{
+    if (!p) return fail(PFC_ERR_INVALID_ARG, "plan is NULL");
+    if (!p->ws) return fail(PFC_ERR_WORKSPACE, "no workspace attached (pfc_plan_set_workspace)");
+    return PFC_OK;
+}
+
+pfc_status check_ptr(const void *ptr, const char *name)
+{
+    if (!ptr) return fail(PFC_ERR_INVALID_ARG, "%s is NULL", name);
+    if (!aligned16(ptr)) return fail(PFC_ERR_ALIGNMENT, "%s is not 16-byte aligned", name);
+    return PFC_OK;
+}
+
+bool overlap(const void *a, size_t na, const void *b, size_t nb)
+{
+    uintptr_t x = (uintptr_t)a, y = (uintptr_t)b;
+    return x < y + nb && y < x + na;
+}
+
+template <typename T>
+pfc::ModelParams<T> model_params(const pfc_plan *p)
+{
+    pfc::ModelParams<T> m;
+    m.r = (T)p->d.r;
+    m.dt = (T)p->d.dt;
+    m.q1sq = (T)p->d.q1sq;
+    m.R1 = (T)p->d.R1;
+    for (int a = 0; a < 3; ++a) m.fk[a] = (T)p->fk[a];
+    m.nl = (p->d.flags & PFC_FLAG_LINEAR_ONLY) ? T(0) : T(1);
+    m.model = (int)p->d.model;
+    return m;
+}
+
+template <typename T>
+struct Bufs {
+    const cx<T> *tw;
+    double *partial;
+    cx<T> *scratch;
+};
+
+template <typename T>
+Bufs<T> bufs(const pfc_plan *p)
+{
+    return {reinterpret_cast<const cx<T> *>(p->ws + p->tw_off), reinterpret_cast<double *>(p->ws + p->partial_off),
+            reinterpret_cast<cx<T> *>(p->ws + p->scratch_off)};
+}
+
+#define PFC_TRY(call, what)                           \
+    do {                                              \
+        hipError_t e_ = (call);                       \
+        if (e_ != hipSuccess) return hip_fail(e_, what); \
+    } while (0)
+
+// forward transform of a real field into the packed spectrum `out` (x, then y in 3D; the last
+// axis is left to the caller)
+template <typename T>
+pfc_status fwd_xy(const pfc_plan *p, const T *real, bool cube, cx<T> *out, hipStream_t s)
+{
+    const Geom &g = p->g;
+    const Bufs<T> b = bufs<T>(p);
+    PFC_TRY(pfc::launch_x_r2c<T>(g, real, out, cube, b.tw, s), "x_r2c launch");
+    if (g.ndim == 3) PFC_TRY(pfc::launch_y_c2c<T>(g, out, -1, b.tw, s), "y forward launch");
+    return PFC_OK;
+}
+
+template <typename T>
+pfc_status inv_yx(const pfc_plan *p, cx<T> *spec, T *real, hipStream_t s)
+{
+    const Geom &g = p->g;
+    const Bufs<T> b = bufs<T>(p);
+    if (g.ndim == 3) PFC_TRY(pfc::launch_y_c2c<T>(g, spec, +1, b.tw, s), "y inverse launch");
+    PFC_TRY(pfc::launch_x_c2r<T>(g, spec, real, b.tw, s), "x_c2r launch");
+    return PFC_OK;
+}
+
+template <typename T>
+pfc_status do_r2c(pfc_plan *p, const void *in, void *out, hipStream_t s)
+{
+    const Bufs<T> b = bufs<T>(p);
+    pfc_status st = fwd_xy<T>(p, (const T *)in, false, b.scratch, s);
+    if (st) return st;
+    pfc::ModelParams<T> mp = model_params<T>(p);
+    PFC_TRY(pfc::launch_last<T>(p->g, pfc::LAST_R2C_NATURAL, b.scratch, (cx<T> *)out, nullptr, nullptr, mp, b.tw, s),
+            "last-axis launch");
+    return PFC_OK;
+}
+
+template <typename T>
+pfc_status do_c2r(pfc_plan *p, const void *in, void *out, hipStream_t s)
+{
+    const Bufs<T> b = bufs<T>(p);
+    pfc::ModelParams<T> mp = model_params<T>(p);
+    PFC_TRY(pfc::launch_last<T>(p->g, pfc::LAST_C2R_NATURAL, (const cx<T> *)in, b.scratch, nullptr, nullptr, mp, b.tw,
+                                s),
+            "last-axis launch");
+    return inv_yx<T>(p, b.scratch, (T *)out, s);
+}
+
+template <typename T>
+pfc_status do_state_init(pfc_plan *p, const void *psi0, void *state, hipStream_t s)
+{
+    const Bufs<T> b = bufs<T>(p);
+    pfc_status st = fwd_xy<T>(p, (const T *)psi0, false, b.scratch, s);
+    if (st) return st;
+    PFC_TRY(pfc::launch_last_fwd<T>(p->g, b.scratch, (cx<T> *)state, b.tw, s), "last-axis launch");
+    const int64_t ntot = p->g.n0 * p->g.nrows * p->g.nx;
+    PFC_TRY(pfc::launch_set_mass<T>((const T *)psi0, ntot, b.partial, (cx<T> *)state, s), "mass launch");
+    return PFC_OK;
+}
+
+template <typename T>
+pfc_status do_step(pfc_plan *p, void *psi, void *state, int64_t nsteps, hipStream_t s)
+{
+    const Bufs<T> b = bufs<T>(p);
+    const pfc::ModelParams<T> mp = model_params<T>(p);
+    for (int64_t n = 0; n < nsteps; ++n) {
+        pfc_status st = fwd_xy<T>(p, (const T *)psi, true, b.scratch, s);
+        if (st) return st;
+        PFC_TRY(pfc::launch_last<T>(p->g, pfc::LAST_STEP, b.scratch, b.scratch, nullptr, (cx<T> *)state, mp, b.tw, s),
+                "last-axis step launch");
+        st = inv_yx<T>(p, b.scratch, (T *)psi, s);
+        if (st) return st;
+    }
+    return PFC_OK;
+}
+
+template <typename T>
+pfc_status do_backward(pfc_plan *p, const void *psi_n, const void *psi_np1, const void *lam_np1, void *lam_n,
+                       double *dLdr, hipStream_t s)
+{
+    const Geom &g = p->g;
+    const Bufs<T> b = bufs<T>(p);
+    const pfc::ModelParams<T> mp = model_params<T>(p);
+    pfc_status st = fwd_xy<T>(p, (const T *)lam_np1, false, b.scratch, s);
+    if (st) return st;
+    cx<T> *nu = (cx<T> *)lam_n;  // the output buffer holds the nu spectrum until the last pass
+    PFC_TRY(pfc::launch_last<T>(g, pfc::LAST_ADJOINT, b.scratch, b.scratch, nu, nullptr, mp, b.tw, s),
+            "last-axis adjoint launch");
+    if (g.ndim == 3) {
+        PFC_TRY(pfc::launch_y_c2c<T>(g, b.scratch, +1, b.tw, s), "y inverse launch");
+        PFC_TRY(pfc::launch_y_c2c<T>(g, nu, +1, b.tw, s), "y inverse launch");
+    }
+    const T c3 = (p->d.flags & PFC_FLAG_LINEAR_ONLY) ? T(0) : (T)(3.0 * p->d.dt);
+    int64_t nb = 0;
+    PFC_TRY(pfc::launch_x_c2r_adjoint<T>(g, b.scratch, nu, (const T *)psi_n, (const T *)psi_np1, (T *)lam_n, c3,
+                                          b.partial, &nb, b.tw, s),
+            "x_c2r adjoint launch");
+    if ((size_t)nb > p->n_partials) return fail(PFC_ERR_INTERNAL, "partials buffer too small");
+    PFC_TRY(pfc::launch_accumulate(b.partial, (int)nb, -p->d.dt, dLdr, s), "accumulate launch");
+    return PFC_OK;
+}
+
+template <typename T>
+pfc_status do_energy(pfc_plan *p, const void *psi, const void *state, double *out, hipStream_t s)
+{
+    const Bufs<T> b = bufs<T>(p);
+    PFC_TRY(pfc::launch_energy<T>(p->g, (const T *)psi, (const cx<T> *)state, p->fk, p->d.r, p->d.q1sq, p->d.R1,
+                                  (int)p->d.model, p->dV, b.partial, out, s),
+            "energy launch");
+    return PFC_OK;
+}
+
+template <typename T>
+pfc_status do_export(pfc_plan *p, const void *state, void *out, hipStream_t s)
+{
+    PFC_TRY(pfc::launch_export<T>(p->g, (const cx<T> *)state, (cx<T> *)out, s), "export launch");
+    return PFC_OK;
+}
+
+size_t real_bytes(const pfc_plan *p) { return (size_t)(p->g.n0 * p->g.nrows * p->g.nx) * cx_size(p) / 2; }
+size_t half_bytes(const pfc_plan *p) { return (size_t)(p->g.n0 * p->g.nrows * (p->g.M + 1)) * cx_size(p); }
+size_t state_bytes(const pfc_plan *p) { return (size_t)(p->g.n0 * p->g.nrows * p->g.M) * cx_size(p); }
+
+}  // namespace
+
+extern "C" {
+
+pfc_status pfc_plan_create(pfc_plan **out, const pfc_plan_desc *d)
+{
+    if (!out) return fail(PFC_ERR_INVALID_ARG, "out is NULL");
+    *out = nullptr;
+    pfc_status st = validate_desc(d);
+    if (st) return st;
+    pfc_plan *p = new (std::nothrow) pfc_plan();
+    if (!p) return fail(PFC_ERR_INTERNAL, "out of host memory");
+    p->d = *d;
+    Geom &g = p->g;
+    g.ndim = d->ndim;
+    if (d->ndim == 3) {
+        g.n0 = d->n[0];
+        g.n1 = d->n[1];
+        g.nx = d->n[2];
+        g.nrows = d->n[1];
+        p->fk[0] = 2.0 * M_PI / ((double)d->n[0] * d->dx[0]);
+        p->fk[1] = 2.0 * M_PI / ((double)d->n[1] * d->dx[1]);
+        p->fk[2] = 2.0 * M_PI / ((double)d->n[2] * d->dx[2]);
+        p->dV = d->dx[0] * d->dx[1] * d->dx[2];
+    } else {
+        g.n0 = d->n[0];
+        g.n1 = 1;
+        g.nx = d->n[1];
+        g.nrows = 1;
+        p->fk[0] = 2.0 * M_PI / ((double)d->n[0] * d->dx[0]);
+        p->fk[1] = 0.0;
+        p->fk[2] = 2.0 * M_PI / ((double)d->n[1] * d->dx[1]);
+        p->dV = d->dx[0] * d->dx[1];
+    }
+    g.M = g.nx / 2;
+    g.xrows = g.n0 * g.nrows;
+    int64_t Lt = g.nx;
+    if (g.n0 > Lt) Lt = g.n0;
+    if (g.n1 > Lt) Lt = g.n1;
+    g.lt_shift = 0;
+    while ((int64_t(1) << g.lt_shift) < Lt) ++g.lt_shift;
+    const size_t cs = cx_size(p);
+    p->n_partials = (size_t)std::max<int64_t>(2 * pfc::kReduceBlocks, g.xrows);
+    p->tw_off = 0;
+    p->partial_off = align256((size_t)Lt * cs);
+    p->scratch_off = p->partial_off + align256(p->n_partials * sizeof(double));
+    p->ws_need = p->scratch_off + align256(state_bytes(p));
+    *out = p;
+    return PFC_OK;
+}
+
+size_t pfc_plan_workspace_bytes(const pfc_plan *p) { return p ? p->ws_need : 0; }
+size_t pfc_plan_real_bytes(const pfc_plan *p) { return p ? real_bytes(p) : 0; }
+size_t pfc_plan_half_bytes(const pfc_plan *p) { return p ? half_bytes(p) : 0; }
+size_t pfc_plan_state_bytes(const pfc_plan *p) { return p ? state_bytes(p) : 0; }
+
+pfc_status pfc_plan_set_workspace(pfc_plan *p, void *dev_ptr, size_t bytes)
+{
+    if (!p) return fail(PFC_ERR_INVALID_ARG, "plan is NULL");
+    if (!dev_ptr) return fail(PFC_ERR_INVALID_ARG, "workspace is NULL");
+    if (((uintptr_t)dev_ptr & 255u) != 0) return fail(PFC_ERR_ALIGNMENT, "workspace must be 256-byte aligned");
+    if (bytes < p->ws_need) return fail(PFC_ERR_WORKSPACE, "workspace has %zu bytes, needs %zu", bytes, p->ws_need);
+    const int64_t Lt = int64_t(1) << p->g.lt_shift;
+    std::vector<char> host((size_t)Lt * cx_size(p));
+    for (int64_t e = 0; e < Lt; ++e) {
+        long double c, s;
+        twiddle_value(e, Lt, &c, &s);
+        if (p->d.dtype == PFC_F64) {
+            double *t = reinterpret_cast<double *>(host.data()) + 2 * e;
+            t[0] = (double)c;
+            t[1] = (double)s;
+        } else {
+            float *t = reinterpret_cast<float *>(host.data()) + 2 * e;
+            t[0] = (float)c;
+            t[1] = (float)s;
+        }
+    }
+    DeviceGuard dg(p->d.device);
+    if (dg.err != hipSuccess) return hip_fail(dg.err, "hipSetDevice");
+    hipError_t e = hipMemcpy((char *)dev_ptr + p->tw_off, host.data(), host.size(), hipMemcpyHostToDevice);
+    if (e != hipSuccess) return hip_fail(e, "twiddle upload");
+    p->ws = (char *)dev_ptr;
+    p->ws_bytes = bytes;
+    return PFC_OK;
+}
+
+pfc_status pfc_plan_set_params(pfc_plan *p, double r, double dt)
+{
+    if (!p) return fail(PFC_ERR_INVALID_ARG, "plan is NULL");
+    pfc_plan_desc d = p->d;
+    d.r = r;
+    d.dt = dt;
+    pfc_status st = validate_desc(&d);
+    if (st) return st;
+    p->d = d;
+    return PFC_OK;
+}
+
+pfc_status pfc_plan_destroy(pfc_plan *p)
+{
+    delete p;
+    return PFC_OK;
+}
+
+#define PFC_DISPATCH(p, fn, ...)                                                   \
+    do {                                                                           \
+        DeviceGuard dg_((p)->d.device);                                            \
+        if (dg_.err != hipSuccess) return hip_fail(dg_.err, "hipSetDevice");       \
+        return (p)->d.dtype == PFC_F64 ? fn<double>(__VA_ARGS__) : fn<float>(__VA_ARGS__); \
+    } while (0)
+
+#define PFC_CHECK(expr)              \
+    do {                             \
+        pfc_status st_ = (expr);     \
+        if (st_ != PFC_OK) return st_; \
+    } while (0)
+
+pfc_status pfc_fft_r2c(pfc_plan *p, const void *real_in, void *half_out, void *stream)
+{
+    PFC_CHECK(check_ready(p));
+    PFC_CHECK(check_ptr(real_in, "real_in"));
+    PFC_CHECK(check_ptr(half_out, "half_out"));
+    if (overlap(real_in, real_bytes(p), half_out, half_bytes(p)))
+        return fail(PFC_ERR_INVALID_ARG, "real_in and half_out overlap");
+    PFC_DISPATCH(p, do_r2c, p, real_in, half_out, (hipStream_t)stream);
+}
+
+pfc_status pfc_fft_c2r(pfc_plan *p, const void *half_in, void *real_out, void *stream)
+{
+    PFC_CHECK(check_ready(p));
+    PFC_CHECK(check_ptr(half_in, "half_in"));
+    PFC_CHECK(check_ptr(real_out, "real_out"));
+    if (overlap(half_in, half_bytes(p), real_out, real_bytes(p)))
+        return fail(PFC_ERR_INVALID_ARG, "half_in and real_out overlap");
+    PFC_DISPATCH(p, do_c2r, p, half_in, real_out, (hipStream_t)stream);
+}
+
+pfc_status pfc_state_init(pfc_plan *p, const void *psi0, void *state, void *stream)
+{
+    PFC_CHECK(check_ready(p));
+    PFC_CHECK(check_ptr(psi0, "psi0"));
+    PFC_CHECK(check_ptr(state, "state"));
+    if (overlap(psi0, real_bytes(p), state, state_bytes(p))) return fail(PFC_ERR_INVALID_ARG, "psi0 and state overlap");
+    PFC_DISPATCH(p, do_state_init, p, psi0, state, (hipStream_t)stream);
+}
+
+pfc_status pfc_state_export(pfc_plan *p, const void *state, void *half_natural, void *stream)
+{
+    PFC_CHECK(check_ready(p));
+    PFC_CHECK(check_ptr(state, "state"));
+    PFC_CHECK(check_ptr(half_natural, "half_natural"));
+    if (overlap(state, state_bytes(p), half_natural, half_bytes(p)))
+        return fail(PFC_ERR_INVALID_ARG, "state and half_natural overlap");
+    PFC_DISPATCH(p, do_export, p, state, half_natural, (hipStream_t)stream);
+}
+
+pfc_status pfc_step(pfc_plan *p, void *psi, void *state, int64_t nsteps, void *stream)
+{
+    PFC_CHECK(check_ready(p));
+    PFC_CHECK(check_ptr(psi, "psi"));
+    PFC_CHECK(check_ptr(state, "state"));
+    if (nsteps < 0) return fail(PFC_ERR_INVALID_ARG, "nsteps < 0");
+    if (overlap(psi, real_bytes(p), state, state_bytes(p))) return fail(PFC_ERR_INVALID_ARG, "psi and state overlap");
+    PFC_DISPATCH(p, do_step, p, psi, state, nsteps, (hipStream_t)stream);
+}
+
+pfc_status pfc_step_backward(pfc_plan *p, const void *psi_n, const void *psi_np1, const void *lambda_np1,
+                             void *lambda_n, double *dLdr_accum_dev, void *stream)
+{
+    PFC_CHECK(check_ready(p));
+    PFC_CHECK(check_ptr(psi_n, "psi_n"));
+    PFC_CHECK(check_ptr(psi_np1, "psi_np1"));
+    PFC_CHECK(check_ptr(lambda_np1, "lambda_np1"));
+    PFC_CHECK(check_ptr(lambda_n, "lambda_n"));
+    if (!dLdr_accum_dev) return fail(PFC_ERR_INVALID_ARG, "dLdr_accum_dev is NULL");
+    const size_t rb = real_bytes(p);
+    if (overlap(lambda_n, rb, psi_n, rb) || overlap(lambda_n, rb, psi_np1, rb))
+        return fail(PFC_ERR_INVALID_ARG, "lambda_n overlaps psi_n or psi_np1");
+    if (lambda_n != lambda_np1 && overlap(lambda_n, rb, lambda_np1, rb))
+        return fail(PFC_ERR_INVALID_ARG, "lambda_n partially overlaps lambda_np1");
+    PFC_DISPATCH(p, do_backward, p, psi_n, psi_np1, lambda_np1, lambda_n, dLdr_accum_dev, (hipStream_t)stream);
+}
+
+pfc_status pfc_energy(pfc_plan *p, const void *psi, const void *state, double *out_dev, void *stream)
+{
+    PFC_CHECK(check_ready(p));
+    PFC_CHECK(check_ptr(psi, "psi"));
+    PFC_CHECK(check_ptr(state, "state"));
+    if (!out_dev) return fail(PFC_ERR_INVALID_ARG, "out_dev is NULL");
+    PFC_DISPATCH(p, do_energy, p, psi, state, out_dev, (hipStream_t)stream);
+}
+
+const char *pfc_status_string(pfc_status st)
+{
+    switch (st) {
+    case PFC_OK: return "PFC_OK";
+    case PFC_ERR_INVALID_ARG: return "PFC_ERR_INVALID_ARG";
+    case PFC_ERR_UNSUPPORTED: return "PFC_ERR_UNSUPPORTED";
+    case PFC_ERR_ALIGNMENT: return "PFC_ERR_ALIGNMENT";
+    case PFC_ERR_WORKSPACE: return "PFC_ERR_WORKSPACE";
+    case PFC_ERR_HIP: return "PFC_ERR_HIP";
+    case PFC_ERR_DIVERGED: return "PFC_ERR_DIVERGED";
+    case PFC_ERR_INTERNAL: return "PFC_ERR_INTERNAL";
+    }
+    return "unknown pfc_status";
+}
+
+const char *pfc_last_error(void) { return g_last_error.c_str(); }
+
+}  // extern "C"

@@ -1,0 +1,119 @@
+"""C-ABI checks that need no GPU: the library loads, exports every declared entry point, and
+validates plans on the host (no kernel is launched by anything here)."""
+import ctypes
+import math
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "pfc.h")
+
+
+def _lib():
+    from paper_2603_26818_amd import _binding
+
+    if not os.path.exists(_binding.library_path()):
+        pytest.skip("libpfc.so not built")
+    return _binding, _binding.load_library()
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(pfc_[a-z0-9_]+)\s*\(", text)))
+
+
+def test_header_declares_the_entry_points():
+    names = declared_functions()
+    for n in ("pfc_plan_create", "pfc_fft_r2c", "pfc_fft_c2r", "pfc_step", "pfc_step_backward", "pfc_energy"):
+        assert n in names
+
+
+def test_every_declared_symbol_is_exported():
+    _, lib = _lib()
+    missing = [n for n in declared_functions() if not hasattr(lib, n)]
+    assert not missing, missing
+
+
+def test_binding_signatures_cover_the_header():
+    b, _ = _lib()
+    assert set(declared_functions()) <= set(b._SIGS)
+
+
+def _desc(b, shape=(64, 64), dtype=0, model=0, r=-0.25, dt=0.5, dx=math.pi / 4, flags=0):
+    d = b.PlanDesc()
+    d.ndim = len(shape)
+    for a in range(3):
+        d.n[a] = shape[a] if a < len(shape) else 1
+        d.dx[a] = dx if a < len(shape) else 1.0
+    d.dtype, d.model, d.r, d.dt, d.q1sq, d.R1, d.device, d.flags = dtype, model, r, dt, 2.0, 0.05, 0, flags
+    return d
+
+
+def _create(b, lib, d):
+    h = ctypes.c_void_p()
+    st = lib.pfc_plan_create(ctypes.byref(h), ctypes.byref(d))
+    return st, h
+
+
+def test_struct_layout_matches_c():
+    b, _ = _lib()
+    assert ctypes.sizeof(b.PlanDesc) == 104
+    assert b.PlanDesc.n.offset == 8 and b.PlanDesc.dx.offset == 32 and b.PlanDesc.r.offset == 64
+    assert b.PlanDesc.device.offset == 96 and b.PlanDesc.flags.offset == 100
+
+
+@pytest.mark.parametrize("shape,dtype", [((64, 64), 0), ((8, 16, 32), 1), ((2048, 2048, 2048), 0), ((4, 4), 1)])
+def test_plan_create_and_sizes(shape, dtype):
+    b, lib = _lib()
+    st, h = _create(b, lib, _desc(b, shape, dtype))
+    assert st == 0, lib.pfc_last_error()
+    npts = math.prod(shape)
+    cs = 16 if dtype == 1 else 8
+    assert lib.pfc_plan_real_bytes(h) == npts * cs // 2
+    assert lib.pfc_plan_state_bytes(h) == npts // 2 * cs  # packed: same bytes as the real field
+    assert lib.pfc_plan_half_bytes(h) == npts // shape[-1] * (shape[-1] // 2 + 1) * cs
+    ws = lib.pfc_plan_workspace_bytes(h)
+    assert ws >= lib.pfc_plan_state_bytes(h) and ws < lib.pfc_plan_state_bytes(h) + (64 << 20)
+    assert lib.pfc_plan_destroy(h) == 0
+
+
+@pytest.mark.parametrize("shape,code", [((64,), 2), ((4, 4, 4, 4), 2), ((48, 64), 2), ((64, 4096), 2), ((2, 64), 2)])
+def test_plan_rejects_unsupported_shapes(shape, code):
+    b, lib = _lib()
+    d = _desc(b, shape[:3])
+    d.ndim = len(shape)
+    st, h = _create(b, lib, d)
+    assert st == code and not h.value
+    assert lib.pfc_last_error()
+
+
+def test_plan_rejects_bad_parameters():
+    b, lib = _lib()
+    assert _create(b, lib, _desc(b, dt=0.0))[0] == 1
+    assert _create(b, lib, _desc(b, dt=float("nan")))[0] == 1
+    assert _create(b, lib, _desc(b, dx=0.0))[0] == 1
+    assert _create(b, lib, _desc(b, model=7))[0] == 1
+    assert _create(b, lib, _desc(b, flags=0x80))[0] == 1
+    # r = -1.5: r + L(q) < 0 near q = 1, and dt = 5 makes 1 + dt q (r + L) negative there
+    assert _create(b, lib, _desc(b, r=-1.5, dt=5.0))[0] == 1
+    assert _create(b, lib, _desc(b, r=-1.5, dt=0.1))[0] == 0
+
+
+def test_calls_without_workspace_fail_cleanly():
+    b, lib = _lib()
+    st, h = _create(b, lib, _desc(b))
+    assert st == 0
+    assert lib.pfc_step(h, None, None, 1, None) == 4  # PFC_ERR_WORKSPACE, before any device call
+    assert lib.pfc_plan_set_workspace(h, ctypes.c_void_p(256), 16) == 4  # too small
+    assert lib.pfc_plan_set_workspace(h, ctypes.c_void_p(100), 1 << 40) == 3  # misaligned
+    lib.pfc_plan_destroy(h)
+
+
+def test_status_strings():
+    _, lib = _lib()
+    for code, name in enumerate(["PFC_OK", "PFC_ERR_INVALID_ARG", "PFC_ERR_UNSUPPORTED", "PFC_ERR_ALIGNMENT",
+                                 "PFC_ERR_WORKSPACE", "PFC_ERR_HIP", "PFC_ERR_DIVERGED", "PFC_ERR_INTERNAL"]):
+        assert lib.pfc_status_string(code).decode() == name
