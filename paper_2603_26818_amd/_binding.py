@@ -72,13 +72,21 @@ _SIGS = {
 
 
 def load_library():
-    """Load libpfc.so (raises if it has not been built)."""
+    """Load libpfc.so (raises if it has not been built).
+
+    torch is imported first when it is installed: its wheel carries its own HIP runtime with the
+    same soname as the system one, so loading it first makes libpfc.so bind to that runtime and the
+    process holds a single HIP runtime (device memory and streams from torch are then valid here)."""
     global _lib
     if _lib is not None:
         return _lib
     path = library_path()
     if not os.path.exists(path):
         raise ImportError(f"{path} is not built; run __graft_entry__.build() (make -C paper_2603_26818_amd/csrc)")
+    try:
+        import torch  # noqa: F401
+    except ImportError:
+        pass
     lib = ctypes.CDLL(path)
     for name, (res, args) in _SIGS.items():
         f = getattr(lib, name)

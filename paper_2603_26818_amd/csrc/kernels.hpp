@@ -396,8 +396,6 @@ __global__ __launch_bounds__(WMAX *PL::Tp) void last_axis_kernel(LastAxisArgs<T>
             __syncthreads();
         }
         auto partner_val = [&](int e) -> cx<T> { return sh[((L - e) & (L - 1)) * WMAX + si.partner]; };
-        const int64_t prow_off =
-            (si.partner >= 0) ? la_slot(nrows, a.tiles_per_row, W, si.partner).row * M : 0;  // partner's kx = 0
 
         if constexpr (MODE == LA_R2C_NATURAL) {
             const int64_t pitch = M + 1;
@@ -421,43 +419,68 @@ __global__ __launch_bounds__(WMAX *PL::Tp) void last_axis_kernel(LastAxisArgs<T>
             }
             return;
         } else if constexpr (MODE == LA_STEP) {
-            const T dt = mp.dt, nl = mp.nl;
+            // Semi-implicit update.  Pencils off the folded column: S <- (S - dt q N) A(q).  Folded
+            // column: the two planes X0 (q0) and XN (qN) are separated with the mirror element -k,
+            // which another thread owns; the mirror's N comes from LDS now, its S in a second LDS
+            // round, so no thread reads a state value that another thread has already updated.
+            const T dt = mp.dt, nl = mp.nl, h = T(0.5);
 #pragma unroll
             for (int b = 0; b < Rmax / Rl; ++b)
 #pragma unroll
                 for (int r = 0; r < Rl; ++r) {
                     const int e = t + b * Tp + r * (L / Rl);
                     const T kz = mp.fk[0] * (T)signed_index(e, L);
-                    const int64_t gi = (int64_t)e * estride + coloff;
-                    cx<T> N = v[b * Rl + r];
-                    N = {N.x * nl, N.y * nl};
-                    cx<T> S = valid ? a.state[gi] : cx<T>{T(0), T(0)};
-                    cx<T> Snew;
+                    const cx<T> N = {v[b * Rl + r].x * nl, v[b * Rl + r].y * nl};
                     if (si.partner < 0) {
+                        const int64_t gi = (int64_t)e * estride + coloff;
+                        const cx<T> S = valid ? a.state[gi] : cx<T>{T(0), T(0)};
                         const T q = kz * kz + ky * ky + kx * kx;
                         const T A = amult(mp, q), dq = dt * q;
-                        Snew = {(S.x - dq * N.x) * A, (S.y - dq * N.y) * A};
+                        const cx<T> Snew = {(S.x - dq * N.x) * A, (S.y - dq * N.y) * A};
+                        if (valid) a.state[gi] = Snew;
+                        v[b * Rl + r] = Snew;
                     } else {
-                        const int ep = (L - e) & (L - 1);
-                        cx<T> Np = partner_val(e);
-                        Np = {Np.x * nl, Np.y * nl};
-                        const cx<T> Sp = valid ? a.state[(int64_t)ep * estride + prow_off] : cx<T>{T(0), T(0)};
-                        const T h = T(0.5);
-                        // the two Hermitian planes of state and cube spectrum
-                        const cx<T> S0 = {(S.x + Sp.x) * h, (S.y - Sp.y) * h};
-                        const cx<T> SN = {(S.y + Sp.y) * h, (Sp.x - S.x) * h};
+                        const cx<T> Np = {partner_val(e).x * nl, partner_val(e).y * nl};
                         const cx<T> N0 = {(N.x + Np.x) * h, (N.y - Np.y) * h};
                         const cx<T> NN = {(N.y + Np.y) * h, (Np.x - N.x) * h};
                         const T q0 = kz * kz + ky * ky, qn = q0 + kxn * kxn;
-                        const T A0 = amult(mp, q0), AN = amult(mp, qn);
-                        const T d0 = dt * q0, dn = dt * qn;
-                        const cx<T> U0 = {(S0.x - d0 * N0.x) * A0, (S0.y - d0 * N0.y) * A0};
-                        const cx<T> UN = {(SN.x - dn * NN.x) * AN, (SN.y - dn * NN.y) * AN};
-                        Snew = {U0.x - UN.y, U0.y + UN.x};  // U0 + i UN
+                        const T g0 = dt * q0 * amult(mp, q0), gn = dt * qn * amult(mp, qn);
+                        // G = -(g0 N0 + i gn NN): the cubic term's share of the new value
+                        v[b * Rl + r] = {-g0 * N0.x + gn * NN.y, -g0 * N0.y - gn * NN.x};
                     }
-                    if (valid) a.state[gi] = Snew;
-                    v[b * Rl + r] = Snew;
                 }
+            if (si.has_pairs) {  // uniform per workgroup
+                __syncthreads();  // every mirror N has been read
+#pragma unroll
+                for (int b = 0; b < Rmax / Rl; ++b)
+#pragma unroll
+                    for (int r = 0; r < Rl; ++r) {
+                        const int e = t + b * Tp + r * (L / Rl);
+                        if (si.partner >= 0 && valid) lds(e) = a.state[(int64_t)e * estride + coloff];
+                    }
+                __syncthreads();
+                if (si.partner >= 0) {
+#pragma unroll
+                    for (int b = 0; b < Rmax / Rl; ++b)
+#pragma unroll
+                        for (int r = 0; r < Rl; ++r) {
+                            const int e = t + b * Tp + r * (L / Rl);
+                            const T kz = mp.fk[0] * (T)signed_index(e, L);
+                            const int64_t gi = (int64_t)e * estride + coloff;
+                            const cx<T> S = valid ? a.state[gi] : cx<T>{T(0), T(0)};
+                            const cx<T> Sp = partner_val(e);
+                            const cx<T> S0 = {(S.x + Sp.x) * h, (S.y - Sp.y) * h};
+                            const cx<T> SN = {(S.y + Sp.y) * h, (Sp.x - S.x) * h};
+                            const T q0 = kz * kz + ky * ky, qn = q0 + kxn * kxn;
+                            const T A0 = amult(mp, q0), AN = amult(mp, qn);
+                            const cx<T> G = v[b * Rl + r];
+                            // A0 S0 + i AN SN + G
+                            const cx<T> Snew = {A0 * S0.x - AN * SN.y + G.x, A0 * S0.y + AN * SN.x + G.y};
+                            if (valid) a.state[gi] = Snew;
+                            v[b * Rl + r] = Snew;
+                        }
+                }
+            }
             fft_stages<T, PR, +1>(v, t, lds, a.tw, a.lt_shift);
             if (valid) {
                 constexpr int Rf = PR::last;
