@@ -1,0 +1,185 @@
+#!/usr/bin/env python3
+"""Benchmark of the PFC hot path on one MI355X.
+
+Workload: 3D one-mode PFC on a 512^3 periodic grid in FP32 (dx = pi/4, r = -0.30, dt = 0.5,
+psi0 = -0.30 + U(-0.1, 0.1) from SplitMix64 seed 23), the configuration the headline metric is
+quoted on.  One step = x r2c (cube prologue) -> y forward -> z forward + semi-implicit update + z
+inverse -> y inverse -> x c2r (1/N epilogue), five kernels through the C ABI.
+
+Prints ONE JSON line on stdout: steps/s of the whole step (inputs resident in HBM), the roofline
+of the dominant kernel (algorithmic bytes / its average duration, from HIP events on the stream
+the kernels run on), the 3D r2c / c2r GB/s, and the FP64 CPU oracle timed on this host.
+"""
+import argparse
+import hashlib
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "PFC steps/s at 512^3 FP32 + 3D r2c/c2r FFT HBM GB/s (% of peak)"
+PEAK_HBM_GBPS = 8000.0  # MI355X HBM3E
+N = 512
+R, DT, SEED = -0.30, 0.5, 23
+PASS_NAMES = ["x_r2c_cube", "y_fwd", "z_fused_update", "y_inv", "x_c2r"]
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_512cube_f32.json")
+KERNEL_SOURCES = ["fft_core.hpp", "kernels.hpp", "dispatch_impl.hpp", "types.hpp"]
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def kernel_hash():
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, "paper_2603_26818_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(kernel):
+    """HBM bytes per launch of `kernel` from the committed rocprofv3 counter summary, or None when
+    the kernel sources changed since the counters were taken."""
+    try:
+        with open(TRAFFIC_FILE) as f:
+            t = json.load(f)
+    except (OSError, ValueError):
+        return None
+    if t.get("kernel_hash") != kernel_hash() or kernel not in t.get("kernels", {}):
+        return None
+    return t["kernels"][kernel].get("hbm_bytes_per_launch")
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=300)
+    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--profile-steps", type=int, default=30, help="steps of the per-pass timed run")
+    ap.add_argument("--fft-reps", type=int, default=20)
+    ap.add_argument("--cpu-steps", type=int, default=3, help="oracle steps of the CPU baseline (0: skip)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py runs on one GPU only: this build has no multi-GPU path (see DESIGN.md for how the "
+              "step would shard).", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    import paper_2603_26818_amd as pfc
+    import pfc_inputs
+
+    shape = (N, N, N)
+    dev = torch.device("cuda", 0)
+    torch.cuda.set_device(dev)
+    plan = pfc.Plan(shape, dtype="f32", r=R, dt=DT, device=0)
+    log(f"[bench] drawing psi0 {shape} seed {SEED}")
+    psi = pfc_inputs.pfc_initial_field_torch(SEED, shape, R, torch.float32, dev)
+    state = plan.state_init(psi)
+    stream = torch.cuda.current_stream(dev)
+
+    log(f"[bench] warmup {args.warmup} steps")
+    plan.step(psi, state, args.warmup)
+    torch.cuda.synchronize()
+
+    log(f"[bench] timed {args.steps} steps")
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    e0.record(stream)
+    plan.step(psi, state, args.steps)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ms_per_step = e0.elapsed_time(e1) / args.steps
+    steps_per_s = 1000.0 / ms_per_step
+    log(f"[bench] {ms_per_step:.4f} ms/step ({steps_per_s:.1f} steps/s), wall {wall:.3f} s")
+
+    F = plan.energy(psi, state).cpu().tolist()
+    if not all(math.isfinite(v) for v in F):
+        log(f"[bench] non-finite energy {F}")
+        sys.exit(1)
+
+    # per-pass durations, HIP events on the same stream, in a separate run of profile-steps steps
+    log(f"[bench] per-pass timing over {args.profile_steps} steps")
+    pass_ms = plan.step_timed(psi, state, args.profile_steps)
+    Rb = N**3 * 4  # real field, FP32
+    Cb = N**3 // 2 * 8  # packed spectrum (same bytes as the real field)
+    alg = [Rb + Cb, 2 * Cb, 4 * Cb, 2 * Cb, Cb + Rb]  # algorithmic HBM bytes per launch
+    passes = []
+    for name, tot, b in zip(PASS_NAMES, pass_ms, alg):
+        avg = tot / args.profile_steps
+        passes.append({"kernel": name, "avg_ms": round(avg, 5), "alg_bytes": b, "alg_gbps": round(b / avg / 1e6, 1),
+                       "frac": round(b / avg / 1e6 / PEAK_HBM_GBPS, 4)})
+    dom = max(passes, key=lambda p: p["avg_ms"])
+    step_bytes = sum(alg)
+    roofline = {"bound": "hbm", "kernel": dom["kernel"], "achieved": dom["alg_gbps"], "peak": PEAK_HBM_GBPS,
+                "unit": "GB/s", "frac": dom["frac"], "traffic": measured_traffic(dom["kernel"]),
+                "alg_bytes_per_launch": dom["alg_bytes"], "avg_ms": dom["avg_ms"]}
+
+    # standalone 3D r2c / c2r at 512^3 FP32 on seeded N(0,1) (seed 22), natural half spectrum
+    log(f"[bench] r2c / c2r {args.fft_reps} reps each")
+    x = pfc_inputs.normal_torch(22, shape, torch.float32, dev)
+    X = plan.fft_r2c(x)
+    y = plan.fft_c2r(X)
+    torch.cuda.synchronize()
+
+    def timed(fn):
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record(stream)
+        for _ in range(args.fft_reps):
+            fn()
+        b.record(stream)
+        torch.cuda.synchronize()
+        return a.elapsed_time(b) / args.fft_reps
+
+    t_r2c = timed(lambda: plan.fft_r2c(x, X))
+    t_c2r = timed(lambda: plan.fft_c2r(X, y))
+    rt_err = (torch.linalg.vector_norm((y - x).double()) / torch.linalg.vector_norm(x.double())).item()
+    Cn = N * N * (N // 2 + 1) * 8  # natural half spectrum
+    fft_bytes = Rb + 5 * Cn  # three passes: x (Rb + C), y (2C), z (2C)
+    fft = {"r2c_ms": round(t_r2c, 4), "c2r_ms": round(t_c2r, 4),
+           "r2c_gbps": round(fft_bytes / t_r2c / 1e6, 1), "c2r_gbps": round(fft_bytes / t_c2r / 1e6, 1),
+           "r2c_frac": round(fft_bytes / t_r2c / 1e6 / PEAK_HBM_GBPS, 4),
+           "c2r_frac": round(fft_bytes / t_c2r / 1e6 / PEAK_HBM_GBPS, 4),
+           "alg_bytes": fft_bytes, "roundtrip_rel_l2": rt_err}
+    del x, X, y
+
+    cpu = None
+    if args.cpu_steps > 0:
+        import oracle
+
+        log(f"[bench] CPU oracle: {args.cpu_steps} FP64 steps of the same 512^3 workload")
+        p = oracle.Params(shape, r=R, dt=DT)
+        psi0 = pfc_inputs.pfc_initial_field(SEED, shape, R).astype("float32").astype("float64")
+        s0 = oracle.state_init(p, psi0)
+        t0 = time.perf_counter()
+        oracle.step(p, psi0, s0, args.cpu_steps)
+        dt_cpu = time.perf_counter() - t0
+        cpu = {"value": round(args.cpu_steps / dt_cpu, 4), "unit": "steps/s", "cores": oracle.num_threads(),
+               "kind": "oracle",
+               "sample": f"{args.cpu_steps} steps of the 512^3 workload by the FP64 C oracle "
+                         f"(recursive radix-2 FFT, OpenMP), {dt_cpu:.1f} s"}
+        log(f"[bench] CPU oracle {cpu['value']} steps/s on {cpu['cores']} threads")
+
+    out = {
+        "metric": METRIC, "value": round(steps_per_s, 2), "unit": "steps/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": round(ms_per_step, 5), "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "3D one-mode PFC step, 512^3 periodic grid, FP32, dx=pi/4, r=-0.30, dt=0.5, "
+                               "psi0=-0.30+U(-0.1,0.1) SplitMix64 seed 23", "grid": list(shape)},
+        "roofline": roofline, "cpu_baseline": cpu, "fft": fft, "passes": passes,
+        "step_alg_gbps": round(step_bytes / ms_per_step / 1e6, 1),
+        "step_frac": round(step_bytes / ms_per_step / 1e6 / PEAK_HBM_GBPS, 4),
+        "energy_after": F[0],
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -116,6 +116,14 @@ pfc_status pfc_state_export(pfc_plan *p, const void *state, void *half_natural, 
  * one the cube is taken of; the state is the one the update is applied to. */
 pfc_status pfc_step(pfc_plan *p, void *psi, void *state, int64_t nsteps, void *stream);
 
+/* pfc_step with a HIP event recorded on `stream` around every kernel of every step, for
+ * measurement.  pass_ms[i] receives the summed duration (ms) of pass i over all steps and *npasses
+ * the number of passes per step: 3D 5 (x r2c with cube, y forward, z forward + update + z inverse,
+ * y inverse, x c2r), 2D 3 (x r2c with cube, y forward + update + y inverse, x c2r).  pass_ms must
+ * hold 5 doubles.  Synchronises the stream after each step; results equal those of pfc_step. */
+pfc_status pfc_step_timed(pfc_plan *p, void *psi, void *state, int64_t nsteps, void *stream, double *pass_ms,
+                          int *npasses);
+
 /* Transpose of the Jacobian of one step, applied to lambda_np1 (the adjoint of psi^{n+1}):
  *     lambda_n = S_A lambda - 3 dt (psi_n)^2 .* S_K S_A lambda,
  * where S_A and S_K are the real symmetric Fourier multipliers A = 1/(1 + dt q (r + L(q))) and q.

@@ -27,4 +27,5 @@ from ._binding import (  # noqa: F401
     pfc_state_init,
     pfc_step,
     pfc_step_backward,
+    pfc_step_timed,
 )

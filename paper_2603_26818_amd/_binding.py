@@ -64,6 +64,8 @@ _SIGS = {
     "pfc_state_init": (ctypes.c_int, [ctypes.c_void_p] * 4),
     "pfc_state_export": (ctypes.c_int, [ctypes.c_void_p] * 4),
     "pfc_step": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p]),
+    "pfc_step_timed": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64,
+                                      ctypes.c_void_p, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int)]),
     "pfc_step_backward": (ctypes.c_int, [ctypes.c_void_p] * 7),
     "pfc_energy": (ctypes.c_int, [ctypes.c_void_p] * 5),
     "pfc_status_string": (ctypes.c_char_p, [ctypes.c_int]),
@@ -208,6 +210,16 @@ class Plan:
                                   int(nsteps), _stream_ptr(self.device)), "pfc_step")
         return psi, state
 
+    def step_timed(self, psi, state, nsteps=1):
+        """pfc_step_timed: returns the summed milliseconds of each pass (list)."""
+        ms = (ctypes.c_double * 5)()
+        npass = ctypes.c_int(0)
+        _check(self._lib.pfc_step_timed(self._h, self._tensor(psi, self.shape, self.real_dtype, "psi"),
+                                        self._tensor(state, self.state_shape, self.complex_dtype, "state"),
+                                        int(nsteps), _stream_ptr(self.device), ms, ctypes.byref(npass)),
+               "pfc_step_timed")
+        return [ms[i] for i in range(npass.value)]
+
     def step_backward(self, psi_n, psi_np1, lambda_np1, lambda_n=None, dLdr=None):
         torch = _torch()
         lambda_n = self.empty_real() if lambda_n is None else lambda_n
@@ -279,6 +291,10 @@ def pfc_state_export(plan: Plan, state, half_natural=None):
 
 def pfc_step(plan: Plan, psi, state, nsteps=1):
     return plan.step(psi, state, nsteps)
+
+
+def pfc_step_timed(plan: Plan, psi, state, nsteps=1):
+    return plan.step_timed(psi, state, nsteps)
 
 
 def pfc_step_backward(plan: Plan, psi_n, psi_np1, lambda_np1, lambda_n=None, dLdr=None):

@@ -265,20 +265,75 @@ pfc_status do_state_init(pfc_plan *p, const void *psi0, void *state, hipStream_t
     return PFC_OK;
 }
 
+// One pass of a step.  3D: 0 x r2c + cube, 1 y forward, 2 z fused update, 3 y inverse, 4 x c2r.
+// 2D: 0 x r2c + cube, 1 y fused update, 2 x c2r.
+int step_passes(const pfc_plan *p) { return p->g.ndim == 3 ? 5 : 3; }
+
+template <typename T>
+pfc_status step_pass(const pfc_plan *p, int pass, void *psi, void *state, hipStream_t s)
+{
+    const Geom &g = p->g;
+    const Bufs<T> b = bufs<T>(p);
+    const int id = (g.ndim == 3) ? pass : (pass == 0 ? 0 : pass == 1 ? 2 : 4);
+    switch (id) {
+    case 0: PFC_TRY(pfc::launch_x_r2c<T>(g, (const T *)psi, b.scratch, true, b.tw, s), "x_r2c launch"); break;
+    case 1: PFC_TRY(pfc::launch_y_c2c<T>(g, b.scratch, -1, b.tw, s), "y forward launch"); break;
+    case 2: {
+        const pfc::ModelParams<T> mp = model_params<T>(p);
+        PFC_TRY(pfc::launch_last<T>(g, pfc::LAST_STEP, b.scratch, b.scratch, nullptr, (cx<T> *)state, mp, b.tw, s),
+                "last-axis step launch");
+        break;
+    }
+    case 3: PFC_TRY(pfc::launch_y_c2c<T>(g, b.scratch, +1, b.tw, s), "y inverse launch"); break;
+    case 4: PFC_TRY(pfc::launch_x_c2r<T>(g, b.scratch, (T *)psi, b.tw, s), "x_c2r launch"); break;
+    default: return fail(PFC_ERR_INTERNAL, "bad pass %d", pass);
+    }
+    return PFC_OK;
+}
+
 template <typename T>
 pfc_status do_step(pfc_plan *p, void *psi, void *state, int64_t nsteps, hipStream_t s)
 {
-    const Bufs<T> b = bufs<T>(p);
-    const pfc::ModelParams<T> mp = model_params<T>(p);
-    for (int64_t n = 0; n < nsteps; ++n) {
-        pfc_status st = fwd_xy<T>(p, (const T *)psi, true, b.scratch, s);
-        if (st) return st;
-        PFC_TRY(pfc::launch_last<T>(p->g, pfc::LAST_STEP, b.scratch, b.scratch, nullptr, (cx<T> *)state, mp, b.tw, s),
-                "last-axis step launch");
-        st = inv_yx<T>(p, b.scratch, (T *)psi, s);
-        if (st) return st;
-    }
+    const int np = step_passes(p);
+    for (int64_t n = 0; n < nsteps; ++n)
+        for (int k = 0; k < np; ++k) {
+            pfc_status st = step_pass<T>(p, k, psi, state, s);
+            if (st) return st;
+        }
     return PFC_OK;
+}
+
+template <typename T>
+pfc_status do_step_timed(pfc_plan *p, void *psi, void *state, int64_t nsteps, hipStream_t s, double *pass_ms)
+{
+    const int np = step_passes(p);
+    hipEvent_t ev[6];
+    int made = 0;
+    pfc_status st = PFC_OK;
+    for (; made < np + 1; ++made) {
+        hipError_t e = hipEventCreate(&ev[made]);
+        if (e != hipSuccess) {
+            st = hip_fail(e, "hipEventCreate");
+            break;
+        }
+    }
+    for (int k = 0; k < np; ++k) pass_ms[k] = 0.0;
+    for (int64_t n = 0; n < nsteps && st == PFC_OK; ++n) {
+        hipError_t e = hipEventRecord(ev[0], s);
+        for (int k = 0; k < np && e == hipSuccess && st == PFC_OK; ++k) {
+            st = step_pass<T>(p, k, psi, state, s);
+            if (st == PFC_OK) e = hipEventRecord(ev[k + 1], s);
+        }
+        if (st == PFC_OK && e == hipSuccess) e = hipEventSynchronize(ev[np]);
+        for (int k = 0; k < np && st == PFC_OK && e == hipSuccess; ++k) {
+            float ms = 0.f;
+            e = hipEventElapsedTime(&ms, ev[k], ev[k + 1]);
+            pass_ms[k] += ms;
+        }
+        if (st == PFC_OK && e != hipSuccess) st = hip_fail(e, "timing events");
+    }
+    for (int k = 0; k < made; ++k) (void)hipEventDestroy(ev[k]);
+    return st;
 }
 
 template <typename T>
@@ -492,6 +547,19 @@ pfc_status pfc_step(pfc_plan *p, void *psi, void *state, int64_t nsteps, void *s
     if (nsteps < 0) return fail(PFC_ERR_INVALID_ARG, "nsteps < 0");
     if (overlap(psi, real_bytes(p), state, state_bytes(p))) return fail(PFC_ERR_INVALID_ARG, "psi and state overlap");
     PFC_DISPATCH(p, do_step, p, psi, state, nsteps, (hipStream_t)stream);
+}
+
+pfc_status pfc_step_timed(pfc_plan *p, void *psi, void *state, int64_t nsteps, void *stream, double *pass_ms,
+                          int *npasses)
+{
+    PFC_CHECK(check_ready(p));
+    PFC_CHECK(check_ptr(psi, "psi"));
+    PFC_CHECK(check_ptr(state, "state"));
+    if (!pass_ms || !npasses) return fail(PFC_ERR_INVALID_ARG, "pass_ms or npasses is NULL");
+    if (nsteps < 0) return fail(PFC_ERR_INVALID_ARG, "nsteps < 0");
+    if (overlap(psi, real_bytes(p), state, state_bytes(p))) return fail(PFC_ERR_INVALID_ARG, "psi and state overlap");
+    *npasses = step_passes(p);
+    PFC_DISPATCH(p, do_step_timed, p, psi, state, nsteps, (hipStream_t)stream, pass_ms);
 }
 
 pfc_status pfc_step_backward(pfc_plan *p, const void *psi_n, const void *psi_np1, const void *lambda_np1,
