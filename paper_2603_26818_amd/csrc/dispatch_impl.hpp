@@ -45,8 +45,8 @@ hipError_t launch_x_r2c(const Geom &g, const T *in, cx<T> *out, bool cube, const
         if constexpr (M > 1024) {
             return hipErrorInvalidValue;
         } else {
-            using PL = typename DefaultPlan<M>::type;
-            constexpr int ROWS = XRows<M>::value;
+            using PL = typename XFwdPlan<M>::type;
+            constexpr int ROWS = XRows<PL>::value;
             const dim3 grid((unsigned)cdiv(g.xrows, ROWS)), block(ROWS * PL::Tp);
             if (cube)
                 hipLaunchKernelGGL((x_r2c_kernel<T, PL, ROWS, true>), grid, block, 0, s, in, out, g.xrows, tw, g.lt_shift);
@@ -65,8 +65,8 @@ hipError_t launch_x_c2r(const Geom &g, const cx<T> *in, T *out, const cx<T> *tw,
         if constexpr (M > 1024) {
             return hipErrorInvalidValue;
         } else {
-            using PL = typename DefaultPlan<M>::type;
-            constexpr int ROWS = XRows<M>::value;
+            using PL = typename XInvPlan<M>::type;
+            constexpr int ROWS = XRows<PL>::value;
             const dim3 grid((unsigned)cdiv(g.xrows, ROWS)), block(ROWS * PL::Tp);
             const T sc = (T)(1.0 / ((double)g.M * (double)g.n0 * (double)g.nrows));
             AdjEpi<T> ea{};
@@ -86,8 +86,8 @@ hipError_t launch_x_c2r_adjoint(const Geom &g, const cx<T> *mu, const cx<T> *nu,
         if constexpr (M > 1024) {
             return hipErrorInvalidValue;
         } else {
-            using PL = typename DefaultPlan<M>::type;
-            constexpr int ROWS = XRows<M>::value;
+            using PL = typename XInvPlan<M>::type;
+            constexpr int ROWS = XRows<PL>::value;
             const int64_t nb = cdiv(g.xrows, ROWS);
             *nblocks = nb;
             const dim3 grid((unsigned)nb), block(ROWS * PL::Tp);
@@ -108,7 +108,7 @@ hipError_t launch_y_c2c(const Geom &g, cx<T> *data, int dir, const cx<T> *tw, hi
         if constexpr (L < 4) {
             return hipErrorInvalidValue;
         } else {
-            using PL = typename DefaultPlan<L>::type;
+            using PL = typename AxisPlan<L>::type;
             constexpr int WM = WMax<T, L>::value;
             const int W = (int)(g.M < WM ? g.M : WM);
             const int64_t tiles = cdiv(g.M, W);
@@ -132,7 +132,7 @@ hipError_t launch_last_fwd(const Geom &g, const cx<T> *src, cx<T> *dst, const cx
         if constexpr (L < 4) {
             return hipErrorInvalidValue;
         } else {
-            using PL = typename DefaultPlan<L>::type;
+            using PL = typename AxisPlan<L>::type;
             constexpr int WM = WMax<T, L>::value;
             const int64_t ncols = g.nrows * g.M;
             const int W = (int)(ncols < WM ? ncols : WM);
@@ -154,7 +154,7 @@ hipError_t launch_last(const Geom &g, int mode, const cx<T> *src, cx<T> *dst, cx
         if constexpr (L < 4) {
             return hipErrorInvalidValue;
         } else {
-            using PL = typename DefaultPlan<L>::type;
+            using PL = typename LastPlan<L>::type;
             constexpr int WM = WMax<T, L>::value;
             LastAxisArgs<T> a;
             a.src = src;

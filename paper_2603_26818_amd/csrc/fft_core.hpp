@@ -147,6 +147,16 @@ template <> struct DefaultPlan<512> { using type = Radices<8, 8, 8>; };
 template <> struct DefaultPlan<1024> { using type = Radices<8, 8, 16>; };
 template <> struct DefaultPlan<2048> { using type = Radices<8, 16, 16>; };
 
+// Schedules per pass kind (measured on MI355X at 512^3 FP32; other lengths use DefaultPlan until
+// tuned).  x forward (r2c, contiguous rows), x inverse (c2r), strided middle axis, last axis.
+template <int M> struct XFwdPlan { using type = typename DefaultPlan<M>::type; };
+template <int M> struct XInvPlan { using type = typename DefaultPlan<M>::type; };
+template <> struct XInvPlan<256> { using type = Radices<8, 4, 8>; };
+template <int L> struct AxisPlan { using type = typename DefaultPlan<L>::type; };
+template <> struct AxisPlan<512> { using type = Radices<16, 2, 16>; };
+template <int L> struct LastPlan { using type = typename DefaultPlan<L>::type; };
+template <> struct LastPlan<512> { using type = Radices<2, 16, 16>; };
+
 // Twiddle W_{Ns R}^{m}, m = (j mod Ns) r, from the table of length Lt (forward sign); conjugated
 // for the inverse.
 template <typename T, int DIR>

@@ -60,19 +60,29 @@ __device__ __forceinline__ double block_sum(double v, double *red)
 // z[m] = x[2m] + i x[2m+1] (cubed first when CUBE), Z = FFT_M(z), then for k = 1..M-1
 //   X(k) = E + W_{2M}^k O,  E = (Z(k) + conj Z(M-k)) / 2,  O = -i (Z(k) - conj Z(M-k)) / 2,
 // and slot 0 = (Re Z0 + Im Z0) + i (Re Z0 - Im Z0) = X(0) + i X(M).
-template <int M>
+// rows per workgroup of the x pass: about 256 threads
+template <class PL>
 struct XRows {
-    static constexpr int Tp = DefaultPlan<M>::type::Tp;
-    static constexpr int value = (256 / Tp) > 64 ? 64 : ((256 / Tp) < 1 ? 1 : 256 / Tp);
+    static constexpr int value = (256 / PL::Tp) > 64 ? 64 : ((256 / PL::Tp) < 1 ? 1 : 256 / PL::Tp);
 };
 
-template <typename T, class PL, int ROWS, bool CUBE>
+// LDS slot of element e in a row of the x pass: one spare slot after every 8 elements, so that the
+// Stockham stage writes (stride R between neighbouring threads) spread over the banks.
+__device__ __forceinline__ int xpad(int e) { return e + (e >> 3); }
+template <int M, bool PAD>
+struct XPitch {
+    static constexpr int value = PAD ? M + M / 8 + (M < 8 ? 1 : 0) : M;
+};
+template <bool PAD>
+__device__ __forceinline__ int xidx(int e) { return PAD ? xpad(e) : e; }
+
+template <typename T, class PL, int ROWS, bool CUBE, bool PAD = false>
 __global__ __launch_bounds__(ROWS *PL::Tp) void x_r2c_kernel(const T *__restrict__ in, cx<T> *__restrict__ out,
                                                               int64_t nrows, const cx<T> *__restrict__ tw,
                                                               int lt_shift)
 {
     constexpr int M = PL::L, Tp = PL::Tp, R0 = PL::first, Rl = PL::last, Rmax = PL::Rmax;
-    constexpr int LD = M;  // row pitch in LDS
+    constexpr int LD = XPitch<M, PAD>::value;  // row pitch in LDS
     __shared__ cx<T> sh[ROWS * LD];
     const int tid = threadIdx.x, p = tid / Tp, t = tid - p * Tp;
     const int64_t row = (int64_t)blockIdx.x * ROWS + p;
@@ -87,7 +97,7 @@ __global__ __launch_bounds__(ROWS *PL::Tp) void x_r2c_kernel(const T *__restrict
             if constexpr (CUBE) z = {z.x * z.x * z.x, z.y * z.y * z.y};
             v[b * R0 + r] = z;
         }
-    auto lds = [&](int e) -> cx<T> & { return sh[p * LD + e]; };
+    auto lds = [&](int e) -> cx<T> & { return sh[p * LD + xidx<PAD>(e)]; };
     fft_stages<T, PL, -1>(v, t, lds, tw, lt_shift);
     __syncthreads();
 #pragma unroll
@@ -137,7 +147,7 @@ struct AdjEpi {
     double *partial;
 };
 
-template <typename T, class PL, int ROWS>
+template <typename T, class PL, int ROWS, bool PAD>
 __device__ __forceinline__ void x_c2r_row(cx<T> *v, const cx<T> *src, bool valid, int t, cx<T> *rowlds,
                                           const cx<T> *__restrict__ tw, int lt_shift)
 {
@@ -150,7 +160,7 @@ __device__ __forceinline__ void x_c2r_row(cx<T> *v, const cx<T> *src, bool valid
         for (int r = 0; r < R0; ++r) {
             const int k = t + b * Tp + r * (M / R0);
             v[b * R0 + r] = valid ? src[k] : cx<T>{T(0), T(0)};
-            rowlds[k] = v[b * R0 + r];
+            rowlds[xidx<PAD>(k)] = v[b * R0 + r];
         }
     __syncthreads();
     const T h = T(0.5);
@@ -163,7 +173,7 @@ __device__ __forceinline__ void x_c2r_row(cx<T> *v, const cx<T> *src, bool valid
             if (k == 0) {
                 v[b * R0 + r] = {(a.x + a.y) * h, (a.x - a.y) * h};
             } else {
-                const cx<T> c = rowlds[M - k];  // X(M-k); conj taken below
+                const cx<T> c = rowlds[xidx<PAD>(M - k)];  // X(M-k); conj taken below
                 const cx<T> E = {(a.x + c.x) * h, (a.y - c.y) * h};
                 const cx<T> D = {(a.x - c.x) * h, (a.y + c.y) * h};
                 const cx<T> O = cmul(conj(tw[k << (lt_shift - tshift)]), D);
@@ -172,21 +182,21 @@ __device__ __forceinline__ void x_c2r_row(cx<T> *v, const cx<T> *src, bool valid
         }
 }
 
-template <typename T, class PL, int ROWS, int EPI>
+template <typename T, class PL, int ROWS, int EPI, bool PAD = false>
 __global__ __launch_bounds__(ROWS *PL::Tp) void x_c2r_kernel(const cx<T> *in, T *out, int64_t nrows,
                                                               const cx<T> *__restrict__ tw, int lt_shift, T sc,
                                                               AdjEpi<T> ea)
 {
     constexpr int M = PL::L, Tp = PL::Tp, Rl = PL::last, Rmax = PL::Rmax;
-    constexpr int LD = M;
+    constexpr int LD = XPitch<M, PAD>::value;
     __shared__ cx<T> sh[ROWS * LD];
     const int tid = threadIdx.x, p = tid / Tp, t = tid - p * Tp;
     const int64_t row = (int64_t)blockIdx.x * ROWS + p;
     const bool valid = row < nrows;
     const int64_t r0 = valid ? row : 0;
-    auto lds = [&](int e) -> cx<T> & { return sh[p * LD + e]; };
+    auto lds = [&](int e) -> cx<T> & { return sh[p * LD + xidx<PAD>(e)]; };
     cx<T> v[Rmax];
-    x_c2r_row<T, PL, ROWS>(v, in + r0 * M, valid, t, &sh[p * LD], tw, lt_shift);
+    x_c2r_row<T, PL, ROWS, PAD>(v, in + r0 * M, valid, t, &sh[p * LD], tw, lt_shift);
     fft_stages<T, PL, +1>(v, t, lds, tw, lt_shift);
     cx<T> *dst = reinterpret_cast<cx<T> *>(out) + r0 * M;
     if constexpr (EPI == EPI_PLAIN) {
@@ -199,7 +209,7 @@ __global__ __launch_bounds__(ROWS *PL::Tp) void x_c2r_kernel(const cx<T> *in, T 
         }
     } else {
         cx<T> w[Rmax];
-        x_c2r_row<T, PL, ROWS>(w, ea.in2 + r0 * M, valid, t, &sh[p * LD], tw, lt_shift);
+        x_c2r_row<T, PL, ROWS, PAD>(w, ea.in2 + r0 * M, valid, t, &sh[p * LD], tw, lt_shift);
         fft_stages<T, PL, +1>(w, t, lds, tw, lt_shift);
         const cx<T> *pn = reinterpret_cast<const cx<T> *>(ea.psi_n) + r0 * M;
         const cx<T> *pn1 = reinterpret_cast<const cx<T> *>(ea.psi_np1) + r0 * M;
@@ -227,8 +237,8 @@ __global__ __launch_bounds__(ROWS *PL::Tp) void x_c2r_kernel(const cx<T> *in, T 
 // Pencil (batch, col) has element e at  batch*bstride + e*estride + col,  col < ncols contiguous.
 // A workgroup handles W adjacent columns (W <= WMAX); its threads are laid out column-fastest so
 // each load/store instruction moves W * sizeof(cx) contiguous bytes per element row.
-template <typename T, class PL, int WMAX, int DIR>
-__global__ __launch_bounds__(WMAX *PL::Tp) void axis_c2c_kernel(const cx<T> *src, cx<T> *dst, int W,
+template <typename T, class PL, int WMAX, int DIR, int OCC = 1>
+__global__ __launch_bounds__(WMAX *PL::Tp, OCC) void axis_c2c_kernel(const cx<T> *src, cx<T> *dst, int W,
                                                                  int64_t ncols, int64_t estride, int64_t bstride,
                                                                  int64_t tiles_per_batch,
                                                                  const cx<T> *__restrict__ tw, int lt_shift)
@@ -319,8 +329,8 @@ __device__ __forceinline__ SlotInfo la_slot(int64_t nrows, int TR, int W, int p)
     return s;
 }
 
-template <typename T, class PL, int WMAX, int MODE>
-__global__ __launch_bounds__(WMAX *PL::Tp) void last_axis_kernel(LastAxisArgs<T> a)
+template <typename T, class PL, int WMAX, int MODE, int OCC = 1, bool PF = true>
+__global__ __launch_bounds__(WMAX *PL::Tp, OCC) void last_axis_kernel(LastAxisArgs<T> a)
 {
     constexpr int L = PL::L, Tp = PL::Tp, Rmax = PL::Rmax;
     using PR = typename PL::Reverse;  // inverse schedule: its first radix is PL's last
@@ -377,6 +387,17 @@ __global__ __launch_bounds__(WMAX *PL::Tp) void last_axis_kernel(LastAxisArgs<T>
         }
         return;
     } else {
+        // STEP with PF: the state values this thread updates are loaded before the forward FFT so
+        // that their latency overlaps the FFT
+        cx<T> spre[(MODE == LA_STEP && PF) ? Rmax : 1];
+        if constexpr (MODE == LA_STEP && PF) {
+#pragma unroll
+            for (int b = 0; b < Rmax / Rl; ++b)
+#pragma unroll
+                for (int r = 0; r < Rl; ++r)
+                    spre[b * Rl + r] = valid ? a.state[(int64_t)(t + b * Tp + r * (L / Rl)) * estride + coloff]
+                                             : cx<T>{T(0), T(0)};
+        }
         // packed input, forward FFT
         constexpr int R0 = PL::first;
 #pragma unroll
@@ -433,7 +454,11 @@ __global__ __launch_bounds__(WMAX *PL::Tp) void last_axis_kernel(LastAxisArgs<T>
                     const cx<T> N = {v[b * Rl + r].x * nl, v[b * Rl + r].y * nl};
                     if (si.partner < 0) {
                         const int64_t gi = (int64_t)e * estride + coloff;
-                        const cx<T> S = valid ? a.state[gi] : cx<T>{T(0), T(0)};
+                        cx<T> S;
+                        if constexpr (PF)
+                            S = spre[b * Rl + r];
+                        else
+                            S = valid ? a.state[gi] : cx<T>{T(0), T(0)};
                         const T q = kz * kz + ky * ky + kx * kx;
                         const T A = amult(mp, q), dq = dt * q;
                         const cx<T> Snew = {(S.x - dq * N.x) * A, (S.y - dq * N.y) * A};
@@ -456,7 +481,12 @@ __global__ __launch_bounds__(WMAX *PL::Tp) void last_axis_kernel(LastAxisArgs<T>
 #pragma unroll
                     for (int r = 0; r < Rl; ++r) {
                         const int e = t + b * Tp + r * (L / Rl);
-                        if (si.partner >= 0 && valid) lds(e) = a.state[(int64_t)e * estride + coloff];
+                        if (si.partner >= 0 && valid) {
+                            if constexpr (PF)
+                                lds(e) = spre[b * Rl + r];
+                            else
+                                lds(e) = a.state[(int64_t)e * estride + coloff];
+                        }
                     }
                 __syncthreads();
                 if (si.partner >= 0) {
@@ -467,7 +497,11 @@ __global__ __launch_bounds__(WMAX *PL::Tp) void last_axis_kernel(LastAxisArgs<T>
                             const int e = t + b * Tp + r * (L / Rl);
                             const T kz = mp.fk[0] * (T)signed_index(e, L);
                             const int64_t gi = (int64_t)e * estride + coloff;
-                            const cx<T> S = valid ? a.state[gi] : cx<T>{T(0), T(0)};
+                            cx<T> S;
+                            if constexpr (PF)
+                                S = spre[b * Rl + r];
+                            else
+                                S = valid ? a.state[gi] : cx<T>{T(0), T(0)};
                             const cx<T> Sp = partner_val(e);
                             const cx<T> S0 = {(S.x + Sp.x) * h, (S.y - Sp.y) * h};
                             const cx<T> SN = {(S.y + Sp.y) * h, (Sp.x - S.x) * h};
