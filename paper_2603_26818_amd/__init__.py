@@ -29,3 +29,4 @@ from ._binding import (  # noqa: F401
     pfc_step_backward,
     pfc_step_timed,
 )
+from .rollout import PFCRollout, loss_and_grad  # noqa: F401,E402

@@ -138,6 +138,7 @@ class Plan:
         _check(lib.pfc_plan_create(ctypes.byref(h), ctypes.byref(d)), "pfc_plan_create")
         self._h = h
         self._lib = lib
+        self.r, self.dt = float(r), float(dt)
         self.shape = shape
         self.device = torch.device("cuda", int(device))
         self.real_dtype = torch.float64 if self.f64 else torch.float32
@@ -247,6 +248,7 @@ class Plan:
 
     def set_params(self, r, dt):
         _check(self._lib.pfc_plan_set_params(self._h, float(r), float(dt)), "pfc_plan_set_params")
+        self.r, self.dt = float(r), float(dt)
 
     def destroy(self):
         if getattr(self, "_h", None) is not None and self._h.value:
