@@ -138,6 +138,42 @@ pfc_status pfc_step_backward(pfc_plan *p, const void *psi_n, const void *psi_np1
  * from the k = 0 mode.  Accumulation in FP64 in both dtypes.  out_dev: 2 device doubles. */
 pfc_status pfc_energy(pfc_plan *p, const void *psi, const void *state, double *out_dev, void *stream);
 
+/* ---- Batched form: many independent 2D runs of mixed sizes in one persistent launch ----------
+ * Each instance is a 2D grid n0 x n1 (each a power of two in [32, 1024]) with its own model, r and
+ * dt; all instances share the dtype and device.  pfc_batch_step advances every instance by nsteps
+ * steps with ONE launch of a persistent kernel (replayed from a HIP graph captured on first use for
+ * that nsteps): a step is three passes (x r2c with cube, y forward + update + y inverse, x c2r), each a
+ * list of work items over all instances, separated by grid barriers.  The barrier wait is bounded:
+ * if the workgroups cannot all be resident the launch ends early and pfc_batch_check reports it. */
+typedef struct pfc_batch pfc_batch;
+
+/* Validate `count` (1..256) 2D descriptors and create a batch (host memory only). */
+pfc_status pfc_batch_create(pfc_batch **out, const pfc_plan_desc *descs, int count);
+
+/* Device workspace bytes: twiddle table, instance table, barrier state, one packed spectrum per
+ * instance. */
+size_t pfc_batch_workspace_bytes(const pfc_batch *b);
+
+/* Bind the caller's fields: psi[i] (real, n0*n1) and state[i] (native spectrum, n0*n1/2 complex)
+ * for instance i, and the workspace (>= 256-byte aligned).  Uploads the instance table and
+ * twiddles and clears the barrier state (synchronous).  Drops graphs captured for earlier bindings. */
+pfc_status pfc_batch_bind(pfc_batch *b, void *const *psi, void *const *state, void *workspace, size_t bytes);
+
+/* state[i] = spectral state of psi[i] for every instance (as pfc_state_init). */
+pfc_status pfc_batch_state_init(pfc_batch *b, void *stream);
+
+/* Advance every instance by nsteps >= 0 steps: one graph launch of the persistent kernel. */
+pfc_status pfc_batch_step(pfc_batch *b, int64_t nsteps, void *stream);
+
+/* Synchronise `stream` and report whether a grid barrier of an earlier pfc_batch_step timed out
+ * (PFC_ERR_INTERNAL; the barrier state is then cleared). */
+pfc_status pfc_batch_check(pfc_batch *b, void *stream);
+
+/* Number of persistent workgroups of the batch launch (known after pfc_batch_bind). */
+int pfc_batch_grid(const pfc_batch *b);
+
+pfc_status pfc_batch_destroy(pfc_batch *b);
+
 const char *pfc_status_string(pfc_status st);
 const char *pfc_last_error(void);
 

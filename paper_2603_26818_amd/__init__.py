@@ -13,6 +13,7 @@ from ._binding import (  # noqa: F401
     PFC_FLAG_LINEAR_ONLY,
     PFC_ONE_MODE,
     PFC_TWO_MODE,
+    Batch,
     PfcError,
     Plan,
     library_path,

@@ -68,6 +68,15 @@ _SIGS = {
                                       ctypes.c_void_p, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int)]),
     "pfc_step_backward": (ctypes.c_int, [ctypes.c_void_p] * 7),
     "pfc_energy": (ctypes.c_int, [ctypes.c_void_p] * 5),
+    "pfc_batch_create": (ctypes.c_int, [ctypes.POINTER(ctypes.c_void_p), ctypes.POINTER(PlanDesc), ctypes.c_int]),
+    "pfc_batch_workspace_bytes": (ctypes.c_size_t, [ctypes.c_void_p]),
+    "pfc_batch_bind": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_void_p), ctypes.POINTER(ctypes.c_void_p),
+                                      ctypes.c_void_p, ctypes.c_size_t]),
+    "pfc_batch_state_init": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p]),
+    "pfc_batch_step": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p]),
+    "pfc_batch_check": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p]),
+    "pfc_batch_grid": (ctypes.c_int, [ctypes.c_void_p]),
+    "pfc_batch_destroy": (ctypes.c_int, [ctypes.c_void_p]),
     "pfc_status_string": (ctypes.c_char_p, [ctypes.c_int]),
     "pfc_last_error": (ctypes.c_char_p, []),
 }
@@ -112,6 +121,23 @@ def _torch():
 def _stream_ptr(device):
     torch = _torch()
     return ctypes.c_void_p(torch.cuda.current_stream(device).cuda_stream)
+
+
+def make_desc(shape, dtype="f32", model=PFC_ONE_MODE, r=-0.25, dt=0.5, dx=math.pi / 4, q1sq=4.0 / 3.0, R1=0.0,
+              device=0, flags=0) -> PlanDesc:
+    shape = tuple(int(v) for v in shape)
+    d = PlanDesc()
+    d.ndim = len(shape)
+    dxs = tuple(dx) if isinstance(dx, (tuple, list)) else (dx,) * len(shape)
+    for a in range(3):
+        d.n[a] = shape[a] if a < len(shape) else 1
+        d.dx[a] = float(dxs[a]) if a < len(shape) else 1.0
+    d.dtype = PFC_F64 if dtype in ("f64", "float64", PFC_F64) else PFC_F32
+    d.model = int(model)
+    d.r, d.dt, d.q1sq, d.R1 = float(r), float(dt), float(q1sq), float(R1)
+    d.device = int(device)
+    d.flags = int(flags)
+    return d
 
 
 class Plan:
@@ -253,6 +279,79 @@ class Plan:
     def destroy(self):
         if getattr(self, "_h", None) is not None and self._h.value:
             self._lib.pfc_plan_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.destroy()
+        except Exception:
+            pass
+
+
+class Batch:
+    """A pfc_batch: many independent 2D runs advanced together by one persistent launch.
+
+    instances: list of dicts with the Plan keywords (shape, dtype, model, r, dt, dx, q1sq, R1, flags)."""
+
+    def __init__(self, instances, device=0):
+        torch = _torch()
+        lib = load_library()
+        self._lib = lib
+        self.instances = [dict(i) for i in instances]
+        descs = (PlanDesc * len(instances))()
+        for k, inst in enumerate(self.instances):
+            descs[k] = make_desc(device=device, **inst)
+        h = ctypes.c_void_p()
+        _check(lib.pfc_batch_create(ctypes.byref(h), descs, len(instances)), "pfc_batch_create")
+        self._h = h
+        self.device = torch.device("cuda", int(device))
+        self.f64 = descs[0].dtype == PFC_F64
+        self.real_dtype = torch.float64 if self.f64 else torch.float32
+        self.complex_dtype = torch.complex128 if self.f64 else torch.complex64
+        self.psi = self.state = None
+
+    def bind(self, psis, states=None):
+        """Attach the fields (psi[i]: real (n0, n1), state[i]: complex (n0, n1/2)); allocates states
+        when not given, and the workspace."""
+        torch = _torch()
+        if states is None:
+            states = [torch.empty(tuple(p.shape[:-1]) + (p.shape[-1] // 2,), dtype=self.complex_dtype,
+                                  device=self.device) for p in psis]
+        n = len(self.instances)
+        if len(psis) != n or len(states) != n:
+            raise ValueError("one psi and one state per instance")
+        for k, (p, s_, inst) in enumerate(zip(psis, states, self.instances)):
+            shp = tuple(inst["shape"])
+            if tuple(p.shape) != shp or p.dtype != self.real_dtype or p.device != self.device or not p.is_contiguous():
+                raise ValueError(f"psi[{k}] must be a contiguous {self.real_dtype} tensor of shape {shp}")
+            sshp = shp[:-1] + (shp[-1] // 2,)
+            if tuple(s_.shape) != sshp or s_.dtype != self.complex_dtype or not s_.is_contiguous():
+                raise ValueError(f"state[{k}] must be a contiguous {self.complex_dtype} tensor of shape {sshp}")
+        nbytes = self._lib.pfc_batch_workspace_bytes(self._h)
+        self.workspace = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+        pp = (ctypes.c_void_p * n)(*[p.data_ptr() for p in psis])
+        sp = (ctypes.c_void_p * n)(*[s_.data_ptr() for s_ in states])
+        _check(self._lib.pfc_batch_bind(self._h, pp, sp, ctypes.c_void_p(self.workspace.data_ptr()), nbytes),
+               "pfc_batch_bind")
+        self.psi, self.state = list(psis), list(states)
+        return self
+
+    @property
+    def grid(self):
+        return self._lib.pfc_batch_grid(self._h)
+
+    def state_init(self):
+        _check(self._lib.pfc_batch_state_init(self._h, _stream_ptr(self.device)), "pfc_batch_state_init")
+
+    def step(self, nsteps):
+        _check(self._lib.pfc_batch_step(self._h, int(nsteps), _stream_ptr(self.device)), "pfc_batch_step")
+
+    def check(self):
+        _check(self._lib.pfc_batch_check(self._h, _stream_ptr(self.device)), "pfc_batch_check")
+
+    def destroy(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            self._lib.pfc_batch_destroy(self._h)
             self._h = ctypes.c_void_p()
 
     def __del__(self):

@@ -1,0 +1,190 @@
+// batch.hpp -- persistent kernel that advances many independent 2D PFC runs of mixed sizes.
+//
+// One launch runs `nsteps` steps of every instance.  A step is three passes (x r2c with cube,
+// y forward + update + y inverse, x c2r); each pass is a list of work items (a group of rows or a
+// tile of columns of one instance), and the persistent workgroups take items round-robin.  A grid
+// barrier separates passes.  Every workgroup has NT threads; each size runs a schedule whose
+// thread count per item is exactly NT, so one kernel serves all sizes.
+//
+// The grid barrier waits a bounded number of polls.  If the wait runs out (the workgroups are not
+// all resident), it sets an error flag and every workgroup leaves the kernel at its next barrier,
+// so the launch always terminates; the host reads the flag (pfc_batch_check).
+#pragma once
+
+#include "kernels.hpp"
+
+namespace pfc {
+
+constexpr int kBatchThreads = 512;
+constexpr int kBatchMaxInst = 256;
+
+// Schedules of the batched passes: NT / Tp rows (x passes) or pencils (y pass) per item.
+template <int M> struct BXFwd { using type = typename XFwdPlan<M>::type; };
+template <int M> struct BXInv { using type = typename XInvPlan<M>::type; };
+template <int L> struct BLast { using type = typename LastPlan<L>::type; };
+
+template <class PL>
+struct BRows {
+    static constexpr int value = kBatchThreads / PL::Tp;
+};
+
+// Grid-wide barrier across the persistent workgroups (all resident).  Release: write back this
+// XCD's L2 before arriving; acquire: invalidate it after the wait, so stores of every workgroup
+// before the barrier are visible to loads of every workgroup after it.  Returns false (for the
+// whole workgroup) if an error flag is set or the wait timed out.
+__device__ __forceinline__ bool grid_sync(BatchCtl *ctl, unsigned nblocks, unsigned long long max_polls)
+{
+    __shared__ int ok;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int good = 1;
+        if (__hip_atomic_load(&ctl->err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) {
+            good = 0;
+        } else {
+            const unsigned g = __hip_atomic_load(&ctl->gen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+            const unsigned a = __hip_atomic_fetch_add(&ctl->count, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            if (a + 1 == nblocks) {
+                __hip_atomic_store(&ctl->count, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                __hip_atomic_fetch_add(&ctl->gen, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+            } else {
+                unsigned long long polls = 0;
+                while (__hip_atomic_load(&ctl->gen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == g) {
+                    if (__hip_atomic_load(&ctl->err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) {
+                        good = 0;
+                        break;
+                    }
+                    if (++polls > max_polls) {
+                        __hip_atomic_store(&ctl->err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                        good = 0;
+                        break;
+                    }
+                    __builtin_amdgcn_s_sleep(2);
+                }
+            }
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+        }
+        ok = good;
+    }
+    __syncthreads();
+    return ok != 0;
+}
+
+// instance owning global item k of a pass (items of instance i are [begin_i, begin_{i+1}))
+template <typename T, int PASS>
+__device__ __forceinline__ int find_inst(const BatchArgs<T> &a, int k)
+{
+    int i = 0;
+    while (i + 1 < a.ninst) {
+        const BatchInst<T> &n = a.inst[i + 1];
+        const int b = PASS == 0 ? n.x_begin : PASS == 1 ? n.y_begin : n.c_begin;
+        if (k < b) break;
+        ++i;
+    }
+    return i;
+}
+
+// The per-size pass bodies are separate (non-inlined) functions: inlined into one kernel, the
+// schedules of all sizes interfere in register allocation and spill heavily.  They reach LDS
+// through a file-scope __shared__ array (defined by the including translation unit, one dtype per
+// unit), so their LDS accesses stay ds_* instructions.
+template <typename T>
+__device__ __forceinline__ cx<T> *batch_lds();
+
+template <typename T, int M>
+__device__ __noinline__ void batch_x_fwd(const BatchInst<T> *in, int item, const cx<T> *tw, int lt_shift)
+{
+    using PL = typename BXFwd<M>::type;
+    x_r2c_block<T, PL, BRows<PL>::value, true>(in->psi, in->scratch, in->n0, tw, lt_shift, item, batch_lds<T>());
+}
+
+template <typename T, int L>
+__device__ __noinline__ void batch_y_step(const BatchInst<T> *in, int item, const cx<T> *tw, int lt_shift)
+{
+    using PL = typename BLast<L>::type;
+    constexpr int WM = kBatchThreads / PL::Tp;
+    LastAxisArgs<T> la;
+    la.src = in->scratch;
+    la.dst = in->scratch;
+    la.dst2 = nullptr;
+    la.state = in->state;
+    la.nrows = 1;
+    la.M = in->M;
+    la.W = in->W;
+    la.tiles_per_row = in->tiles;
+    la.tw = tw;
+    la.lt_shift = lt_shift;
+    la.mp = in->mp;
+    last_axis_block<T, PL, WM, LA_STEP>(la, item, batch_lds<T>());
+}
+
+template <typename T, int M>
+__device__ __noinline__ void batch_x_inv(const BatchInst<T> *in, int item, const cx<T> *tw, int lt_shift)
+{
+    using PL = typename BXInv<M>::type;
+    AdjEpi<T> ea{};
+    x_c2r_block<T, PL, BRows<PL>::value, EPI_PLAIN>(in->scratch, in->psi, in->n0, tw, lt_shift, in->sc, ea, item,
+                                                     batch_lds<T>());
+}
+
+// supported lengths: x 32..1024 (M = 16..512), y 32..1024
+template <typename T>
+__device__ __forceinline__ void batch_pass(int pass, const BatchInst<T> *in, int item, const cx<T> *tw, int lt)
+{
+    if (pass == 0) {
+        switch (in->M) {
+        case 16: batch_x_fwd<T, 16>(in, item, tw, lt); break;
+        case 32: batch_x_fwd<T, 32>(in, item, tw, lt); break;
+        case 64: batch_x_fwd<T, 64>(in, item, tw, lt); break;
+        case 128: batch_x_fwd<T, 128>(in, item, tw, lt); break;
+        case 256: batch_x_fwd<T, 256>(in, item, tw, lt); break;
+        case 512: batch_x_fwd<T, 512>(in, item, tw, lt); break;
+        default: break;
+        }
+    } else if (pass == 1) {
+        switch (in->n0) {
+        case 32: batch_y_step<T, 32>(in, item, tw, lt); break;
+        case 64: batch_y_step<T, 64>(in, item, tw, lt); break;
+        case 128: batch_y_step<T, 128>(in, item, tw, lt); break;
+        case 256: batch_y_step<T, 256>(in, item, tw, lt); break;
+        case 512: batch_y_step<T, 512>(in, item, tw, lt); break;
+        case 1024: batch_y_step<T, 1024>(in, item, tw, lt); break;
+        default: break;
+        }
+    } else {
+        switch (in->M) {
+        case 16: batch_x_inv<T, 16>(in, item, tw, lt); break;
+        case 32: batch_x_inv<T, 32>(in, item, tw, lt); break;
+        case 64: batch_x_inv<T, 64>(in, item, tw, lt); break;
+        case 128: batch_x_inv<T, 128>(in, item, tw, lt); break;
+        case 256: batch_x_inv<T, 256>(in, item, tw, lt); break;
+        case 512: batch_x_inv<T, 512>(in, item, tw, lt); break;
+        default: break;
+        }
+    }
+}
+
+// LDS needed by the largest schedule: NT * Rmax complex values (Rmax <= 16).
+constexpr int kBatchLdsElems = kBatchThreads * 16;
+
+// 2 workgroups of kBatchThreads per CU (4 waves per SIMD).
+template <typename T>
+__global__ __launch_bounds__(kBatchThreads, 4) void batch_kernel(BatchArgs<T> a)
+{
+    const unsigned G = gridDim.x;
+    for (int64_t step = 0; step < a.nsteps; ++step) {
+        for (int pass = 0; pass < 3; ++pass) {
+            const int total = pass == 0 ? a.x_total : pass == 1 ? a.y_total : a.c_total;
+            for (int k = blockIdx.x; k < total; k += G) {
+                const int i = pass == 0 ? find_inst<T, 0>(a, k) : pass == 1 ? find_inst<T, 1>(a, k)
+                                                                             : find_inst<T, 2>(a, k);
+                const BatchInst<T> *in = &a.inst[i];
+                const int item = k - (pass == 0 ? in->x_begin : pass == 1 ? in->y_begin : in->c_begin);
+                batch_pass<T>(pass, in, item, a.tw, a.lt_shift);
+            }
+            if (!grid_sync(a.ctl, G, a.max_polls)) return;
+        }
+    }
+}
+
+}  // namespace pfc

@@ -76,16 +76,16 @@ struct XPitch {
 template <bool PAD>
 __device__ __forceinline__ int xidx(int e) { return PAD ? xpad(e) : e; }
 
+// One block of ROWS rows (block index `bid`); `sh` holds ROWS * XPitch<M, PAD> LDS slots.
+// Uses threads 0 .. ROWS*Tp-1, which must be all threads of the workgroup.
 template <typename T, class PL, int ROWS, bool CUBE, bool PAD = false>
-__global__ __launch_bounds__(ROWS *PL::Tp) void x_r2c_kernel(const T *__restrict__ in, cx<T> *__restrict__ out,
-                                                              int64_t nrows, const cx<T> *__restrict__ tw,
-                                                              int lt_shift)
+__device__ __forceinline__ void x_r2c_block(const T *__restrict__ in, cx<T> *__restrict__ out, int64_t nrows,
+                                            const cx<T> *__restrict__ tw, int lt_shift, int64_t bid, cx<T> *sh)
 {
     constexpr int M = PL::L, Tp = PL::Tp, R0 = PL::first, Rl = PL::last, Rmax = PL::Rmax;
     constexpr int LD = XPitch<M, PAD>::value;  // row pitch in LDS
-    __shared__ cx<T> sh[ROWS * LD];
     const int tid = threadIdx.x, p = tid / Tp, t = tid - p * Tp;
-    const int64_t row = (int64_t)blockIdx.x * ROWS + p;
+    const int64_t row = bid * ROWS + p;
     const bool valid = row < nrows;
     const cx<T> *src = reinterpret_cast<const cx<T> *>(in) + (valid ? row : 0) * M;
     cx<T> v[Rmax];
@@ -125,6 +125,15 @@ __global__ __launch_bounds__(ROWS *PL::Tp) void x_r2c_kernel(const T *__restrict
             }
             if (valid) dst[k] = X;
         }
+}
+
+template <typename T, class PL, int ROWS, bool CUBE, bool PAD = false>
+__global__ __launch_bounds__(ROWS *PL::Tp) void x_r2c_kernel(const T *__restrict__ in, cx<T> *__restrict__ out,
+                                                              int64_t nrows, const cx<T> *__restrict__ tw,
+                                                              int lt_shift)
+{
+    __shared__ cx<T> sh[ROWS * XPitch<PL::L, PAD>::value];
+    x_r2c_block<T, PL, ROWS, CUBE, PAD>(in, out, nrows, tw, lt_shift, blockIdx.x, sh);
 }
 
 // ------------------------------------------------------------------------------------------------
@@ -183,15 +192,13 @@ __device__ __forceinline__ void x_c2r_row(cx<T> *v, const cx<T> *src, bool valid
 }
 
 template <typename T, class PL, int ROWS, int EPI, bool PAD = false>
-__global__ __launch_bounds__(ROWS *PL::Tp) void x_c2r_kernel(const cx<T> *in, T *out, int64_t nrows,
-                                                              const cx<T> *__restrict__ tw, int lt_shift, T sc,
-                                                              AdjEpi<T> ea)
+__device__ __forceinline__ void x_c2r_block(const cx<T> *in, T *out, int64_t nrows, const cx<T> *__restrict__ tw,
+                                            int lt_shift, T sc, const AdjEpi<T> &ea, int64_t bid, cx<T> *sh)
 {
     constexpr int M = PL::L, Tp = PL::Tp, Rl = PL::last, Rmax = PL::Rmax;
     constexpr int LD = XPitch<M, PAD>::value;
-    __shared__ cx<T> sh[ROWS * LD];
     const int tid = threadIdx.x, p = tid / Tp, t = tid - p * Tp;
-    const int64_t row = (int64_t)blockIdx.x * ROWS + p;
+    const int64_t row = bid * ROWS + p;
     const bool valid = row < nrows;
     const int64_t r0 = valid ? row : 0;
     auto lds = [&](int e) -> cx<T> & { return sh[p * LD + xidx<PAD>(e)]; };
@@ -228,8 +235,17 @@ __global__ __launch_bounds__(ROWS *PL::Tp) void x_c2r_kernel(const cx<T> *in, T 
         }
         __shared__ double red[16];
         const double s = block_sum(acc, red);
-        if (threadIdx.x == 0) ea.partial[blockIdx.x] = s;
+        if (threadIdx.x == 0) ea.partial[bid] = s;
     }
+}
+
+template <typename T, class PL, int ROWS, int EPI, bool PAD = false>
+__global__ __launch_bounds__(ROWS *PL::Tp) void x_c2r_kernel(const cx<T> *in, T *out, int64_t nrows,
+                                                              const cx<T> *__restrict__ tw, int lt_shift, T sc,
+                                                              AdjEpi<T> ea)
+{
+    __shared__ cx<T> sh[ROWS * XPitch<PL::L, PAD>::value];
+    x_c2r_block<T, PL, ROWS, EPI, PAD>(in, out, nrows, tw, lt_shift, sc, ea, blockIdx.x, sh);
 }
 
 // ------------------------------------------------------------------------------------------------
@@ -237,16 +253,14 @@ __global__ __launch_bounds__(ROWS *PL::Tp) void x_c2r_kernel(const cx<T> *in, T 
 // Pencil (batch, col) has element e at  batch*bstride + e*estride + col,  col < ncols contiguous.
 // A workgroup handles W adjacent columns (W <= WMAX); its threads are laid out column-fastest so
 // each load/store instruction moves W * sizeof(cx) contiguous bytes per element row.
-template <typename T, class PL, int WMAX, int DIR, int OCC = 1>
-__global__ __launch_bounds__(WMAX *PL::Tp, OCC) void axis_c2c_kernel(const cx<T> *src, cx<T> *dst, int W,
-                                                                 int64_t ncols, int64_t estride, int64_t bstride,
-                                                                 int64_t tiles_per_batch,
-                                                                 const cx<T> *__restrict__ tw, int lt_shift)
+template <typename T, class PL, int WMAX, int DIR>
+__device__ __forceinline__ void axis_c2c_block(const cx<T> *src, cx<T> *dst, int W, int64_t ncols, int64_t estride,
+                                               int64_t bstride, int64_t tiles_per_batch,
+                                               const cx<T> *__restrict__ tw, int lt_shift, int64_t bid, cx<T> *sh)
 {
     constexpr int L = PL::L, Tp = PL::Tp, R0 = PL::first, Rl = PL::last, Rmax = PL::Rmax;
-    __shared__ cx<T> sh[L * WMAX];
     const int tid = threadIdx.x, p = tid % WMAX, t = tid / WMAX;
-    const int64_t batch = blockIdx.x / tiles_per_batch, tile = blockIdx.x - batch * tiles_per_batch;
+    const int64_t batch = bid / tiles_per_batch, tile = bid - batch * tiles_per_batch;
     const int64_t col = tile * W + p;
     const bool valid = p < W && col < ncols;
     const int64_t base = batch * bstride + (valid ? col : 0);
@@ -264,6 +278,17 @@ __global__ __launch_bounds__(WMAX *PL::Tp, OCC) void axis_c2c_kernel(const cx<T>
 #pragma unroll
             for (int r = 0; r < Rl; ++r) dst[base + (int64_t)(t + b * Tp + r * (L / Rl)) * estride] = v[b * Rl + r];
     }
+}
+
+template <typename T, class PL, int WMAX, int DIR, int OCC = 1>
+__global__ __launch_bounds__(WMAX *PL::Tp, OCC) void axis_c2c_kernel(const cx<T> *src, cx<T> *dst, int W,
+                                                                 int64_t ncols, int64_t estride, int64_t bstride,
+                                                                 int64_t tiles_per_batch,
+                                                                 const cx<T> *__restrict__ tw, int lt_shift)
+{
+    __shared__ cx<T> sh[PL::L * WMAX];
+    axis_c2c_block<T, PL, WMAX, DIR>(src, dst, W, ncols, estride, bstride, tiles_per_batch, tw, lt_shift, blockIdx.x,
+                                     sh);
 }
 
 // ------------------------------------------------------------------------------------------------
@@ -299,10 +324,9 @@ struct SlotInfo {
     bool has_pairs;
 };
 
-__device__ __forceinline__ SlotInfo la_slot(int64_t nrows, int TR, int W, int p)
+__device__ __forceinline__ SlotInfo la_slot(int64_t nrows, int TR, int W, int p, int64_t bid)
 {
     SlotInfo s;
-    const int64_t bid = blockIdx.x;
     if (nrows == 1) {
         s.row = 0;
         s.kx = (int)bid * W + p;
@@ -329,17 +353,16 @@ __device__ __forceinline__ SlotInfo la_slot(int64_t nrows, int TR, int W, int p)
     return s;
 }
 
-template <typename T, class PL, int WMAX, int MODE, int OCC = 1, bool PF = true>
-__global__ __launch_bounds__(WMAX *PL::Tp, OCC) void last_axis_kernel(LastAxisArgs<T> a)
+template <typename T, class PL, int WMAX, int MODE, bool PF = true>
+__device__ __forceinline__ void last_axis_block(const LastAxisArgs<T> &a, int64_t bid, cx<T> *sh)
 {
     constexpr int L = PL::L, Tp = PL::Tp, Rmax = PL::Rmax;
     using PR = typename PL::Reverse;  // inverse schedule: its first radix is PL's last
     constexpr int Rl = PL::last;
-    __shared__ cx<T> sh[L * WMAX];
     const int tid = threadIdx.x, p = tid % WMAX, t = tid / WMAX;
     const int W = a.W;
     const int64_t nrows = a.nrows, M = a.M, estride = nrows * M;
-    const SlotInfo si = la_slot(nrows, a.tiles_per_row, W, p < W ? p : 0);
+    const SlotInfo si = la_slot(nrows, a.tiles_per_row, W, p < W ? p : 0, bid);
     const bool valid = p < W;
     const int64_t coloff = si.row * M + si.kx;
     auto lds = [&](int e) -> cx<T> & { return sh[e * WMAX + p]; };
@@ -352,7 +375,7 @@ __global__ __launch_bounds__(WMAX *PL::Tp, OCC) void last_axis_kernel(LastAxisAr
     if constexpr (MODE == LA_C2R_NATURAL) {
         // natural half spectrum in: fold kx = 0 and kx = M (projected) into one plane, inverse FFT
         constexpr int R0 = PR::first;
-        const int64_t prow = (si.partner >= 0) ? la_slot(nrows, a.tiles_per_row, W, si.partner).row : 0;
+        const int64_t prow = (si.partner >= 0) ? la_slot(nrows, a.tiles_per_row, W, si.partner, bid).row : 0;
         const int64_t pitch = M + 1;
 #pragma unroll
         for (int b = 0; b < Rmax / R0; ++b)
@@ -572,6 +595,13 @@ __global__ __launch_bounds__(WMAX *PL::Tp, OCC) void last_axis_kernel(LastAxisAr
             }
         }
     }
+}
+
+template <typename T, class PL, int WMAX, int MODE, int OCC = 1, bool PF = true>
+__global__ __launch_bounds__(WMAX *PL::Tp, OCC) void last_axis_kernel(LastAxisArgs<T> a)
+{
+    __shared__ cx<T> sh[PL::L * WMAX];
+    last_axis_block<T, PL, WMAX, MODE, PF>(a, blockIdx.x, sh);
 }
 
 // ------------------------------------------------------------------------------------------------

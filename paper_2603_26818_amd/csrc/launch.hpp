@@ -56,4 +56,15 @@ template <typename T>
 hipError_t launch_export(const Geom &g, const cx<T> *state, cx<T> *out, hipStream_t s);
 hipError_t launch_accumulate(const double *partial, int np, double coef, double *acc, hipStream_t s);
 
+// batched persistent kernel: kBatchThreads threads per workgroup, `grid` workgroups (all resident)
+template <typename T>
+hipError_t launch_batch(const BatchArgs<T> &a, int grid, hipStream_t s);
+template <typename T>
+hipError_t batch_blocks_per_cu(int *blocks);
+constexpr int kBatchThreadsHost = 512;
+constexpr int kBatchMaxInstHost = 256;
+// rows per x-forward / x-inverse item and pencils per y item of the batched kernel for an n0 x 2M
+// instance (returns false for unsupported lengths)
+bool batch_tiles(int n0, int M, int *x_rows, int *c_rows, int *y_pencils);
+
 }  // namespace pfc

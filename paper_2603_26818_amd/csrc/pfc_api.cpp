@@ -7,8 +7,11 @@
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
+#include <algorithm>
 #include <cstring>
+#include <map>
 #include <new>
+#include <numeric>
 #include <string>
 #include <vector>
 
@@ -27,6 +30,28 @@ struct pfc_plan {
     size_t n_partials;
     char *ws = nullptr;
     size_t ws_bytes = 0;
+};
+
+struct pfc_batch {
+    int count = 0;
+    pfc_dtype dtype = PFC_F32;
+    int device = 0;
+    std::vector<pfc_plan_desc> descs;  // caller's order
+    std::vector<int> order;            // device table order (largest first) -> caller's index
+    struct Inst {
+        int n0, nx, M, x_rows, c_rows, W, tiles, x_items, c_items;
+    };
+    std::vector<Inst> inst;  // caller's order
+    int lt_shift = 0;
+    int x_total = 0, y_total = 0, c_total = 0;
+    size_t ctl_off = 0, inst_off = 0, tw_off = 0, partial_off = 0, ws_need = 0;
+    std::vector<size_t> scratch_off;  // caller's order
+    char *ws = nullptr;
+    size_t ws_bytes = 0;
+    std::vector<void *> psi, state;
+    int grid = 0;
+    hipStream_t cap = nullptr;
+    std::map<int64_t, std::pair<hipGraph_t, hipGraphExec_t>> graphs;
 };
 
 namespace {
@@ -383,6 +408,146 @@ size_t real_bytes(const pfc_plan *p) { return (size_t)(p->g.n0 * p->g.nrows * p-
 size_t half_bytes(const pfc_plan *p) { return (size_t)(p->g.n0 * p->g.nrows * (p->g.M + 1)) * cx_size(p); }
 size_t state_bytes(const pfc_plan *p) { return (size_t)(p->g.n0 * p->g.nrows * p->g.M) * cx_size(p); }
 
+void drop_graphs(pfc_batch *b)
+{
+    for (auto &kv : b->graphs) {
+        (void)hipGraphExecDestroy(kv.second.second);
+        (void)hipGraphDestroy(kv.second.first);
+    }
+    b->graphs.clear();
+}
+
+template <typename T>
+pfc_status batch_bind_impl(pfc_batch *b)
+{
+    const size_t cs = sizeof(cx<T>);
+    std::vector<pfc::BatchInst<T>> table(b->count);
+    int xb = 0, yb = 0, cb = 0;
+    for (int j = 0; j < b->count; ++j) {
+        const int i = b->order[j];
+        const pfc_batch::Inst &g = b->inst[i];
+        const pfc_plan_desc &d = b->descs[i];
+        pfc::BatchInst<T> &t = table[j];
+        t.psi = (T *)b->psi[i];
+        t.state = (cx<T> *)b->state[i];
+        t.scratch = (cx<T> *)(b->ws + b->scratch_off[i]);
+        t.n0 = g.n0;
+        t.M = g.M;
+        t.W = g.W;
+        t.tiles = g.tiles;
+        t.x_items = g.x_items;
+        t.c_items = g.c_items;
+        t.x_begin = xb;
+        t.y_begin = yb;
+        t.c_begin = cb;
+        xb += g.x_items;
+        yb += g.tiles;
+        cb += g.c_items;
+        t.sc = (T)(1.0 / ((double)g.n0 * (double)g.M));
+        t.mp.r = (T)d.r;
+        t.mp.dt = (T)d.dt;
+        t.mp.q1sq = (T)d.q1sq;
+        t.mp.R1 = (T)d.R1;
+        t.mp.fk[0] = (T)(2.0 * M_PI / ((double)d.n[0] * d.dx[0]));
+        t.mp.fk[1] = (T)0;
+        t.mp.fk[2] = (T)(2.0 * M_PI / ((double)d.n[1] * d.dx[1]));
+        t.mp.nl = (d.flags & PFC_FLAG_LINEAR_ONLY) ? T(0) : T(1);
+        t.mp.model = (int)d.model;
+    }
+    b->x_total = xb;
+    b->y_total = yb;
+    b->c_total = cb;
+    const int64_t Lt = int64_t(1) << b->lt_shift;
+    std::vector<cx<T>> tw(Lt);
+    for (int64_t e = 0; e < Lt; ++e) {
+        long double c, sn;
+        twiddle_value(e, Lt, &c, &sn);
+        tw[e].x = (T)c;
+        tw[e].y = (T)sn;
+    }
+    (void)cs;
+    PFC_TRY(hipMemcpy(b->ws + b->inst_off, table.data(), table.size() * sizeof(table[0]), hipMemcpyHostToDevice),
+            "instance table upload");
+    PFC_TRY(hipMemcpy(b->ws + b->tw_off, tw.data(), tw.size() * sizeof(tw[0]), hipMemcpyHostToDevice),
+            "twiddle upload");
+    PFC_TRY(hipMemset(b->ws + b->ctl_off, 0, sizeof(pfc::BatchCtl)), "barrier state reset");
+    int per_cu = 0, cus = 0;
+    PFC_TRY(pfc::batch_blocks_per_cu<T>(&per_cu), "occupancy query");
+    PFC_TRY(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, b->device), "CU count");
+    if (per_cu < 1) return fail(PFC_ERR_INTERNAL, "batched kernel does not fit on a CU");
+    b->grid = per_cu * cus;
+    return PFC_OK;
+}
+
+template <typename T>
+pfc::BatchArgs<T> batch_args(const pfc_batch *b, int64_t nsteps)
+{
+    pfc::BatchArgs<T> a;
+    a.inst = (const pfc::BatchInst<T> *)(b->ws + b->inst_off);
+    a.ninst = b->count;
+    a.x_total = b->x_total;
+    a.y_total = b->y_total;
+    a.c_total = b->c_total;
+    a.tw = (const cx<T> *)(b->ws + b->tw_off);
+    a.lt_shift = b->lt_shift;
+    a.ctl = (pfc::BatchCtl *)(b->ws + b->ctl_off);
+    a.max_polls = 1ull << 22;  // a few seconds of polling: far beyond any pass of a resident grid
+    a.nsteps = nsteps;
+    return a;
+}
+
+template <typename T>
+pfc_status batch_step_impl(pfc_batch *b, int64_t nsteps, hipStream_t s)
+{
+    auto it = b->graphs.find(nsteps);
+    if (it == b->graphs.end()) {
+        if (!b->cap) PFC_TRY(hipStreamCreateWithFlags(&b->cap, hipStreamNonBlocking), "capture stream");
+        hipGraph_t graph = nullptr;
+        hipGraphExec_t exec = nullptr;
+        PFC_TRY(hipStreamBeginCapture(b->cap, hipStreamCaptureModeThreadLocal), "graph capture begin");
+        hipError_t le = pfc::launch_batch<T>(batch_args<T>(b, nsteps), b->grid, b->cap);
+        hipError_t ee = hipStreamEndCapture(b->cap, &graph);
+        if (le != hipSuccess) {
+            if (graph) (void)hipGraphDestroy(graph);
+            return hip_fail(le, "batched kernel launch (capture)");
+        }
+        if (ee != hipSuccess) return hip_fail(ee, "graph capture end");
+        hipError_t ie = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+        if (ie != hipSuccess) {
+            (void)hipGraphDestroy(graph);
+            return hip_fail(ie, "graph instantiate");
+        }
+        it = b->graphs.emplace(nsteps, std::make_pair(graph, exec)).first;
+    }
+    PFC_TRY(hipGraphLaunch(it->second.second, s), "graph launch");
+    return PFC_OK;
+}
+
+template <typename T>
+pfc_status batch_state_init_impl(pfc_batch *b, hipStream_t s)
+{
+    const cx<T> *tw = (const cx<T> *)(b->ws + b->tw_off);
+    double *partial = (double *)(b->ws + b->partial_off);
+    for (int i = 0; i < b->count; ++i) {
+        const pfc_batch::Inst &in = b->inst[i];
+        Geom g;
+        g.ndim = 2;
+        g.n0 = in.n0;
+        g.n1 = 1;
+        g.nx = in.nx;
+        g.M = in.M;
+        g.nrows = 1;
+        g.xrows = in.n0;
+        g.lt_shift = b->lt_shift;
+        cx<T> *scratch = (cx<T> *)(b->ws + b->scratch_off[i]);
+        PFC_TRY(pfc::launch_x_r2c<T>(g, (const T *)b->psi[i], scratch, false, tw, s), "x_r2c launch");
+        PFC_TRY(pfc::launch_last_fwd<T>(g, scratch, (cx<T> *)b->state[i], tw, s), "last-axis launch");
+        PFC_TRY(pfc::launch_set_mass<T>((const T *)b->psi[i], (int64_t)in.n0 * in.nx, partial, (cx<T> *)b->state[i], s),
+                "mass launch");
+    }
+    return PFC_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -586,6 +751,148 @@ pfc_status pfc_energy(pfc_plan *p, const void *psi, const void *state, double *o
     PFC_CHECK(check_ptr(state, "state"));
     if (!out_dev) return fail(PFC_ERR_INVALID_ARG, "out_dev is NULL");
     PFC_DISPATCH(p, do_energy, p, psi, state, out_dev, (hipStream_t)stream);
+}
+
+pfc_status pfc_batch_create(pfc_batch **out, const pfc_plan_desc *descs, int count)
+{
+    if (!out) return fail(PFC_ERR_INVALID_ARG, "out is NULL");
+    *out = nullptr;
+    if (!descs || count < 1 || count > pfc::kBatchMaxInstHost)
+        return fail(PFC_ERR_INVALID_ARG, "count must be in [1, %d]", pfc::kBatchMaxInstHost);
+    for (int i = 0; i < count; ++i) {
+        const pfc_plan_desc &d = descs[i];
+        if (d.ndim != 2) return fail(PFC_ERR_UNSUPPORTED, "instance %d: the batched form takes 2D grids", i);
+        for (int a = 0; a < 2; ++a)
+            if (!is_pow2(d.n[a]) || d.n[a] < 32 || d.n[a] > 1024)
+                return fail(PFC_ERR_UNSUPPORTED, "instance %d: n[%d] = %lld, batched sizes are powers of two in "
+                            "[32, 1024]", i, a, (long long)d.n[a]);
+        pfc_status st = validate_desc(&d);
+        if (st) return fail(st, "instance %d: %s", i, g_last_error.c_str());
+        if (d.dtype != descs[0].dtype) return fail(PFC_ERR_INVALID_ARG, "instance %d: dtypes differ", i);
+        if (d.device != descs[0].device) return fail(PFC_ERR_INVALID_ARG, "instance %d: devices differ", i);
+    }
+    pfc_batch *b = new (std::nothrow) pfc_batch();
+    if (!b) return fail(PFC_ERR_INTERNAL, "out of host memory");
+    b->count = count;
+    b->dtype = descs[0].dtype;
+    b->device = descs[0].device;
+    b->descs.assign(descs, descs + count);
+    int64_t Lt = 4;
+    for (int i = 0; i < count; ++i) {
+        pfc_batch::Inst g;
+        g.n0 = (int)descs[i].n[0];
+        g.nx = (int)descs[i].n[1];
+        g.M = g.nx / 2;
+        int wm = 0;
+        if (!pfc::batch_tiles(g.n0, g.M, &g.x_rows, &g.c_rows, &wm)) {
+            delete b;
+            return fail(PFC_ERR_UNSUPPORTED, "instance %d: no batched schedule for %d x %d", i, g.n0, g.nx);
+        }
+        g.W = std::min(wm, g.M);
+        g.tiles = g.M / g.W;
+        g.x_items = (g.n0 + g.x_rows - 1) / g.x_rows;
+        g.c_items = (g.n0 + g.c_rows - 1) / g.c_rows;
+        b->inst.push_back(g);
+        Lt = std::max<int64_t>(Lt, std::max(g.n0, g.nx));
+    }
+    while ((int64_t(1) << b->lt_shift) < Lt) ++b->lt_shift;
+    // largest instances first: their items are the longest, so they start first
+    b->order.resize(count);
+    std::iota(b->order.begin(), b->order.end(), 0);
+    std::stable_sort(b->order.begin(), b->order.end(), [&](int x, int y) {
+        return (int64_t)b->inst[x].n0 * b->inst[x].nx > (int64_t)b->inst[y].n0 * b->inst[y].nx;
+    });
+    const size_t cs = b->dtype == PFC_F64 ? 16 : 8;
+    const size_t inst_size = b->dtype == PFC_F64 ? sizeof(pfc::BatchInst<double>) : sizeof(pfc::BatchInst<float>);
+    b->ctl_off = 0;
+    b->inst_off = 256;
+    b->tw_off = b->inst_off + align256(inst_size * count);
+    b->partial_off = b->tw_off + align256((size_t)Lt * cs);
+    size_t off = b->partial_off + align256(pfc::kReduceBlocks * sizeof(double));
+    for (int i = 0; i < count; ++i) {
+        b->scratch_off.push_back(off);
+        off += align256((size_t)b->inst[i].n0 * b->inst[i].M * cs);
+    }
+    b->ws_need = off;
+    *out = b;
+    return PFC_OK;
+}
+
+size_t pfc_batch_workspace_bytes(const pfc_batch *b) { return b ? b->ws_need : 0; }
+
+int pfc_batch_grid(const pfc_batch *b) { return b ? b->grid : 0; }
+
+pfc_status pfc_batch_bind(pfc_batch *b, void *const *psi, void *const *state, void *workspace, size_t bytes)
+{
+    if (!b) return fail(PFC_ERR_INVALID_ARG, "batch is NULL");
+    if (!psi || !state) return fail(PFC_ERR_INVALID_ARG, "psi or state array is NULL");
+    if (!workspace) return fail(PFC_ERR_INVALID_ARG, "workspace is NULL");
+    if (((uintptr_t)workspace & 255u) != 0) return fail(PFC_ERR_ALIGNMENT, "workspace must be 256-byte aligned");
+    if (bytes < b->ws_need) return fail(PFC_ERR_WORKSPACE, "workspace has %zu bytes, needs %zu", bytes, b->ws_need);
+    const size_t cs = b->dtype == PFC_F64 ? 16 : 8;
+    for (int i = 0; i < b->count; ++i) {
+        PFC_CHECK(check_ptr(psi[i], "psi[i]"));
+        PFC_CHECK(check_ptr(state[i], "state[i]"));
+        const size_t n = (size_t)b->inst[i].n0 * b->inst[i].M * cs;
+        if (overlap(psi[i], n, state[i], n)) return fail(PFC_ERR_INVALID_ARG, "psi[%d] and state[%d] overlap", i, i);
+        if (overlap(psi[i], n, workspace, bytes) || overlap(state[i], n, workspace, bytes))
+            return fail(PFC_ERR_INVALID_ARG, "instance %d overlaps the workspace", i);
+    }
+    DeviceGuard dg(b->device);
+    if (dg.err != hipSuccess) return hip_fail(dg.err, "hipSetDevice");
+    drop_graphs(b);
+    b->psi.assign(psi, psi + b->count);
+    b->state.assign(state, state + b->count);
+    b->ws = (char *)workspace;
+    b->ws_bytes = bytes;
+    pfc_status st = b->dtype == PFC_F64 ? batch_bind_impl<double>(b) : batch_bind_impl<float>(b);
+    if (st) b->ws = nullptr;
+    return st;
+}
+
+pfc_status pfc_batch_state_init(pfc_batch *b, void *stream)
+{
+    if (!b || !b->ws) return fail(PFC_ERR_WORKSPACE, "batch not bound");
+    DeviceGuard dg(b->device);
+    if (dg.err != hipSuccess) return hip_fail(dg.err, "hipSetDevice");
+    return b->dtype == PFC_F64 ? batch_state_init_impl<double>(b, (hipStream_t)stream)
+                               : batch_state_init_impl<float>(b, (hipStream_t)stream);
+}
+
+pfc_status pfc_batch_step(pfc_batch *b, int64_t nsteps, void *stream)
+{
+    if (!b || !b->ws) return fail(PFC_ERR_WORKSPACE, "batch not bound");
+    if (nsteps < 0) return fail(PFC_ERR_INVALID_ARG, "nsteps < 0");
+    if (nsteps == 0) return PFC_OK;
+    DeviceGuard dg(b->device);
+    if (dg.err != hipSuccess) return hip_fail(dg.err, "hipSetDevice");
+    return b->dtype == PFC_F64 ? batch_step_impl<double>(b, nsteps, (hipStream_t)stream)
+                               : batch_step_impl<float>(b, nsteps, (hipStream_t)stream);
+}
+
+pfc_status pfc_batch_check(pfc_batch *b, void *stream)
+{
+    if (!b || !b->ws) return fail(PFC_ERR_WORKSPACE, "batch not bound");
+    DeviceGuard dg(b->device);
+    if (dg.err != hipSuccess) return hip_fail(dg.err, "hipSetDevice");
+    PFC_TRY(hipStreamSynchronize((hipStream_t)stream), "stream synchronize");
+    pfc::BatchCtl ctl;
+    PFC_TRY(hipMemcpy(&ctl, b->ws + b->ctl_off, sizeof ctl, hipMemcpyDeviceToHost), "barrier state read");
+    if (ctl.err) {
+        PFC_TRY(hipMemset(b->ws + b->ctl_off, 0, sizeof ctl), "barrier state reset");
+        return fail(PFC_ERR_INTERNAL, "a grid barrier of the batched kernel timed out (workgroups not all resident); "
+                    "results of that launch are incomplete");
+    }
+    return PFC_OK;
+}
+
+pfc_status pfc_batch_destroy(pfc_batch *b)
+{
+    if (!b) return PFC_OK;
+    drop_graphs(b);
+    if (b->cap) (void)hipStreamDestroy(b->cap);
+    delete b;
+    return PFC_OK;
 }
 
 const char *pfc_status_string(pfc_status st)

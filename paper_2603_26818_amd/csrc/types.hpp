@@ -22,4 +22,40 @@ struct ModelParams {
     int model;
 };
 
+// ---- batched persistent form (one entry per instance, in device memory)
+template <typename T>
+struct BatchInst {
+    T *psi;
+    cx<T> *state;
+    cx<T> *scratch;
+    int n0;          // y length (last-axis FFT length)
+    int M;           // x length / 2
+    int W;           // active pencils per y item
+    int tiles;       // y items (M / W)
+    int x_items;     // x r2c items
+    int c_items;     // x c2r items
+    int x_begin, y_begin, c_begin;  // first global item of this instance in each pass
+    T sc;            // 1 / (n0 M)
+    ModelParams<T> mp;
+};
+
+struct BatchCtl {
+    unsigned count;
+    unsigned gen;
+    int err;
+    int pad;
+};
+
+template <typename T>
+struct BatchArgs {
+    const BatchInst<T> *inst;  // sorted largest first
+    int ninst;
+    int x_total, y_total, c_total;
+    const cx<T> *tw;
+    int lt_shift;
+    BatchCtl *ctl;
+    unsigned long long max_polls;
+    int64_t nsteps;
+};
+
 }  // namespace pfc

@@ -1,0 +1,84 @@
+"""Batched persistent form (pfc_batch_*): every instance equals its own single-plan run.
+
+The batched kernel runs the same per-element arithmetic as the single-plan path (same FFT
+schedules, same twiddle values, same update), so each instance must match pfc_step bit for bit,
+after every replay of the captured graph; the single-plan path is checked against the oracle in
+test_gpu_step.py, and one instance is also checked against the oracle here."""
+import numpy as np
+import pytest
+
+import oracle
+import pfc_inputs as P
+from gpu_common import relerr, rounded, say, to_dev, to_np
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def pfc():
+    import paper_2603_26818_amd as m
+
+    m.load_library()
+    return m
+
+
+def _instances(dtype):
+    sizes = [(1024, 1024), (512, 512), (256, 128), (128, 256), (64, 64), (32, 1024), (128, 128), (512, 64)]
+    out = []
+    for i, shp in enumerate(sizes):
+        two = i % 2 == 1
+        r = float(P.uniform(P.derive_seed(4, i), (1,), -0.35, -0.15)[0])
+        out.append(dict(shape=shp, dtype=dtype, model=1 if two else 0, r=r, dt=0.25,
+                        q1sq=2.0 if two else 4.0 / 3.0, R1=0.05 if two else 0.0))
+    return out
+
+
+@pytest.mark.parametrize("dtype", ["f32", "f64"])
+def test_batch_matches_single_plans_every_replay(pfc, dtype):
+    import torch
+
+    insts = _instances(dtype)
+    say(f"[batch] {len(insts)} instances dtype={dtype}")
+    psi0 = [rounded(P.pfc_initial_field(P.derive_seed(4, 100 + i), d["shape"], d["r"]), dtype) for i, d in enumerate(insts)]
+    b = pfc.Batch(insts)
+    psis = [to_dev(x, dtype) for x in psi0]
+    b.bind(psis)
+    b.state_init()
+    say(f"        grid {b.grid} workgroups")
+    # single-plan runs of the same instances (eager launches)
+    plans = [pfc.Plan(d["shape"], dtype=dtype, model=d["model"], r=d["r"], dt=d["dt"], q1sq=d["q1sq"], R1=d["R1"])
+             for d in insts]
+    ref_psi = [to_dev(x, dtype) for x in psi0]
+    ref_state = [p.state_init(x) for p, x in zip(plans, ref_psi)]
+    torch.cuda.synchronize()
+    for k in range(len(insts)):
+        assert torch.equal(b.state[k], ref_state[k]), f"state_init differs for instance {k}"
+    for rep in range(3):
+        b.step(7)  # graph replay
+        b.check()
+        for p, x, s in zip(plans, ref_psi, ref_state):
+            p.step(x, s, 7)
+        torch.cuda.synchronize()
+        for k in range(len(insts)):
+            same = torch.equal(b.psi[k], ref_psi[k]) and torch.equal(b.state[k], ref_state[k])
+            if not same:
+                e = relerr(to_np(b.psi[k]), to_np(ref_psi[k]))
+                raise AssertionError(f"replay {rep}: instance {k} {insts[k]['shape']} differs (rel L2 {e:.2e})")
+        say(f"        replay {rep}: all instances bitwise equal to their single-plan runs")
+
+
+def test_batch_instance_vs_oracle(pfc):
+    insts = _instances("f64")[4:6]  # 64 x 64 two-mode? and 32 x 1024
+    say(f"[batch] oracle check of {[d['shape'] for d in insts]}")
+    psi0 = [P.pfc_initial_field(P.derive_seed(4, 200 + i), d["shape"], d["r"]) for i, d in enumerate(insts)]
+    b = pfc.Batch(insts)
+    b.bind([to_dev(x, "f64") for x in psi0])
+    b.state_init()
+    b.step(60)
+    b.check()
+    for k, d in enumerate(insts):
+        p = oracle.Params(d["shape"], model=d["model"], r=d["r"], dt=d["dt"], q1sq=d["q1sq"], R1=d["R1"])
+        ref, _ = oracle.step(p, psi0[k], oracle.state_init(p, psi0[k]), 60)
+        e = relerr(to_np(b.psi[k]), ref)
+        say(f"        instance {d['shape']}: rel L2 {e:.2e}")
+        assert e < 1e-12
