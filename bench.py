@@ -55,6 +55,96 @@ def measured_traffic(kernel):
     return t["kernels"][kernel].get("hbm_bytes_per_launch")
 
 
+def batched_instances():
+    """48 independent 2D runs: {128^2, 256^2, 512^2, 1024^2} x 12, six one-mode and six two-mode
+    (Q1^2 = 2, R1 = 0.05) per size, r_i ~ U(-0.35, -0.15) from sub-stream (4, i), dt = 0.25, FP32."""
+    import pfc_inputs
+
+    out = []
+    i = 0
+    for n in (128, 256, 512, 1024):
+        for j in range(12):
+            two = j >= 6
+            r = float(pfc_inputs.uniform(pfc_inputs.derive_seed(4, i), (1,), -0.35, -0.15)[0])
+            out.append(dict(shape=(n, n), dtype="f32", model=1 if two else 0, r=r, dt=0.25,
+                            q1sq=2.0 if two else 4.0 / 3.0, R1=0.05 if two else 0.0))
+            i += 1
+    return out
+
+
+def bench_batched(nsteps):
+    import torch
+
+    import paper_2603_26818_amd as pfc
+    import pfc_inputs
+
+    insts = batched_instances()
+    psis = [pfc_inputs.pfc_initial_field_torch(pfc_inputs.derive_seed(4, 1000 + i), d["shape"], d["r"],
+                                               torch.float32, "cuda:0") for i, d in enumerate(insts)]
+    b = pfc.Batch(insts).bind(psis)
+    b.state_init()
+    b.step(nsteps)  # captures the graph for this nsteps and warms up
+    b.check()
+    stream = torch.cuda.current_stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    b.step(nsteps)
+    e1.record(stream)
+    b.check()
+    ms = e0.elapsed_time(e1)
+    pts = sum(d["shape"][0] * d["shape"][1] for d in insts)
+    # the same 48 runs as separate single-plan launches (3 kernels per instance per step), for reference
+    plans = [pfc.Plan(d["shape"], dtype="f32", model=d["model"], r=d["r"], dt=d["dt"], q1sq=d["q1sq"], R1=d["R1"])
+             for d in insts]
+    states = [p.state_init(x) for p, x in zip(plans, psis)]
+    ref_steps = min(nsteps, 100)
+    torch.cuda.synchronize()
+    e0.record(stream)
+    for _ in range(ref_steps):
+        for p, x, st in zip(plans, psis, states):
+            p.step(x, st, 1)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms_sep = e0.elapsed_time(e1) / ref_steps
+    return {"workload": "48 2D runs {128^2,256^2,512^2,1024^2}x12, one-/two-mode, FP32, dt=0.25", "steps": nsteps,
+            "ms": round(ms, 3), "batch_steps_per_s": round(1000.0 * nsteps / ms, 1),
+            "points_per_step": pts, "alg_gbps": round(32.0 * pts * nsteps / ms / 1e6, 1),
+            "grid_workgroups": b.grid,
+            "separate_launches_ms_per_step": round(ms_sep, 4),
+            "separate_launches_steps_per_s": round(1000.0 / ms_sep, 1)}
+
+
+def bench_adjoint(nsteps, every):
+    import torch
+
+    import paper_2603_26818_amd as pfc
+    import pfc_inputs
+
+    shape = (512, 512)
+    plan_t = pfc.Plan(shape, dtype="f32", r=-0.30, dt=0.5)
+    psi0 = pfc_inputs.pfc_initial_field_torch(5, shape, -0.25, torch.float32, "cuda:0")
+    target = psi0.clone()
+    plan_t.step(target, plan_t.state_init(target), nsteps)
+    plan = pfc.Plan(shape, dtype="f32", r=-0.25, dt=0.5)
+    pfc.loss_and_grad(plan, psi0, -0.25, target, 100, every)  # warm-up
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    L, g, dr = pfc.loss_and_grad(plan, psi0, -0.25, target, nsteps, every)
+    torch.cuda.synchronize()
+    t = time.perf_counter() - t0
+    x = psi0.clone()
+    st = plan.state_init(x)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    plan.step(x, st, nsteps)
+    torch.cuda.synchronize()
+    tf = time.perf_counter() - t1
+    return {"workload": "2D 512^2 FP32, dt=0.5, loss on psi(T), grads w.r.t. psi0 and r, checkpoints every "
+                        f"{every}", "steps": nsteps, "fwd_bwd_s": round(t, 4),
+            "fwd_bwd_steps_per_s": round(nsteps / t, 1), "forward_only_steps_per_s": round(nsteps / tf, 1),
+            "dL_dr": dr}
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -63,6 +153,8 @@ def main():
     ap.add_argument("--profile-steps", type=int, default=30, help="steps of the per-pass timed run")
     ap.add_argument("--fft-reps", type=int, default=20)
     ap.add_argument("--cpu-steps", type=int, default=3, help="oracle steps of the CPU baseline (0: skip)")
+    ap.add_argument("--batch-steps", type=int, default=500, help="steps of the batched form (0: skip)")
+    ap.add_argument("--adjoint-steps", type=int, default=2000, help="steps of the adjoint form (0: skip)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path (see DESIGN.md for how the "
@@ -150,6 +242,17 @@ def main():
            "alg_bytes": fft_bytes, "roundtrip_rel_l2": rt_err}
     del x, X, y
 
+    batched = None
+    if args.batch_steps > 0:
+        log(f"[bench] batched form: 48 instances, {args.batch_steps} steps")
+        batched = bench_batched(args.batch_steps)
+        log(f"[bench] batched {batched['batch_steps_per_s']} batch steps/s")
+    adjoint = None
+    if args.adjoint_steps > 0:
+        log(f"[bench] adjoint form: 512^2, {args.adjoint_steps} steps")
+        adjoint = bench_adjoint(args.adjoint_steps, 50)
+        log(f"[bench] adjoint {adjoint['fwd_bwd_steps_per_s']} steps/s forward+backward")
+
     cpu = None
     if args.cpu_steps > 0:
         import oracle
@@ -173,7 +276,8 @@ def main():
         "vs_baseline": None, "dtype": "f32", "data": "synthetic",
         "config": {"workload": "3D one-mode PFC step, 512^3 periodic grid, FP32, dx=pi/4, r=-0.30, dt=0.5, "
                                "psi0=-0.30+U(-0.1,0.1) SplitMix64 seed 23", "grid": list(shape)},
-        "roofline": roofline, "cpu_baseline": cpu, "fft": fft, "passes": passes,
+        "roofline": roofline, "cpu_baseline": cpu, "fft": fft, "passes": passes, "batched": batched,
+        "adjoint": adjoint,
         "step_alg_gbps": round(step_bytes / ms_per_step / 1e6, 1),
         "step_frac": round(step_bytes / ms_per_step / 1e6 / PEAK_HBM_GBPS, 4),
         "energy_after": F[0],

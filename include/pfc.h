@@ -124,6 +124,21 @@ pfc_status pfc_step(pfc_plan *p, void *psi, void *state, int64_t nsteps, void *s
 pfc_status pfc_step_timed(pfc_plan *p, void *psi, void *state, int64_t nsteps, void *stream, double *pass_ms,
                           int *npasses);
 
+/* Autotuner: every pass of the step has a few candidate radix schedules compiled in (tile shapes
+ * follow from the schedule: rows per workgroup of the x passes, 128-byte column tiles of the strided
+ * passes).  Times each candidate of each pass (`reps` launches after one warm-up, events on
+ * `stream`) on this plan's shape and keeps the fastest in the plan; best_ms (5 doubles, may be NULL)
+ * receives the winning average time per pass.  psi_scratch (real field) and state_scratch (native
+ * state) are caller-owned scratch of the plan's sizes: their contents are overwritten; they should
+ * hold a finite field and its state (values do not change the timing).  Blocks until done. */
+pfc_status pfc_plan_autotune(pfc_plan *p, void *psi_scratch, void *state_scratch, void *stream, int reps,
+                             double *best_ms);
+
+/* The candidate chosen for each step pass (variants: 5 ints; *npasses as in pfc_step_timed), and
+ * setting them back (e.g. from a cache of earlier tuning); set rejects out-of-range candidates. */
+pfc_status pfc_plan_get_tuning(const pfc_plan *p, int *variants, int *npasses);
+pfc_status pfc_plan_set_tuning(pfc_plan *p, const int *variants, int npasses);
+
 /* Transpose of the Jacobian of one step, applied to lambda_np1 (the adjoint of psi^{n+1}):
  *     lambda_n = S_A lambda - 3 dt (psi_n)^2 .* S_K S_A lambda,
  * where S_A and S_K are the real symmetric Fourier multipliers A = 1/(1 + dt q (r + L(q))) and q.

@@ -67,6 +67,10 @@ _SIGS = {
     "pfc_step_timed": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64,
                                       ctypes.c_void_p, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int)]),
     "pfc_step_backward": (ctypes.c_int, [ctypes.c_void_p] * 7),
+    "pfc_plan_autotune": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                         ctypes.c_int, ctypes.POINTER(ctypes.c_double)]),
+    "pfc_plan_get_tuning": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int)]),
+    "pfc_plan_set_tuning": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_int), ctypes.c_int]),
     "pfc_energy": (ctypes.c_int, [ctypes.c_void_p] * 5),
     "pfc_batch_create": (ctypes.c_int, [ctypes.POINTER(ctypes.c_void_p), ctypes.POINTER(PlanDesc), ctypes.c_int]),
     "pfc_batch_workspace_bytes": (ctypes.c_size_t, [ctypes.c_void_p]),
@@ -271,6 +275,53 @@ class Plan:
                                     self._tensor(state, self.state_shape, self.complex_dtype, "state"),
                                     ctypes.c_void_p(out.data_ptr()), _stream_ptr(self.device)), "pfc_energy")
         return out
+
+    # ---------------------------------------------------------------- autotuner
+    def get_tuning(self):
+        v = (ctypes.c_int * 5)()
+        n = ctypes.c_int(0)
+        _check(self._lib.pfc_plan_get_tuning(self._h, v, ctypes.byref(n)), "pfc_plan_get_tuning")
+        return [v[i] for i in range(n.value)]
+
+    def set_tuning(self, variants):
+        v = (ctypes.c_int * 5)(*list(variants))
+        _check(self._lib.pfc_plan_set_tuning(self._h, v, len(variants)), "pfc_plan_set_tuning")
+
+    def tuning_key(self):
+        arch = _torch().cuda.get_device_properties(self.device).gcnArchName.split(":")[0]
+        return f"{arch}|{'x'.join(map(str, self.shape))}|{'f64' if self.f64 else 'f32'}"
+
+    def autotune(self, reps=5, cache_path=None):
+        """Pick the fastest candidate schedule of each step pass (pfc_plan_autotune) on scratch
+        fields; with cache_path, reuse / record the choice in a JSON file keyed by GPU arch, shape
+        and dtype.  Returns (variants, best ms per pass or None when taken from the cache)."""
+        import json
+
+        torch = _torch()
+        key = self.tuning_key()
+        cache = {}
+        if cache_path and os.path.exists(cache_path):
+            with open(cache_path) as f:
+                cache = json.load(f)
+            if key in cache:
+                self.set_tuning(cache[key]["variants"])
+                return cache[key]["variants"], None
+        g = torch.Generator(device=self.device).manual_seed(0)
+        psi = (-0.3 + 0.2 * (torch.rand(self.shape, generator=g, device=self.device, dtype=torch.float64) - 0.5))
+        psi = psi.to(self.real_dtype)
+        state = self.state_init(psi)
+        best = (ctypes.c_double * 5)()
+        _check(self._lib.pfc_plan_autotune(self._h, ctypes.c_void_p(psi.data_ptr()), ctypes.c_void_p(state.data_ptr()),
+                                           _stream_ptr(self.device), int(reps), best), "pfc_plan_autotune")
+        variants = self.get_tuning()
+        best_ms = [best[i] for i in range(len(variants))]
+        if cache_path:
+            cache[key] = {"variants": variants, "best_ms": best_ms}
+            tmp = cache_path + ".tmp"
+            with open(tmp, "w") as f:
+                json.dump(cache, f, indent=1, sort_keys=True)
+            os.replace(tmp, cache_path)
+        return variants, best_ms
 
     def set_params(self, r, dt):
         _check(self._lib.pfc_plan_set_params(self._h, float(r), float(dt)), "pfc_plan_set_params")

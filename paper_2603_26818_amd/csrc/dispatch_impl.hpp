@@ -37,42 +37,47 @@ static hipError_t by_length(int64_t L, F &&f)
 static inline int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
 
 template <typename T>
-hipError_t launch_x_r2c(const Geom &g, const T *in, cx<T> *out, bool cube, const cx<T> *tw, hipStream_t s)
+hipError_t launch_x_r2c(const Geom &g, const T *in, cx<T> *out, bool cube, const cx<T> *tw, hipStream_t s,
+                        int variant)
 {
-    if (g.M > 1024) return hipErrorInvalidValue;
     return by_length(g.M, [&](auto Mc) -> hipError_t {
         constexpr int M = decltype(Mc)::value;
         if constexpr (M > 1024) {
             return hipErrorInvalidValue;
         } else {
-            using PL = typename XFwdPlan<M>::type;
-            constexpr int ROWS = XRows<PL>::value;
-            const dim3 grid((unsigned)cdiv(g.xrows, ROWS)), block(ROWS * PL::Tp);
-            if (cube)
-                hipLaunchKernelGGL((x_r2c_kernel<T, PL, ROWS, true>), grid, block, 0, s, in, out, g.xrows, tw, g.lt_shift);
-            else
-                hipLaunchKernelGGL((x_r2c_kernel<T, PL, ROWS, false>), grid, block, 0, s, in, out, g.xrows, tw, g.lt_shift);
-            return hipGetLastError();
+            auto run = [&](auto plc, auto cubec) -> hipError_t {
+                using PL = decltype(plc);
+                constexpr bool CUBE = decltype(cubec)::value;
+                constexpr int ROWS = XRows<PL>::value;
+                const dim3 grid((unsigned)cdiv(g.xrows, ROWS)), block(ROWS * PL::Tp);
+                hipLaunchKernelGGL((x_r2c_kernel<T, PL, ROWS, CUBE>), grid, block, 0, s, in, out, g.xrows, tw,
+                                   g.lt_shift);
+                return hipGetLastError();
+            };
+            if (!cube) return run(typename XFwdPlan<M>::type{}, std::false_type{});
+            return with_plan<typename XFwdCands<M>::type>(variant, [&](auto plc) { return run(plc, std::true_type{}); });
         }
     });
 }
 
 template <typename T>
-hipError_t launch_x_c2r(const Geom &g, const cx<T> *in, T *out, const cx<T> *tw, hipStream_t s)
+hipError_t launch_x_c2r(const Geom &g, const cx<T> *in, T *out, const cx<T> *tw, hipStream_t s, int variant)
 {
     return by_length(g.M, [&](auto Mc) -> hipError_t {
         constexpr int M = decltype(Mc)::value;
         if constexpr (M > 1024) {
             return hipErrorInvalidValue;
         } else {
-            using PL = typename XInvPlan<M>::type;
-            constexpr int ROWS = XRows<PL>::value;
-            const dim3 grid((unsigned)cdiv(g.xrows, ROWS)), block(ROWS * PL::Tp);
-            const T sc = (T)(1.0 / ((double)g.M * (double)g.n0 * (double)g.nrows));
-            AdjEpi<T> ea{};
-            hipLaunchKernelGGL((x_c2r_kernel<T, PL, ROWS, EPI_PLAIN>), grid, block, 0, s, in, out, g.xrows, tw,
-                               g.lt_shift, sc, ea);
-            return hipGetLastError();
+            return with_plan<typename XInvCands<M>::type>(variant, [&](auto plc) -> hipError_t {
+                using PL = decltype(plc);
+                constexpr int ROWS = XRows<PL>::value;
+                const dim3 grid((unsigned)cdiv(g.xrows, ROWS)), block(ROWS * PL::Tp);
+                const T sc = (T)(1.0 / ((double)g.M * (double)g.n0 * (double)g.nrows));
+                AdjEpi<T> ea{};
+                hipLaunchKernelGGL((x_c2r_kernel<T, PL, ROWS, EPI_PLAIN>), grid, block, 0, s, in, out, g.xrows, tw,
+                                   g.lt_shift, sc, ea);
+                return hipGetLastError();
+            });
         }
     });
 }
@@ -101,25 +106,27 @@ hipError_t launch_x_c2r_adjoint(const Geom &g, const cx<T> *mu, const cx<T> *nu,
 }
 
 template <typename T>
-hipError_t launch_y_c2c(const Geom &g, cx<T> *data, int dir, const cx<T> *tw, hipStream_t s)
+hipError_t launch_y_c2c(const Geom &g, cx<T> *data, int dir, const cx<T> *tw, hipStream_t s, int variant)
 {
     return by_length(g.n1, [&](auto Lc) -> hipError_t {
         constexpr int L = decltype(Lc)::value;
         if constexpr (L < 4) {
             return hipErrorInvalidValue;
         } else {
-            using PL = typename AxisPlan<L>::type;
-            constexpr int WM = WMax<T, L>::value;
-            const int W = (int)(g.M < WM ? g.M : WM);
-            const int64_t tiles = cdiv(g.M, W);
-            const dim3 grid((unsigned)(tiles * g.n0)), block(WM * PL::Tp);
-            if (dir < 0)
-                hipLaunchKernelGGL((axis_c2c_kernel<T, PL, WM, -1>), grid, block, 0, s, data, data, W, g.M, g.M,
-                                   g.n1 * g.M, tiles, tw, g.lt_shift);
-            else
-                hipLaunchKernelGGL((axis_c2c_kernel<T, PL, WM, +1>), grid, block, 0, s, data, data, W, g.M, g.M,
-                                   g.n1 * g.M, tiles, tw, g.lt_shift);
-            return hipGetLastError();
+            return with_plan<typename AxisCands<L>::type>(variant, [&](auto plc) -> hipError_t {
+                using PL = decltype(plc);
+                constexpr int WM = WMax<T, L>::value;
+                const int W = (int)(g.M < WM ? g.M : WM);
+                const int64_t tiles = cdiv(g.M, W);
+                const dim3 grid((unsigned)(tiles * g.n0)), block(WM * PL::Tp);
+                if (dir < 0)
+                    hipLaunchKernelGGL((axis_c2c_kernel<T, PL, WM, -1>), grid, block, 0, s, data, data, W, g.M, g.M,
+                                       g.n1 * g.M, tiles, tw, g.lt_shift);
+                else
+                    hipLaunchKernelGGL((axis_c2c_kernel<T, PL, WM, +1>), grid, block, 0, s, data, data, W, g.M, g.M,
+                                       g.n1 * g.M, tiles, tw, g.lt_shift);
+                return hipGetLastError();
+            });
         }
     });
 }
@@ -147,14 +154,13 @@ hipError_t launch_last_fwd(const Geom &g, const cx<T> *src, cx<T> *dst, const cx
 
 template <typename T>
 hipError_t launch_last(const Geom &g, int mode, const cx<T> *src, cx<T> *dst, cx<T> *dst2, cx<T> *state,
-                       const ModelParams<T> &mp, const cx<T> *tw, hipStream_t s)
+                       const ModelParams<T> &mp, const cx<T> *tw, hipStream_t s, int variant)
 {
     return by_length(g.n0, [&](auto Lc) -> hipError_t {
         constexpr int L = decltype(Lc)::value;
         if constexpr (L < 4) {
             return hipErrorInvalidValue;
         } else {
-            using PL = typename LastPlan<L>::type;
             constexpr int WM = WMax<T, L>::value;
             LastAxisArgs<T> a;
             a.src = src;
@@ -169,19 +175,23 @@ hipError_t launch_last(const Geom &g, int mode, const cx<T> *src, cx<T> *dst, cx
             a.lt_shift = g.lt_shift;
             a.mp = mp;
             const int64_t nblocks = (g.nrows == 1) ? a.tiles_per_row : g.nrows * a.tiles_per_row;
-            const dim3 grid((unsigned)nblocks), block(WM * PL::Tp);
+            const dim3 grid((unsigned)nblocks);
+            using P0 = typename LastPlan<L>::type;
             switch (mode) {
             case LAST_STEP:
-                hipLaunchKernelGGL((last_axis_kernel<T, PL, WM, LA_STEP>), grid, block, 0, s, a);
-                break;
+                return with_plan<typename LastCands<L>::type>(variant, [&](auto plc) -> hipError_t {
+                    using PL = decltype(plc);
+                    hipLaunchKernelGGL((last_axis_kernel<T, PL, WM, LA_STEP>), grid, dim3(WM * PL::Tp), 0, s, a);
+                    return hipGetLastError();
+                });
             case LAST_R2C_NATURAL:
-                hipLaunchKernelGGL((last_axis_kernel<T, PL, WM, LA_R2C_NATURAL>), grid, block, 0, s, a);
+                hipLaunchKernelGGL((last_axis_kernel<T, P0, WM, LA_R2C_NATURAL>), grid, dim3(WM * P0::Tp), 0, s, a);
                 break;
             case LAST_C2R_NATURAL:
-                hipLaunchKernelGGL((last_axis_kernel<T, PL, WM, LA_C2R_NATURAL>), grid, block, 0, s, a);
+                hipLaunchKernelGGL((last_axis_kernel<T, P0, WM, LA_C2R_NATURAL>), grid, dim3(WM * P0::Tp), 0, s, a);
                 break;
             case LAST_ADJOINT:
-                hipLaunchKernelGGL((last_axis_kernel<T, PL, WM, LA_ADJOINT>), grid, block, 0, s, a);
+                hipLaunchKernelGGL((last_axis_kernel<T, P0, WM, LA_ADJOINT>), grid, dim3(WM * P0::Tp), 0, s, a);
                 break;
             default: return hipErrorInvalidValue;
             }
@@ -227,14 +237,14 @@ hipError_t launch_export(const Geom &g, const cx<T> *state, cx<T> *out, hipStrea
 }
 
 #define PFC_INSTANTIATE(T)                                                                                            \
-    template hipError_t launch_x_r2c<T>(const Geom &, const T *, cx<T> *, bool, const cx<T> *, hipStream_t);          \
-    template hipError_t launch_x_c2r<T>(const Geom &, const cx<T> *, T *, const cx<T> *, hipStream_t);                \
+    template hipError_t launch_x_r2c<T>(const Geom &, const T *, cx<T> *, bool, const cx<T> *, hipStream_t, int);     \
+    template hipError_t launch_x_c2r<T>(const Geom &, const cx<T> *, T *, const cx<T> *, hipStream_t, int);           \
     template hipError_t launch_x_c2r_adjoint<T>(const Geom &, const cx<T> *, const cx<T> *, const T *, const T *, T *, \
                                                 T, double *, int64_t *, const cx<T> *, hipStream_t);                  \
-    template hipError_t launch_y_c2c<T>(const Geom &, cx<T> *, int, const cx<T> *, hipStream_t);                      \
+    template hipError_t launch_y_c2c<T>(const Geom &, cx<T> *, int, const cx<T> *, hipStream_t, int);                 \
     template hipError_t launch_last_fwd<T>(const Geom &, const cx<T> *, cx<T> *, const cx<T> *, hipStream_t);         \
     template hipError_t launch_last<T>(const Geom &, int, const cx<T> *, cx<T> *, cx<T> *, cx<T> *,                   \
-                                       const ModelParams<T> &, const cx<T> *, hipStream_t);                           \
+                                       const ModelParams<T> &, const cx<T> *, hipStream_t, int);                      \
     template hipError_t launch_set_mass<T>(const T *, int64_t, double *, cx<T> *, hipStream_t);                       \
     template hipError_t launch_energy<T>(const Geom &, const T *, const cx<T> *, const double *, double, double,      \
                                          double, int, double, double *, double *, hipStream_t);                       \

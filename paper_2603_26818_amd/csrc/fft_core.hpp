@@ -147,15 +147,59 @@ template <> struct DefaultPlan<512> { using type = Radices<8, 8, 8>; };
 template <> struct DefaultPlan<1024> { using type = Radices<8, 8, 16>; };
 template <> struct DefaultPlan<2048> { using type = Radices<8, 16, 16>; };
 
-// Schedules per pass kind (measured on MI355X at 512^3 FP32; other lengths use DefaultPlan until
-// tuned).  x forward (r2c, contiguous rows), x inverse (c2r), strided middle axis, last axis.
-template <int M> struct XFwdPlan { using type = typename DefaultPlan<M>::type; };
-template <int M> struct XInvPlan { using type = typename DefaultPlan<M>::type; };
-template <> struct XInvPlan<256> { using type = Radices<8, 4, 8>; };
-template <int L> struct AxisPlan { using type = typename DefaultPlan<L>::type; };
-template <> struct AxisPlan<512> { using type = Radices<16, 2, 16>; };
-template <int L> struct LastPlan { using type = typename DefaultPlan<L>::type; };
-template <> struct LastPlan<512> { using type = Radices<2, 16, 16>; };
+// Candidate schedules per pass kind and length.  Candidate 0 is the default (measured best on
+// MI355X at 512^3 FP32 where the lengths occur there); the autotuner may pick another per plan.
+template <class... Ps>
+struct PlanList {
+    static constexpr int size = sizeof...(Ps);
+};
+template <int I, class List>
+struct ListAt;
+template <class P, class... Ps>
+struct ListAt<0, PlanList<P, Ps...>> {
+    using type = P;
+};
+template <int I, class P, class... Ps>
+struct ListAt<I, PlanList<P, Ps...>> {
+    using type = typename ListAt<I - 1, PlanList<Ps...>>::type;
+};
+
+// generic candidates: the default schedule and, from 16 up, one alternative split
+template <int L> struct AltPlans { using type = PlanList<typename DefaultPlan<L>::type>; };
+template <> struct AltPlans<16> { using type = PlanList<Radices<4, 4>, Radices<16>>; };
+template <> struct AltPlans<32> { using type = PlanList<Radices<8, 4>, Radices<4, 8>>; };
+template <> struct AltPlans<64> { using type = PlanList<Radices<8, 8>, Radices<4, 16>>; };
+template <> struct AltPlans<128> { using type = PlanList<Radices<8, 16>, Radices<16, 8>>; };
+template <> struct AltPlans<256> { using type = PlanList<Radices<16, 16>, Radices<4, 8, 8>>; };
+template <> struct AltPlans<512> { using type = PlanList<Radices<8, 8, 8>, Radices<16, 2, 16>>; };
+template <> struct AltPlans<1024> { using type = PlanList<Radices<8, 8, 16>, Radices<16, 4, 16>>; };
+template <> struct AltPlans<2048> { using type = PlanList<Radices<8, 16, 16>, Radices<16, 8, 16>>; };
+
+// x forward (r2c, contiguous rows), x inverse (c2r), strided middle axis, last axis
+template <int M> struct XFwdCands { using type = typename AltPlans<M>::type; };
+template <int M> struct XInvCands { using type = typename AltPlans<M>::type; };
+template <> struct XInvCands<256> { using type = PlanList<Radices<8, 4, 8>, Radices<16, 16>>; };
+template <int L> struct AxisCands { using type = typename AltPlans<L>::type; };
+template <> struct AxisCands<512> { using type = PlanList<Radices<16, 2, 16>, Radices<8, 8, 8>>; };
+template <int L> struct LastCands { using type = typename AltPlans<L>::type; };
+template <> struct LastCands<512> { using type = PlanList<Radices<2, 16, 16>, Radices<16, 16, 2>>; };
+
+template <int M> struct XFwdPlan { using type = typename ListAt<0, typename XFwdCands<M>::type>::type; };
+template <int M> struct XInvPlan { using type = typename ListAt<0, typename XInvCands<M>::type>::type; };
+template <int L> struct AxisPlan { using type = typename ListAt<0, typename AxisCands<L>::type>::type; };
+template <int L> struct LastPlan { using type = typename ListAt<0, typename LastCands<L>::type>::type; };
+
+// Calls f(PL{}) with the schedule number v of List (v out of range: candidate 0).
+template <class List, int I = 0, class F>
+__host__ __device__ __forceinline__ auto with_plan(int v, F &&f)
+{
+    if constexpr (I + 1 >= List::size) {
+        return f(typename ListAt<I, List>::type{});
+    } else {
+        if (v == I) return f(typename ListAt<I, List>::type{});
+        return with_plan<List, I + 1>(v, f);
+    }
+}
 
 // Twiddle W_{Ns R}^{m}, m = (j mod Ns) r, from the table of length Lt (forward sign); conjugated
 // for the inverse.

@@ -19,11 +19,14 @@ struct Geom {
     int lt_shift;        // log2 of the twiddle table length
 };
 
+// `variant`: candidate schedule of the pass (0 = default); only the step's passes (x r2c with the
+// cube, y forward/inverse, last-axis STEP, x c2r) have more than one candidate.
 template <typename T>
-hipError_t launch_x_r2c(const Geom &g, const T *in, cx<T> *out, bool cube, const cx<T> *tw, hipStream_t s);
+hipError_t launch_x_r2c(const Geom &g, const T *in, cx<T> *out, bool cube, const cx<T> *tw, hipStream_t s,
+                        int variant = 0);
 
 template <typename T>
-hipError_t launch_x_c2r(const Geom &g, const cx<T> *in, T *out, const cx<T> *tw, hipStream_t s);
+hipError_t launch_x_c2r(const Geom &g, const cx<T> *in, T *out, const cx<T> *tw, hipStream_t s, int variant = 0);
 
 // adjoint epilogue: out = mu - c3 psi_n^2 nu; partial[block] = sum nu psi_np1.  Returns the number
 // of partials through *nblocks.
@@ -33,7 +36,7 @@ hipError_t launch_x_c2r_adjoint(const Geom &g, const cx<T> *mu, const cx<T> *nu,
 
 // y-axis (3D middle axis) complex FFT, in place; dir = -1 forward, +1 inverse.
 template <typename T>
-hipError_t launch_y_c2c(const Geom &g, cx<T> *data, int dir, const cx<T> *tw, hipStream_t s);
+hipError_t launch_y_c2c(const Geom &g, cx<T> *data, int dir, const cx<T> *tw, hipStream_t s, int variant = 0);
 
 // last-axis complex FFT, forward, out of place, packed in and out (no update).
 template <typename T>
@@ -43,7 +46,11 @@ enum LastMode { LAST_STEP = 0, LAST_R2C_NATURAL = 1, LAST_C2R_NATURAL = 2, LAST_
 
 template <typename T>
 hipError_t launch_last(const Geom &g, int mode, const cx<T> *src, cx<T> *dst, cx<T> *dst2, cx<T> *state,
-                       const ModelParams<T> &mp, const cx<T> *tw, hipStream_t s);
+                       const ModelParams<T> &mp, const cx<T> *tw, hipStream_t s, int variant = 0);
+
+// number of candidate schedules of each step pass for this geometry (index as pfc_step_timed's
+// passes); used by the autotuner
+int step_candidates(const Geom &g, int pass);
 
 // reductions; every launcher uses exactly kReduceBlocks partials
 constexpr int kReduceBlocks = 1024;

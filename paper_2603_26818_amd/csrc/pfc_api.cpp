@@ -30,6 +30,7 @@ struct pfc_plan {
     size_t n_partials;
     char *ws = nullptr;
     size_t ws_bytes = 0;
+    int var[5] = {0, 0, 0, 0, 0};  // candidate schedule of each step pass (autotuner)
 };
 
 struct pfc_batch {
@@ -300,17 +301,18 @@ pfc_status step_pass(const pfc_plan *p, int pass, void *psi, void *state, hipStr
     const Geom &g = p->g;
     const Bufs<T> b = bufs<T>(p);
     const int id = (g.ndim == 3) ? pass : (pass == 0 ? 0 : pass == 1 ? 2 : 4);
+    const int v = p->var[pass];
     switch (id) {
-    case 0: PFC_TRY(pfc::launch_x_r2c<T>(g, (const T *)psi, b.scratch, true, b.tw, s), "x_r2c launch"); break;
-    case 1: PFC_TRY(pfc::launch_y_c2c<T>(g, b.scratch, -1, b.tw, s), "y forward launch"); break;
+    case 0: PFC_TRY(pfc::launch_x_r2c<T>(g, (const T *)psi, b.scratch, true, b.tw, s, v), "x_r2c launch"); break;
+    case 1: PFC_TRY(pfc::launch_y_c2c<T>(g, b.scratch, -1, b.tw, s, v), "y forward launch"); break;
     case 2: {
         const pfc::ModelParams<T> mp = model_params<T>(p);
-        PFC_TRY(pfc::launch_last<T>(g, pfc::LAST_STEP, b.scratch, b.scratch, nullptr, (cx<T> *)state, mp, b.tw, s),
+        PFC_TRY(pfc::launch_last<T>(g, pfc::LAST_STEP, b.scratch, b.scratch, nullptr, (cx<T> *)state, mp, b.tw, s, v),
                 "last-axis step launch");
         break;
     }
-    case 3: PFC_TRY(pfc::launch_y_c2c<T>(g, b.scratch, +1, b.tw, s), "y inverse launch"); break;
-    case 4: PFC_TRY(pfc::launch_x_c2r<T>(g, b.scratch, (T *)psi, b.tw, s), "x_c2r launch"); break;
+    case 3: PFC_TRY(pfc::launch_y_c2c<T>(g, b.scratch, +1, b.tw, s, v), "y inverse launch"); break;
+    case 4: PFC_TRY(pfc::launch_x_c2r<T>(g, b.scratch, (T *)psi, b.tw, s, v), "x_c2r launch"); break;
     default: return fail(PFC_ERR_INTERNAL, "bad pass %d", pass);
     }
     return PFC_OK;
@@ -358,6 +360,47 @@ pfc_status do_step_timed(pfc_plan *p, void *psi, void *state, int64_t nsteps, hi
         if (st == PFC_OK && e != hipSuccess) st = hip_fail(e, "timing events");
     }
     for (int k = 0; k < made; ++k) (void)hipEventDestroy(ev[k]);
+    return st;
+}
+
+// Times every candidate schedule of every step pass (`reps` launches each after one warm-up,
+// events on the stream) and keeps the fastest.  psi/state are scratch: their contents change.
+template <typename T>
+pfc_status do_autotune(pfc_plan *p, void *psi, void *state, hipStream_t s, int reps, double *best_ms)
+{
+    hipEvent_t e0, e1;
+    PFC_TRY(hipEventCreate(&e0), "hipEventCreate");
+    hipError_t ce = hipEventCreate(&e1);
+    if (ce != hipSuccess) {
+        (void)hipEventDestroy(e0);
+        return hip_fail(ce, "hipEventCreate");
+    }
+    pfc_status st = PFC_OK;
+    const int np = step_passes(p);
+    for (int k = 0; k < np && st == PFC_OK; ++k) {
+        const int nc = pfc::step_candidates(p->g, k);
+        int best = 0;
+        double best_t = INFINITY;
+        for (int c = 0; c < nc && st == PFC_OK; ++c) {
+            p->var[k] = c;
+            st = step_pass<T>(p, k, psi, state, s);  // warm-up
+            hipError_t e = hipEventRecord(e0, s);
+            for (int r = 0; r < reps && st == PFC_OK && e == hipSuccess; ++r) st = step_pass<T>(p, k, psi, state, s);
+            if (st == PFC_OK && e == hipSuccess) e = hipEventRecord(e1, s);
+            if (st == PFC_OK && e == hipSuccess) e = hipEventSynchronize(e1);
+            float ms = 0.f;
+            if (st == PFC_OK && e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+            if (st == PFC_OK && e != hipSuccess) st = hip_fail(e, "autotune timing");
+            if (st == PFC_OK && ms < best_t) {
+                best_t = ms;
+                best = c;
+            }
+        }
+        p->var[k] = best;
+        if (best_ms) best_ms[k] = best_t / reps;
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
     return st;
 }
 
@@ -725,6 +768,39 @@ pfc_status pfc_step_timed(pfc_plan *p, void *psi, void *state, int64_t nsteps, v
     if (overlap(psi, real_bytes(p), state, state_bytes(p))) return fail(PFC_ERR_INVALID_ARG, "psi and state overlap");
     *npasses = step_passes(p);
     PFC_DISPATCH(p, do_step_timed, p, psi, state, nsteps, (hipStream_t)stream, pass_ms);
+}
+
+pfc_status pfc_plan_autotune(pfc_plan *p, void *psi_scratch, void *state_scratch, void *stream, int reps,
+                             double *best_ms)
+{
+    PFC_CHECK(check_ready(p));
+    PFC_CHECK(check_ptr(psi_scratch, "psi_scratch"));
+    PFC_CHECK(check_ptr(state_scratch, "state_scratch"));
+    if (reps < 1) return fail(PFC_ERR_INVALID_ARG, "reps must be >= 1");
+    if (overlap(psi_scratch, real_bytes(p), state_scratch, state_bytes(p)))
+        return fail(PFC_ERR_INVALID_ARG, "psi_scratch and state_scratch overlap");
+    PFC_DISPATCH(p, do_autotune, p, psi_scratch, state_scratch, (hipStream_t)stream, reps, best_ms);
+}
+
+pfc_status pfc_plan_get_tuning(const pfc_plan *p, int *variants, int *npasses)
+{
+    if (!p || !variants || !npasses) return fail(PFC_ERR_INVALID_ARG, "NULL argument");
+    *npasses = step_passes(p);
+    for (int k = 0; k < *npasses; ++k) variants[k] = p->var[k];
+    return PFC_OK;
+}
+
+pfc_status pfc_plan_set_tuning(pfc_plan *p, const int *variants, int npasses)
+{
+    if (!p || !variants) return fail(PFC_ERR_INVALID_ARG, "NULL argument");
+    if (npasses != step_passes(p)) return fail(PFC_ERR_INVALID_ARG, "expected %d passes", step_passes(p));
+    for (int k = 0; k < npasses; ++k) {
+        const int nc = pfc::step_candidates(p->g, k);
+        if (variants[k] < 0 || variants[k] >= nc)
+            return fail(PFC_ERR_INVALID_ARG, "pass %d: variant %d out of [0, %d)", k, variants[k], nc);
+    }
+    for (int k = 0; k < npasses; ++k) p->var[k] = variants[k];
+    return PFC_OK;
 }
 
 pfc_status pfc_step_backward(pfc_plan *p, const void *psi_n, const void *psi_np1, const void *lambda_np1,

@@ -117,3 +117,20 @@ def test_status_strings():
     for code, name in enumerate(["PFC_OK", "PFC_ERR_INVALID_ARG", "PFC_ERR_UNSUPPORTED", "PFC_ERR_ALIGNMENT",
                                  "PFC_ERR_WORKSPACE", "PFC_ERR_HIP", "PFC_ERR_DIVERGED", "PFC_ERR_INTERNAL"]):
         assert lib.pfc_status_string(code).decode() == name
+
+
+def test_tuning_set_get_validation():
+    b, lib = _lib()
+    st, h = _create(b, lib, _desc(b, (32, 64, 512), 0))
+    assert st == 0
+    v = (ctypes.c_int * 5)()
+    n = ctypes.c_int()
+    assert lib.pfc_plan_get_tuning(h, v, ctypes.byref(n)) == 0 and n.value == 5 and list(v) == [0] * 5
+    assert lib.pfc_plan_set_tuning(h, (ctypes.c_int * 5)(1, 1, 1, 1, 1), 5) == 0
+    assert lib.pfc_plan_get_tuning(h, v, ctypes.byref(n)) == 0 and list(v) == [1] * 5
+    assert lib.pfc_plan_set_tuning(h, (ctypes.c_int * 5)(0, 0, 7, 0, 0), 5) == 1  # no such candidate
+    assert lib.pfc_plan_set_tuning(h, (ctypes.c_int * 5)(0, 0, 0, 0, 0), 3) == 1  # 3D has 5 passes
+    lib.pfc_plan_destroy(h)
+    st, h = _create(b, lib, _desc(b, (8, 4, 8), 0))  # lengths with a single candidate
+    assert lib.pfc_plan_set_tuning(h, (ctypes.c_int * 5)(0, 0, 1, 0, 0), 5) == 1
+    lib.pfc_plan_destroy(h)
