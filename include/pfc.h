@@ -116,6 +116,13 @@ pfc_status pfc_state_export(pfc_plan *p, const void *state, void *half_natural, 
  * one the cube is taken of; the state is the one the update is applied to. */
 pfc_status pfc_step(pfc_plan *p, void *psi, void *state, int64_t nsteps, void *stream);
 
+/* pfc_step with a divergence watchdog: after every `check_every` steps (and after the last) the FP64
+ * energy and mean of (psi, state) are computed (as pfc_energy, into the workspace) and copied to the
+ * host, which synchronises the stream.  A non-finite value stops the run with PFC_ERR_DIVERGED.
+ * *done_steps receives the number of steps run. */
+pfc_status pfc_step_watched(pfc_plan *p, void *psi, void *state, int64_t nsteps, int64_t check_every, void *stream,
+                            int64_t *done_steps);
+
 /* pfc_step with a HIP event recorded on `stream` around every kernel of every step, for
  * measurement.  pass_ms[i] receives the summed duration (ms) of pass i over all steps and *npasses
  * the number of passes per step: 3D 5 (x r2c with cube, y forward, z forward + update + z inverse,
@@ -183,6 +190,19 @@ pfc_status pfc_batch_step(pfc_batch *b, int64_t nsteps, void *stream);
 /* Synchronise `stream` and report whether a grid barrier of an earlier pfc_batch_step timed out
  * (PFC_ERR_INTERNAL; the barrier state is then cleared). */
 pfc_status pfc_batch_check(pfc_batch *b, void *stream);
+
+/* Autotuner of the batched form: for each pass kind (x forward, y, x inverse) and each distinct
+ * length among the instances, times every candidate radix schedule (which also sets the item shape:
+ * rows per x item, pencils per y item) by launching the persistent kernel for `steps` steps, and
+ * keeps the fastest.  THE BOUND FIELDS ARE ADVANCED by every trial: bind scratch fields to tune, then
+ * copy the choice to the production batch with pfc_batch_get/set_tuning.  *ms_per_step (may be NULL)
+ * receives the time per step of the final choice.  Blocks until done. */
+pfc_status pfc_batch_autotune(pfc_batch *b, void *stream, int steps, double *ms_per_step);
+
+/* Candidate per instance and pass: variants[3 i + k], k = 0 x forward, 1 y, 2 x inverse (caller's
+ * instance order); n = 3 * count.  Setting re-uploads the instance table when bound. */
+pfc_status pfc_batch_get_tuning(const pfc_batch *b, int *variants, int n);
+pfc_status pfc_batch_set_tuning(pfc_batch *b, const int *variants, int n);
 
 /* Number of persistent workgroups of the batch launch (known after pfc_batch_bind). */
 int pfc_batch_grid(const pfc_batch *b);

@@ -64,6 +64,8 @@ _SIGS = {
     "pfc_state_init": (ctypes.c_int, [ctypes.c_void_p] * 4),
     "pfc_state_export": (ctypes.c_int, [ctypes.c_void_p] * 4),
     "pfc_step": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p]),
+    "pfc_step_watched": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64,
+                                        ctypes.c_int64, ctypes.c_void_p, ctypes.POINTER(ctypes.c_int64)]),
     "pfc_step_timed": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64,
                                       ctypes.c_void_p, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int)]),
     "pfc_step_backward": (ctypes.c_int, [ctypes.c_void_p] * 7),
@@ -80,6 +82,9 @@ _SIGS = {
     "pfc_batch_step": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p]),
     "pfc_batch_check": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p]),
     "pfc_batch_grid": (ctypes.c_int, [ctypes.c_void_p]),
+    "pfc_batch_autotune": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int, ctypes.POINTER(ctypes.c_double)]),
+    "pfc_batch_get_tuning": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_int), ctypes.c_int]),
+    "pfc_batch_set_tuning": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_int), ctypes.c_int]),
     "pfc_batch_destroy": (ctypes.c_int, [ctypes.c_void_p]),
     "pfc_status_string": (ctypes.c_char_p, [ctypes.c_int]),
     "pfc_last_error": (ctypes.c_char_p, []),
@@ -241,6 +246,16 @@ class Plan:
                                   int(nsteps), _stream_ptr(self.device)), "pfc_step")
         return psi, state
 
+    def step_watched(self, psi, state, nsteps, check_every=50):
+        """pfc_step_watched: raises PfcError (PFC_ERR_DIVERGED) on a non-finite energy; returns the
+        number of steps run."""
+        done = ctypes.c_int64(0)
+        st = self._lib.pfc_step_watched(self._h, self._tensor(psi, self.shape, self.real_dtype, "psi"),
+                                        self._tensor(state, self.state_shape, self.complex_dtype, "state"),
+                                        int(nsteps), int(check_every), _stream_ptr(self.device), ctypes.byref(done))
+        _check(st, f"pfc_step_watched (after {done.value} steps)")
+        return done.value
+
     def step_timed(self, psi, state, nsteps=1):
         """pfc_step_timed: returns the summed milliseconds of each pass (list)."""
         ms = (ctypes.c_double * 5)()
@@ -399,6 +414,57 @@ class Batch:
 
     def check(self):
         _check(self._lib.pfc_batch_check(self._h, _stream_ptr(self.device)), "pfc_batch_check")
+
+    def get_tuning(self):
+        n = 3 * len(self.instances)
+        v = (ctypes.c_int * n)()
+        _check(self._lib.pfc_batch_get_tuning(self._h, v, n), "pfc_batch_get_tuning")
+        return [list(v[3 * i:3 * i + 3]) for i in range(len(self.instances))]
+
+    def set_tuning(self, per_instance):
+        flat = [int(x) for t in per_instance for x in t]
+        v = (ctypes.c_int * len(flat))(*flat)
+        _check(self._lib.pfc_batch_set_tuning(self._h, v, len(flat)), "pfc_batch_set_tuning")
+
+    def tuning_key(self):
+        arch = _torch().cuda.get_device_properties(self.device).gcnArchName.split(":")[0]
+        dt = "f64" if self.f64 else "f32"
+        return arch + "|batch|" + dt + "|" + ",".join("x".join(map(str, i["shape"])) for i in self.instances)
+
+    def autotune(self, steps=5, cache_path=None):
+        """Choose candidate schedules per pass and length (pfc_batch_autotune) on a scratch batch with
+        the same instances, then apply the choice here.  With cache_path, reuse / record it in a JSON
+        file.  Returns (per-instance variants, ms per step of the choice or None from the cache)."""
+        import json
+
+        torch = _torch()
+        key = self.tuning_key()
+        cache = {}
+        if cache_path and os.path.exists(cache_path):
+            with open(cache_path) as f:
+                cache = json.load(f)
+            if key in cache:
+                self.set_tuning(cache[key]["variants"])
+                return cache[key]["variants"], None
+        scratch = Batch(self.instances, device=self.device.index)
+        g = torch.Generator(device=self.device).manual_seed(0)
+        psis = [(i["r"] + 0.2 * (torch.rand(tuple(i["shape"]), generator=g, device=self.device,
+                                            dtype=torch.float64) - 0.5)).to(self.real_dtype) for i in self.instances]
+        scratch.bind(psis)
+        scratch.state_init()
+        ms = ctypes.c_double(0.0)
+        _check(self._lib.pfc_batch_autotune(scratch._h, _stream_ptr(self.device), int(steps), ctypes.byref(ms)),
+               "pfc_batch_autotune")
+        variants = scratch.get_tuning()
+        scratch.destroy()
+        self.set_tuning(variants)
+        if cache_path:
+            cache[key] = {"variants": variants, "ms_per_step": ms.value}
+            tmp = cache_path + ".tmp"
+            with open(tmp, "w") as f:
+                json.dump(cache, f, indent=1, sort_keys=True)
+            os.replace(tmp, cache_path)
+        return variants, ms.value
 
     def destroy(self):
         if getattr(self, "_h", None) is not None and self._h.value:

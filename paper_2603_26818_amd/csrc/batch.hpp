@@ -18,10 +18,8 @@ namespace pfc {
 constexpr int kBatchThreads = 512;
 constexpr int kBatchMaxInst = 256;
 
-// Schedules of the batched passes: NT / Tp rows (x passes) or pencils (y pass) per item.
-template <int M> struct BXFwd { using type = typename XFwdPlan<M>::type; };
-template <int M> struct BXInv { using type = typename XInvPlan<M>::type; };
-template <int L> struct BLast { using type = typename LastPlan<L>::type; };
+// Schedules of the batched passes: the same candidate lists as the single-plan passes; each item
+// has NT / Tp rows (x passes) or pencils (y pass).  Each instance records its candidate per pass.
 
 template <class PL>
 struct BRows {
@@ -91,17 +89,15 @@ __device__ __forceinline__ int find_inst(const BatchArgs<T> &a, int k)
 template <typename T>
 __device__ __forceinline__ cx<T> *batch_lds();
 
-template <typename T, int M>
+template <typename T, class PL>
 __device__ __noinline__ void batch_x_fwd(const BatchInst<T> *in, int item, const cx<T> *tw, int lt_shift)
 {
-    using PL = typename BXFwd<M>::type;
     x_r2c_block<T, PL, BRows<PL>::value, true>(in->psi, in->scratch, in->n0, tw, lt_shift, item, batch_lds<T>());
 }
 
-template <typename T, int L>
+template <typename T, class PL>
 __device__ __noinline__ void batch_y_step(const BatchInst<T> *in, int item, const cx<T> *tw, int lt_shift)
 {
-    using PL = typename BLast<L>::type;
     constexpr int WM = kBatchThreads / PL::Tp;
     LastAxisArgs<T> la;
     la.src = in->scratch;
@@ -118,51 +114,59 @@ __device__ __noinline__ void batch_y_step(const BatchInst<T> *in, int item, cons
     last_axis_block<T, PL, WM, LA_STEP>(la, item, batch_lds<T>());
 }
 
-template <typename T, int M>
+template <typename T, class PL>
 __device__ __noinline__ void batch_x_inv(const BatchInst<T> *in, int item, const cx<T> *tw, int lt_shift)
 {
-    using PL = typename BXInv<M>::type;
     AdjEpi<T> ea{};
     x_c2r_block<T, PL, BRows<PL>::value, EPI_PLAIN>(in->scratch, in->psi, in->n0, tw, lt_shift, in->sc, ea, item,
                                                      batch_lds<T>());
 }
 
 // supported lengths: x 32..1024 (M = 16..512), y 32..1024
+#define PFC_BCASE(LEN, CANDS, FN, VAR)                                                                       \
+    case LEN:                                                                                                \
+        with_plan<typename CANDS<LEN>::type>(VAR, [&](auto plc) {                                            \
+            FN<T, decltype(plc)>(in, item, tw, lt);                                                          \
+            return 0;                                                                                        \
+        });                                                                                                  \
+        break;
+
 template <typename T>
 __device__ __forceinline__ void batch_pass(int pass, const BatchInst<T> *in, int item, const cx<T> *tw, int lt)
 {
     if (pass == 0) {
         switch (in->M) {
-        case 16: batch_x_fwd<T, 16>(in, item, tw, lt); break;
-        case 32: batch_x_fwd<T, 32>(in, item, tw, lt); break;
-        case 64: batch_x_fwd<T, 64>(in, item, tw, lt); break;
-        case 128: batch_x_fwd<T, 128>(in, item, tw, lt); break;
-        case 256: batch_x_fwd<T, 256>(in, item, tw, lt); break;
-        case 512: batch_x_fwd<T, 512>(in, item, tw, lt); break;
+            PFC_BCASE(16, XFwdCands, batch_x_fwd, in->vx)
+            PFC_BCASE(32, XFwdCands, batch_x_fwd, in->vx)
+            PFC_BCASE(64, XFwdCands, batch_x_fwd, in->vx)
+            PFC_BCASE(128, XFwdCands, batch_x_fwd, in->vx)
+            PFC_BCASE(256, XFwdCands, batch_x_fwd, in->vx)
+            PFC_BCASE(512, XFwdCands, batch_x_fwd, in->vx)
         default: break;
         }
     } else if (pass == 1) {
         switch (in->n0) {
-        case 32: batch_y_step<T, 32>(in, item, tw, lt); break;
-        case 64: batch_y_step<T, 64>(in, item, tw, lt); break;
-        case 128: batch_y_step<T, 128>(in, item, tw, lt); break;
-        case 256: batch_y_step<T, 256>(in, item, tw, lt); break;
-        case 512: batch_y_step<T, 512>(in, item, tw, lt); break;
-        case 1024: batch_y_step<T, 1024>(in, item, tw, lt); break;
+            PFC_BCASE(32, LastCands, batch_y_step, in->vy)
+            PFC_BCASE(64, LastCands, batch_y_step, in->vy)
+            PFC_BCASE(128, LastCands, batch_y_step, in->vy)
+            PFC_BCASE(256, LastCands, batch_y_step, in->vy)
+            PFC_BCASE(512, LastCands, batch_y_step, in->vy)
+            PFC_BCASE(1024, LastCands, batch_y_step, in->vy)
         default: break;
         }
     } else {
         switch (in->M) {
-        case 16: batch_x_inv<T, 16>(in, item, tw, lt); break;
-        case 32: batch_x_inv<T, 32>(in, item, tw, lt); break;
-        case 64: batch_x_inv<T, 64>(in, item, tw, lt); break;
-        case 128: batch_x_inv<T, 128>(in, item, tw, lt); break;
-        case 256: batch_x_inv<T, 256>(in, item, tw, lt); break;
-        case 512: batch_x_inv<T, 512>(in, item, tw, lt); break;
+            PFC_BCASE(16, XInvCands, batch_x_inv, in->vc)
+            PFC_BCASE(32, XInvCands, batch_x_inv, in->vc)
+            PFC_BCASE(64, XInvCands, batch_x_inv, in->vc)
+            PFC_BCASE(128, XInvCands, batch_x_inv, in->vc)
+            PFC_BCASE(256, XInvCands, batch_x_inv, in->vc)
+            PFC_BCASE(512, XInvCands, batch_x_inv, in->vc)
         default: break;
         }
     }
 }
+#undef PFC_BCASE
 
 // LDS needed by the largest schedule: NT * Rmax complex values (Rmax <= 16).
 constexpr int kBatchLdsElems = kBatchThreads * 16;

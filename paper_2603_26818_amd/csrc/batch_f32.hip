@@ -26,33 +26,52 @@ hipError_t batch_blocks_per_cu(int *blocks)
 }
 
 template hipError_t launch_batch<float>(const BatchArgs<float> &, int, hipStream_t);
+template hipError_t batch_blocks_per_cu<float>(int *);
 
-bool batch_tiles(int n0, int M, int *x_rows, int *c_rows, int *y_pencils)
+bool batch_tiles(int n0, int M, int vx, int vy, int vc, int *x_rows, int *c_rows, int *y_pencils)
 {
-    auto xr = [](int m, int *f, int *c) {
+    if (vx < 0 || vy < 0 || vc < 0 || vx >= batch_candidates(n0, M, 0) || vy >= batch_candidates(n0, M, 1) ||
+        vc >= batch_candidates(n0, M, 2))
+        return false;
+    bool ok = true;
+    auto xr = [&](int m) {
         switch (m) {
-#define PFC_XCASE(MM)                                                     \
-    case MM:                                                              \
-        *f = BRows<typename BXFwd<MM>::type>::value;                      \
-        *c = BRows<typename BXInv<MM>::type>::value;                      \
-        return true;
+#define PFC_XCASE(MM)                                                                                   \
+    case MM:                                                                                            \
+        with_plan<typename XFwdCands<MM>::type>(vx, [&](auto p) { *x_rows = BRows<decltype(p)>::value; return 0; }); \
+        with_plan<typename XInvCands<MM>::type>(vc, [&](auto p) { *c_rows = BRows<decltype(p)>::value; return 0; }); \
+        break;
             PFC_XCASE(16) PFC_XCASE(32) PFC_XCASE(64) PFC_XCASE(128) PFC_XCASE(256) PFC_XCASE(512)
 #undef PFC_XCASE
-        default: return false;
+        default: ok = false;
         }
     };
-    auto yr = [](int l, int *w) {
+    auto yr = [&](int l) {
         switch (l) {
-#define PFC_YCASE(LL)                                                     \
-    case LL:                                                              \
-        *w = kBatchThreads / BLast<LL>::type::Tp;                         \
-        return true;
+#define PFC_YCASE(LL)                                                                                   \
+    case LL:                                                                                            \
+        with_plan<typename LastCands<LL>::type>(vy, [&](auto p) { *y_pencils = kBatchThreads / decltype(p)::Tp; return 0; }); \
+        break;
             PFC_YCASE(32) PFC_YCASE(64) PFC_YCASE(128) PFC_YCASE(256) PFC_YCASE(512) PFC_YCASE(1024)
 #undef PFC_YCASE
-        default: return false;
+        default: ok = false;
         }
     };
-    return xr(M, x_rows, c_rows) && yr(n0, y_pencils);
+    xr(M);
+    yr(n0);
+    return ok;
 }
-template hipError_t batch_blocks_per_cu<float>(int *);
+
+int batch_candidates(int n0, int M, int pass)
+{
+    const int len = pass == 1 ? n0 : M;
+    switch (len) {
+#define PFC_CCASE(LL)                                                                                   \
+    case LL:                                                                                            \
+        return pass == 0 ? XFwdCands<LL>::type::size : pass == 1 ? LastCands<LL>::type::size : XInvCands<LL>::type::size;
+        PFC_CCASE(16) PFC_CCASE(32) PFC_CCASE(64) PFC_CCASE(128) PFC_CCASE(256) PFC_CCASE(512) PFC_CCASE(1024)
+#undef PFC_CCASE
+    default: return 0;
+    }
+}
 }  // namespace pfc

@@ -26,7 +26,7 @@ struct pfc_plan {
     Geom g;
     double fk[3];  // 2 pi / (n dx) for axes (last-axis, rows, x)
     double dV;
-    size_t tw_off, partial_off, scratch_off, ws_need;
+    size_t tw_off, partial_off, watch_off, scratch_off, ws_need;
     size_t n_partials;
     char *ws = nullptr;
     size_t ws_bytes = 0;
@@ -41,6 +41,7 @@ struct pfc_batch {
     std::vector<int> order;            // device table order (largest first) -> caller's index
     struct Inst {
         int n0, nx, M, x_rows, c_rows, W, tiles, x_items, c_items;
+        int vx = 0, vy = 0, vc = 0;  // candidate schedules (autotuner)
     };
     std::vector<Inst> inst;  // caller's order
     int lt_shift = 0;
@@ -441,6 +442,29 @@ pfc_status do_energy(pfc_plan *p, const void *psi, const void *state, double *ou
 }
 
 template <typename T>
+pfc_status do_step_watched(pfc_plan *p, void *psi, void *state, int64_t nsteps, int64_t every, hipStream_t s,
+                           int64_t *done)
+{
+    *done = 0;
+    double *dev = reinterpret_cast<double *>(p->ws + p->watch_off);
+    while (*done < nsteps) {
+        const int64_t k = std::min<int64_t>(every, nsteps - *done);
+        pfc_status st = do_step<T>(p, psi, state, k, s);
+        if (st) return st;
+        *done += k;
+        st = do_energy<T>(p, psi, state, dev, s);
+        if (st) return st;
+        double host[2];
+        PFC_TRY(hipMemcpyAsync(host, dev, sizeof host, hipMemcpyDeviceToHost, s), "energy copy");
+        PFC_TRY(hipStreamSynchronize(s), "stream synchronize");
+        if (!std::isfinite(host[0]) || !std::isfinite(host[1]))
+            return fail(PFC_ERR_DIVERGED, "non-finite energy (%g) or mean (%g) after %lld steps", host[0], host[1],
+                        (long long)*done);
+    }
+    return PFC_OK;
+}
+
+template <typename T>
 pfc_status do_export(pfc_plan *p, const void *state, void *out, hipStream_t s)
 {
     PFC_TRY(pfc::launch_export<T>(p->g, (const cx<T> *)state, (cx<T> *)out, s), "export launch");
@@ -460,10 +484,27 @@ void drop_graphs(pfc_batch *b)
     b->graphs.clear();
 }
 
-template <typename T>
-pfc_status batch_bind_impl(pfc_batch *b)
+// rows / pencils / items of every instance for its current candidate schedules
+pfc_status batch_layout(pfc_batch *b)
 {
-    const size_t cs = sizeof(cx<T>);
+    for (int i = 0; i < b->count; ++i) {
+        pfc_batch::Inst &g = b->inst[i];
+        int wm = 0;
+        if (!pfc::batch_tiles(g.n0, g.M, g.vx, g.vy, g.vc, &g.x_rows, &g.c_rows, &wm))
+            return fail(PFC_ERR_UNSUPPORTED, "instance %d: no batched schedule for %d x %d (candidates %d %d %d)", i,
+                        g.n0, g.nx, g.vx, g.vy, g.vc);
+        g.W = std::min(wm, g.M);
+        g.tiles = g.M / g.W;
+        g.x_items = (g.n0 + g.x_rows - 1) / g.x_rows;
+        g.c_items = (g.n0 + g.c_rows - 1) / g.c_rows;
+    }
+    return PFC_OK;
+}
+
+// builds the device instance table (largest instances first) and uploads it (synchronous)
+template <typename T>
+pfc_status batch_upload_table(pfc_batch *b)
+{
     std::vector<pfc::BatchInst<T>> table(b->count);
     int xb = 0, yb = 0, cb = 0;
     for (int j = 0; j < b->count; ++j) {
@@ -483,6 +524,9 @@ pfc_status batch_bind_impl(pfc_batch *b)
         t.x_begin = xb;
         t.y_begin = yb;
         t.c_begin = cb;
+        t.vx = g.vx;
+        t.vy = g.vy;
+        t.vc = g.vc;
         xb += g.x_items;
         yb += g.tiles;
         cb += g.c_items;
@@ -500,6 +544,17 @@ pfc_status batch_bind_impl(pfc_batch *b)
     b->x_total = xb;
     b->y_total = yb;
     b->c_total = cb;
+    PFC_TRY(hipMemcpy(b->ws + b->inst_off, table.data(), table.size() * sizeof(table[0]), hipMemcpyHostToDevice),
+            "instance table upload");
+    drop_graphs(b);  // the captured launches hold the item totals
+    return PFC_OK;
+}
+
+template <typename T>
+pfc_status batch_bind_impl(pfc_batch *b)
+{
+    pfc_status st = batch_upload_table<T>(b);
+    if (st) return st;
     const int64_t Lt = int64_t(1) << b->lt_shift;
     std::vector<cx<T>> tw(Lt);
     for (int64_t e = 0; e < Lt; ++e) {
@@ -508,9 +563,6 @@ pfc_status batch_bind_impl(pfc_batch *b)
         tw[e].x = (T)c;
         tw[e].y = (T)sn;
     }
-    (void)cs;
-    PFC_TRY(hipMemcpy(b->ws + b->inst_off, table.data(), table.size() * sizeof(table[0]), hipMemcpyHostToDevice),
-            "instance table upload");
     PFC_TRY(hipMemcpy(b->ws + b->tw_off, tw.data(), tw.size() * sizeof(tw[0]), hipMemcpyHostToDevice),
             "twiddle upload");
     PFC_TRY(hipMemset(b->ws + b->ctl_off, 0, sizeof(pfc::BatchCtl)), "barrier state reset");
@@ -591,6 +643,67 @@ pfc_status batch_state_init_impl(pfc_batch *b, hipStream_t s)
     return PFC_OK;
 }
 
+// Coordinate descent over the candidate schedules: for each pass kind and each distinct length,
+// time every candidate by launching the persistent kernel (no graph) for `steps` steps.
+template <typename T>
+pfc_status batch_autotune_impl(pfc_batch *b, hipStream_t s, int steps, double *total_ms)
+{
+    hipEvent_t e0, e1;
+    PFC_TRY(hipEventCreate(&e0), "hipEventCreate");
+    hipError_t ce = hipEventCreate(&e1);
+    if (ce != hipSuccess) {
+        (void)hipEventDestroy(e0);
+        return hip_fail(ce, "hipEventCreate");
+    }
+    auto trial = [&](float *ms) -> pfc_status {
+        pfc_status st = batch_layout(b);
+        if (!st) st = batch_upload_table<T>(b);
+        if (st) return st;
+        PFC_TRY(hipEventRecord(e0, s), "event record");
+        PFC_TRY(pfc::launch_batch<T>(batch_args<T>(b, steps), b->grid, s), "batched kernel launch");
+        PFC_TRY(hipEventRecord(e1, s), "event record");
+        PFC_TRY(hipEventSynchronize(e1), "event synchronize");
+        PFC_TRY(hipEventElapsedTime(ms, e0, e1), "event timing");
+        pfc::BatchCtl ctl;
+        PFC_TRY(hipMemcpy(&ctl, b->ws + b->ctl_off, sizeof ctl, hipMemcpyDeviceToHost), "barrier state read");
+        if (ctl.err) return fail(PFC_ERR_INTERNAL, "grid barrier timed out during autotuning");
+        return PFC_OK;
+    };
+    pfc_status st = PFC_OK;
+    float ms = 0.f;
+    st = trial(&ms);  // warm-up
+    for (int pass = 0; pass < 3 && st == PFC_OK; ++pass) {
+        std::vector<int> lens;
+        for (auto &g : b->inst) lens.push_back(pass == 1 ? g.n0 : g.M);
+        std::sort(lens.begin(), lens.end());
+        lens.erase(std::unique(lens.begin(), lens.end()), lens.end());
+        for (int len : lens) {
+            const pfc_batch::Inst *any = nullptr;
+            for (auto &g : b->inst)
+                if ((pass == 1 ? g.n0 : g.M) == len) any = &g;
+            const int nc = pfc::batch_candidates(any->n0, any->M, pass);
+            int best = 0;
+            float best_t = INFINITY;
+            for (int c = 0; c < nc && st == PFC_OK; ++c) {
+                for (auto &g : b->inst)
+                    if ((pass == 1 ? g.n0 : g.M) == len) (pass == 0 ? g.vx : pass == 1 ? g.vy : g.vc) = c;
+                st = trial(&ms);
+                if (st == PFC_OK && ms < best_t) {
+                    best_t = ms;
+                    best = c;
+                }
+            }
+            for (auto &g : b->inst)
+                if ((pass == 1 ? g.n0 : g.M) == len) (pass == 0 ? g.vx : pass == 1 ? g.vy : g.vc) = best;
+        }
+    }
+    if (st == PFC_OK) st = trial(&ms);
+    if (st == PFC_OK && total_ms) *total_ms = ms / steps;
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    return st;
+}
+
 }  // namespace
 
 extern "C" {
@@ -636,7 +749,8 @@ pfc_status pfc_plan_create(pfc_plan **out, const pfc_plan_desc *d)
     p->n_partials = (size_t)std::max<int64_t>(2 * pfc::kReduceBlocks, g.xrows);
     p->tw_off = 0;
     p->partial_off = align256((size_t)Lt * cs);
-    p->scratch_off = p->partial_off + align256(p->n_partials * sizeof(double));
+    p->watch_off = p->partial_off + align256(p->n_partials * sizeof(double));
+    p->scratch_off = p->watch_off + 256;
     p->ws_need = p->scratch_off + align256(state_bytes(p));
     *out = p;
     return PFC_OK;
@@ -757,6 +871,18 @@ pfc_status pfc_step(pfc_plan *p, void *psi, void *state, int64_t nsteps, void *s
     PFC_DISPATCH(p, do_step, p, psi, state, nsteps, (hipStream_t)stream);
 }
 
+pfc_status pfc_step_watched(pfc_plan *p, void *psi, void *state, int64_t nsteps, int64_t check_every, void *stream,
+                            int64_t *done_steps)
+{
+    PFC_CHECK(check_ready(p));
+    PFC_CHECK(check_ptr(psi, "psi"));
+    PFC_CHECK(check_ptr(state, "state"));
+    if (nsteps < 0 || check_every < 1) return fail(PFC_ERR_INVALID_ARG, "nsteps < 0 or check_every < 1");
+    if (!done_steps) return fail(PFC_ERR_INVALID_ARG, "done_steps is NULL");
+    if (overlap(psi, real_bytes(p), state, state_bytes(p))) return fail(PFC_ERR_INVALID_ARG, "psi and state overlap");
+    PFC_DISPATCH(p, do_step_watched, p, psi, state, nsteps, check_every, (hipStream_t)stream, done_steps);
+}
+
 pfc_status pfc_step_timed(pfc_plan *p, void *psi, void *state, int64_t nsteps, void *stream, double *pass_ms,
                           int *npasses)
 {
@@ -859,17 +985,15 @@ pfc_status pfc_batch_create(pfc_batch **out, const pfc_plan_desc *descs, int cou
         g.n0 = (int)descs[i].n[0];
         g.nx = (int)descs[i].n[1];
         g.M = g.nx / 2;
-        int wm = 0;
-        if (!pfc::batch_tiles(g.n0, g.M, &g.x_rows, &g.c_rows, &wm)) {
-            delete b;
-            return fail(PFC_ERR_UNSUPPORTED, "instance %d: no batched schedule for %d x %d", i, g.n0, g.nx);
-        }
-        g.W = std::min(wm, g.M);
-        g.tiles = g.M / g.W;
-        g.x_items = (g.n0 + g.x_rows - 1) / g.x_rows;
-        g.c_items = (g.n0 + g.c_rows - 1) / g.c_rows;
         b->inst.push_back(g);
         Lt = std::max<int64_t>(Lt, std::max(g.n0, g.nx));
+    }
+    {
+        pfc_status st = batch_layout(b);
+        if (st) {
+            delete b;
+            return st;
+        }
     }
     while ((int64_t(1) << b->lt_shift) < Lt) ++b->lt_shift;
     // largest instances first: their items are the longest, so they start first
@@ -960,6 +1084,56 @@ pfc_status pfc_batch_check(pfc_batch *b, void *stream)
                     "results of that launch are incomplete");
     }
     return PFC_OK;
+}
+
+pfc_status pfc_batch_get_tuning(const pfc_batch *b, int *variants, int n)
+{
+    if (!b || !variants) return fail(PFC_ERR_INVALID_ARG, "NULL argument");
+    if (n != 3 * b->count) return fail(PFC_ERR_INVALID_ARG, "expected %d entries (3 per instance)", 3 * b->count);
+    for (int i = 0; i < b->count; ++i) {
+        variants[3 * i] = b->inst[i].vx;
+        variants[3 * i + 1] = b->inst[i].vy;
+        variants[3 * i + 2] = b->inst[i].vc;
+    }
+    return PFC_OK;
+}
+
+pfc_status pfc_batch_set_tuning(pfc_batch *b, const int *variants, int n)
+{
+    if (!b || !variants) return fail(PFC_ERR_INVALID_ARG, "NULL argument");
+    if (n != 3 * b->count) return fail(PFC_ERR_INVALID_ARG, "expected %d entries (3 per instance)", 3 * b->count);
+    for (int i = 0; i < b->count; ++i)
+        for (int k = 0; k < 3; ++k) {
+            const int nc = pfc::batch_candidates(b->inst[i].n0, b->inst[i].M, k);
+            if (variants[3 * i + k] < 0 || variants[3 * i + k] >= nc)
+                return fail(PFC_ERR_INVALID_ARG, "instance %d pass %d: variant %d out of [0, %d)", i, k,
+                            variants[3 * i + k], nc);
+        }
+    std::vector<pfc_batch::Inst> saved = b->inst;
+    for (int i = 0; i < b->count; ++i) {
+        b->inst[i].vx = variants[3 * i];
+        b->inst[i].vy = variants[3 * i + 1];
+        b->inst[i].vc = variants[3 * i + 2];
+    }
+    pfc_status st = batch_layout(b);
+    if (st) {
+        b->inst = saved;
+        return st;
+    }
+    if (!b->ws) return PFC_OK;
+    DeviceGuard dg(b->device);
+    if (dg.err != hipSuccess) return hip_fail(dg.err, "hipSetDevice");
+    return b->dtype == PFC_F64 ? batch_upload_table<double>(b) : batch_upload_table<float>(b);
+}
+
+pfc_status pfc_batch_autotune(pfc_batch *b, void *stream, int steps, double *ms_per_step)
+{
+    if (!b || !b->ws) return fail(PFC_ERR_WORKSPACE, "batch not bound");
+    if (steps < 1) return fail(PFC_ERR_INVALID_ARG, "steps must be >= 1");
+    DeviceGuard dg(b->device);
+    if (dg.err != hipSuccess) return hip_fail(dg.err, "hipSetDevice");
+    return b->dtype == PFC_F64 ? batch_autotune_impl<double>(b, (hipStream_t)stream, steps, ms_per_step)
+                               : batch_autotune_impl<float>(b, (hipStream_t)stream, steps, ms_per_step);
 }
 
 pfc_status pfc_batch_destroy(pfc_batch *b)

@@ -35,6 +35,7 @@ struct BatchInst {
     int x_items;     // x r2c items
     int c_items;     // x c2r items
     int x_begin, y_begin, c_begin;  // first global item of this instance in each pass
+    int vx, vy, vc;                 // candidate schedule of the x forward, y and x inverse passes
     T sc;            // 1 / (n0 M)
     ModelParams<T> mp;
 };

@@ -82,3 +82,66 @@ def test_batch_instance_vs_oracle(pfc):
         e = relerr(to_np(b.psi[k]), ref)
         say(f"        instance {d['shape']}: rel L2 {e:.2e}")
         assert e < 1e-12
+
+
+@pytest.mark.parametrize("choice", [1])
+def test_batch_candidates_match_single_plans(pfc, choice):
+    """Every instance on its alternative candidate schedules (where a pass has one) still equals the
+    single-plan run on the same candidates, bit for bit."""
+    import torch
+
+    insts = _instances("f32")
+    b = pfc.Batch(insts)
+    psi0 = [rounded(P.pfc_initial_field(P.derive_seed(4, 300 + i), d["shape"], d["r"]), "f32") for i, d in enumerate(insts)]
+    b.bind([to_dev(x, "f32") for x in psi0])
+    tuning = []
+    for k in range(len(insts)):
+        t = []
+        for j in range(3):
+            trial = [list(v) for v in b.get_tuning()]
+            trial[k][j] = choice
+            try:
+                b.set_tuning(trial)
+                t.append(choice)
+            except Exception:
+                t.append(0)
+        tuning.append(t)
+    b.set_tuning(tuning)
+    say(f"[batch] candidates {tuning}")
+    b.state_init()
+    b.step(9)
+    b.check()
+    for k, d in enumerate(insts):
+        p = pfc.Plan(d["shape"], dtype="f32", model=d["model"], r=d["r"], dt=d["dt"], q1sq=d["q1sq"], R1=d["R1"])
+        p.set_tuning(tuning[k])
+        x = to_dev(psi0[k], "f32")
+        s = p.state_init(x)
+        p.step(x, s, 9)
+        torch.cuda.synchronize()
+        assert torch.equal(b.psi[k], x), f"instance {k} {d['shape']} differs"
+
+
+def test_batch_autotune_and_cache(pfc, tmp_path):
+    import torch
+
+    insts = _instances("f32")
+    b = pfc.Batch(insts)
+    psi0 = [rounded(P.pfc_initial_field(P.derive_seed(4, 400 + i), d["shape"], d["r"]), "f32") for i, d in enumerate(insts)]
+    b.bind([to_dev(x, "f32") for x in psi0])
+    cache = str(tmp_path / "bt.json")
+    v, ms = b.autotune(steps=3, cache_path=cache)
+    say(f"[batch] autotuned {v}, {ms:.4f} ms/step")
+    assert b.get_tuning() == v
+    b.state_init()
+    b.step(5)
+    b.check()
+    b2 = pfc.Batch(insts)
+    b2.bind([to_dev(x, "f32") for x in psi0])
+    v2, ms2 = b2.autotune(cache_path=cache)
+    assert v2 == v and ms2 is None
+    b2.state_init()
+    b2.step(5)
+    b2.check()
+    torch.cuda.synchronize()
+    for k in range(len(insts)):
+        assert torch.equal(b.psi[k], b2.psi[k])

@@ -147,3 +147,28 @@ def test_step_backward_vs_oracle(pfc, shape, dtype):
     lam_d = to_dev(lam, dtype)
     out2, _ = plan.step_backward(to_dev(psi_n, dtype), to_dev(psi_np1, dtype), lam_d, lambda_n=lam_d)
     assert relerr(to_np(out2), ref_lam) < tol
+
+
+def test_watchdog_reports_divergence(pfc):
+    """A NaN planted in psi0 (forced from the host) is caught at the first check; a finite run
+    passes and ends like pfc_step."""
+    import torch
+
+    shape = (32, 64)
+    say("[watchdog] NaN in psi0")
+    psi0 = P.pfc_initial_field(15, shape, -0.25)
+    plan = pfc.Plan(shape, dtype="f64", r=-0.25, dt=0.5)
+    x = to_dev(psi0, "f64")
+    s = plan.state_init(x)
+    x2, s2 = x.clone(), s.clone()
+    assert plan.step_watched(x, s, 40, check_every=7) == 40
+    plan.step(x2, s2, 40)
+    torch.cuda.synchronize()
+    assert torch.equal(x, x2)
+    bad = psi0.copy()
+    bad[3, 5] = np.nan
+    xb = to_dev(bad, "f64")
+    sb = plan.state_init(xb)
+    with pytest.raises(pfc.PfcError) as ei:
+        plan.step_watched(xb, sb, 40, check_every=10)
+    assert ei.value.status == 6 and "after 10 steps" in str(ei.value)
