@@ -26,7 +26,7 @@ PEAK_HBM_GBPS = 8000.0  # MI355X HBM3E
 N = 512
 R, DT, SEED = -0.30, 0.5, 23
 PASS_NAMES = ["x_r2c_cube", "y_fwd", "z_fused_update", "y_inv", "x_c2r"]
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_512cube_f32.json")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_512cube_f32.txt")
 KERNEL_SOURCES = ["fft_core.hpp", "kernels.hpp", "dispatch_impl.hpp", "types.hpp"]
 
 
@@ -114,6 +114,41 @@ def bench_batched(nsteps):
             "separate_launches_steps_per_s": round(1000.0 / ms_sep, 1)}
 
 
+def bench_big(nsteps):
+    """3D one-mode PFC at 2048^3 FP32 (r = -0.30, dt = 0.5, psi0 seed 3): steps/s and per-pass GB/s."""
+    import torch
+
+    import paper_2603_26818_amd as pfc
+    import pfc_inputs
+
+    n = 2048
+    shape = (n, n, n)
+    plan = pfc.Plan(shape, dtype="f32", r=R, dt=DT)
+    psi = pfc_inputs.pfc_initial_field_torch(3, shape, R, torch.float32, "cuda:0")
+    state = plan.state_init(psi)
+    plan.step(psi, state, 2)
+    stream = torch.cuda.current_stream()
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    plan.step(psi, state, nsteps)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / nsteps
+    pass_ms = plan.step_timed(psi, state, 3)
+    F = plan.energy(psi, state).cpu().tolist()
+    Rb = n**3 * 4
+    alg = [2 * Rb, 2 * Rb, 4 * Rb, 2 * Rb, 2 * Rb]
+    passes = [{"kernel": k, "avg_ms": round(t / 3, 3), "alg_gbps": round(b / (t / 3) / 1e6, 1),
+               "frac": round(b / (t / 3) / 1e6 / PEAK_HBM_GBPS, 4)} for k, t, b in zip(PASS_NAMES, pass_ms, alg)]
+    del psi, state, plan
+    torch.cuda.empty_cache()
+    return {"workload": "3D one-mode PFC 2048^3 FP32, r=-0.30, dt=0.5, psi0 seed 3", "steps": nsteps,
+            "ms_per_step": round(ms, 3), "steps_per_s": round(1000.0 / ms, 2),
+            "alg_gbps": round(12 * Rb / ms / 1e6, 1), "frac": round(12 * Rb / ms / 1e6 / PEAK_HBM_GBPS, 4),
+            "passes": passes, "energy_finite": all(math.isfinite(v) for v in F)}
+
+
 def bench_adjoint(nsteps, every):
     import torch
 
@@ -145,6 +180,83 @@ def bench_adjoint(nsteps, every):
             "dL_dr": dr}
 
 
+KERNEL_PASS = {"x_r2c_kernel": "x_r2c_cube", "last_axis_kernel": "z_fused_update", "x_c2r_kernel": "x_c2r"}
+
+
+def counters_workload(steps):
+    """Workload of the counter runs: a plain 1 GiB device copy (calibration of FETCH_SIZE and
+    WRITE_SIZE against known bytes), then `steps` steps of the 512^3 FP32 workload."""
+    import torch
+
+    import paper_2603_26818_amd as pfc
+    import pfc_inputs
+
+    x = torch.empty(2**28, dtype=torch.float32, device="cuda:0").fill_(1.0)
+    y = torch.empty_like(x)
+    for _ in range(3):
+        y.copy_(x)
+    torch.cuda.synchronize()
+    del x, y
+    shape = (N, N, N)
+    plan = pfc.Plan(shape, dtype="f32", r=R, dt=DT)
+    psi = pfc_inputs.pfc_initial_field_torch(SEED, shape, R, torch.float32, "cuda:0")
+    state = plan.state_init(psi)
+    plan.step(psi, state, steps)
+    torch.cuda.synchronize()
+
+
+def write_traffic(fetch_dir, write_dir, out_path, command):
+    """Per-dispatch HBM bytes of the step kernels from two rocprofv3 --pmc runs (FETCH_SIZE and
+    WRITE_SIZE, KiB per dispatch), each scaled by the factor that makes the 1 GiB copy read and
+    write exactly 1 GiB."""
+    import csv
+    import glob
+
+    def load(d, counter):
+        rows = []
+        for f in glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True):
+            with open(f) as fh:
+                rows += [r for r in csv.DictReader(fh) if r.get("Counter_Name") == counter]
+        return rows
+
+    def per_kernel(rows):
+        acc = {}
+        for r in rows:
+            name = r["Kernel_Name"]
+            acc.setdefault(name, []).append(float(r["Counter_Value"]))
+        return acc
+
+    fetch = per_kernel(load(fetch_dir, "FETCH_SIZE"))
+    write = per_kernel(load(write_dir, "WRITE_SIZE"))
+    copy_bytes = 2**30
+    copy_f = [v for k, vals in fetch.items() if "copy" in k.lower() for v in vals]
+    copy_w = [v for k, vals in write.items() if "copy" in k.lower() for v in vals]
+    f_fac = copy_bytes / (sum(copy_f) / len(copy_f))
+    w_fac = copy_bytes / (sum(copy_w) / len(copy_w))
+    kernels = {}
+    for name, vals in fetch.items():
+        short = name.replace("void ", "").replace("pfc::", "").split("<")[0]
+        if short == "axis_c2c_kernel":
+            short = "y_fwd_or_inv"
+        short = KERNEL_PASS.get(short, short)
+        if short not in ("x_r2c_cube", "z_fused_update", "x_c2r", "y_fwd_or_inv"):
+            continue
+        if short == "x_r2c_cube" and "true" not in name:
+            continue
+        if short == "z_fused_update" and not name.rstrip(")").split("(")[0].replace(" ", "").endswith(",0,1,true>"):
+            continue
+        wv = write.get(name, [0.0])
+        fb = sum(vals) / len(vals) * f_fac
+        wb = sum(wv) / len(wv) * w_fac
+        kernels[short] = {"fetch_bytes_per_launch": round(fb), "write_bytes_per_launch": round(wb),
+                          "hbm_bytes_per_launch": round(fb + wb), "dispatches": len(vals)}
+    out = {"command": command, "kernel_hash": kernel_hash(), "copy_calibration_bytes": copy_bytes,
+           "fetch_factor_bytes_per_unit": f_fac, "write_factor_bytes_per_unit": w_fac, "kernels": kernels}
+    with open(out_path, "w") as f:
+        json.dump(out, f, indent=1)
+    print(json.dumps(out, indent=1))
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -155,7 +267,19 @@ def main():
     ap.add_argument("--cpu-steps", type=int, default=3, help="oracle steps of the CPU baseline (0: skip)")
     ap.add_argument("--batch-steps", type=int, default=500, help="steps of the batched form (0: skip)")
     ap.add_argument("--adjoint-steps", type=int, default=2000, help="steps of the adjoint form (0: skip)")
+    ap.add_argument("--big-steps", type=int, default=50, help="timed steps at 2048^3 (0: skip)")
+    ap.add_argument("--counters", type=int, default=0, metavar="STEPS",
+                    help="run only the workload of the rocprofv3 --pmc runs (copy calibration + STEPS steps)")
+    ap.add_argument("--write-traffic", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
+                    help="summarise two rocprofv3 --pmc output folders into " + os.path.relpath(TRAFFIC_FILE, ROOT))
+    ap.add_argument("--traffic-command", default="", help="command line recorded in the traffic summary")
     args = ap.parse_args()
+    if args.write_traffic:
+        write_traffic(args.write_traffic[0], args.write_traffic[1], TRAFFIC_FILE, args.traffic_command)
+        return
+    if args.counters:
+        counters_workload(args.counters)
+        return
     if args.gpus != 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path (see DESIGN.md for how the "
               "step would shard).", file=sys.stderr)
@@ -240,8 +364,15 @@ def main():
            "r2c_frac": round(fft_bytes / t_r2c / 1e6 / PEAK_HBM_GBPS, 4),
            "c2r_frac": round(fft_bytes / t_c2r / 1e6 / PEAK_HBM_GBPS, 4),
            "alg_bytes": fft_bytes, "roundtrip_rel_l2": rt_err}
-    del x, X, y
 
+    del x, X, y
+    big = None
+    if args.big_steps > 0:
+        del psi, state, plan
+        torch.cuda.empty_cache()
+        log(f"[bench] 2048^3 FP32: {args.big_steps} steps")
+        big = bench_big(args.big_steps)
+        log(f"[bench] 2048^3: {big['steps_per_s']} steps/s ({big['frac']:.3f} of peak)")
     batched = None
     if args.batch_steps > 0:
         log(f"[bench] batched form: 48 instances, {args.batch_steps} steps")
@@ -276,8 +407,8 @@ def main():
         "vs_baseline": None, "dtype": "f32", "data": "synthetic",
         "config": {"workload": "3D one-mode PFC step, 512^3 periodic grid, FP32, dx=pi/4, r=-0.30, dt=0.5, "
                                "psi0=-0.30+U(-0.1,0.1) SplitMix64 seed 23", "grid": list(shape)},
-        "roofline": roofline, "cpu_baseline": cpu, "fft": fft, "passes": passes, "batched": batched,
-        "adjoint": adjoint,
+        "roofline": roofline, "cpu_baseline": cpu, "fft": fft, "passes": passes, "big_2048": big,
+        "batched": batched, "adjoint": adjoint,
         "step_alg_gbps": round(step_bytes / ms_per_step / 1e6, 1),
         "step_frac": round(step_bytes / ms_per_step / 1e6 / PEAK_HBM_GBPS, 4),
         "energy_after": F[0],
