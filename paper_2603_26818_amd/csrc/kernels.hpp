@@ -156,22 +156,37 @@ struct AdjEpi {
     double *partial;
 };
 
-template <typename T, class PL, int ROWS, bool PAD>
+// Pre-combination of one row for the c2r: own elements X(k) from `src`; the mirror X(M-k) either
+// through LDS (PG = false) or straight from `src` (PG = true: a second, reversed but coalesced load of
+// the same cache lines, without the LDS round trip and its barrier).
+template <typename T, class PL, int ROWS, bool PAD, bool PG = false>
 __device__ __forceinline__ void x_c2r_row(cx<T> *v, const cx<T> *src, bool valid, int t, cx<T> *rowlds,
                                           const cx<T> *__restrict__ tw, int lt_shift)
 {
     constexpr int M = PL::L, Tp = PL::Tp, R0 = PL::first, Rmax = PL::Rmax;
     constexpr int tshift = ilog2c(2 * M);
-    __syncthreads();
+    cx<T> mir[PG ? Rmax : 1];
+    if constexpr (PG) {
 #pragma unroll
-    for (int b = 0; b < Rmax / R0; ++b)
+        for (int b = 0; b < Rmax / R0; ++b)
 #pragma unroll
-        for (int r = 0; r < R0; ++r) {
-            const int k = t + b * Tp + r * (M / R0);
-            v[b * R0 + r] = valid ? src[k] : cx<T>{T(0), T(0)};
-            rowlds[xidx<PAD>(k)] = v[b * R0 + r];
-        }
-    __syncthreads();
+            for (int r = 0; r < R0; ++r) {
+                const int k = t + b * Tp + r * (M / R0);
+                v[b * R0 + r] = valid ? src[k] : cx<T>{T(0), T(0)};
+                mir[b * R0 + r] = valid ? src[(M - k) & (M - 1)] : cx<T>{T(0), T(0)};
+            }
+    } else {
+        __syncthreads();
+#pragma unroll
+        for (int b = 0; b < Rmax / R0; ++b)
+#pragma unroll
+            for (int r = 0; r < R0; ++r) {
+                const int k = t + b * Tp + r * (M / R0);
+                v[b * R0 + r] = valid ? src[k] : cx<T>{T(0), T(0)};
+                rowlds[xidx<PAD>(k)] = v[b * R0 + r];
+            }
+        __syncthreads();
+    }
     const T h = T(0.5);
 #pragma unroll
     for (int b = 0; b < Rmax / R0; ++b)
@@ -182,7 +197,11 @@ __device__ __forceinline__ void x_c2r_row(cx<T> *v, const cx<T> *src, bool valid
             if (k == 0) {
                 v[b * R0 + r] = {(a.x + a.y) * h, (a.x - a.y) * h};
             } else {
-                const cx<T> c = rowlds[xidx<PAD>(M - k)];  // X(M-k); conj taken below
+                cx<T> c;  // X(M-k); conj taken below
+                if constexpr (PG)
+                    c = mir[b * R0 + r];
+                else
+                    c = rowlds[xidx<PAD>(M - k)];
                 const cx<T> E = {(a.x + c.x) * h, (a.y - c.y) * h};
                 const cx<T> D = {(a.x - c.x) * h, (a.y + c.y) * h};
                 const cx<T> O = cmul(conj(tw[k << (lt_shift - tshift)]), D);
@@ -191,7 +210,7 @@ __device__ __forceinline__ void x_c2r_row(cx<T> *v, const cx<T> *src, bool valid
         }
 }
 
-template <typename T, class PL, int ROWS, int EPI, bool PAD = false>
+template <typename T, class PL, int ROWS, int EPI, bool PAD = false, bool PG = false>
 __device__ __forceinline__ void x_c2r_block(const cx<T> *in, T *out, int64_t nrows, const cx<T> *__restrict__ tw,
                                             int lt_shift, T sc, const AdjEpi<T> &ea, int64_t bid, cx<T> *sh)
 {
@@ -203,7 +222,7 @@ __device__ __forceinline__ void x_c2r_block(const cx<T> *in, T *out, int64_t nro
     const int64_t r0 = valid ? row : 0;
     auto lds = [&](int e) -> cx<T> & { return sh[p * LD + xidx<PAD>(e)]; };
     cx<T> v[Rmax];
-    x_c2r_row<T, PL, ROWS, PAD>(v, in + r0 * M, valid, t, &sh[p * LD], tw, lt_shift);
+    x_c2r_row<T, PL, ROWS, PAD, PG>(v, in + r0 * M, valid, t, &sh[p * LD], tw, lt_shift);
     fft_stages<T, PL, +1>(v, t, lds, tw, lt_shift);
     cx<T> *dst = reinterpret_cast<cx<T> *>(out) + r0 * M;
     if constexpr (EPI == EPI_PLAIN) {
@@ -216,7 +235,7 @@ __device__ __forceinline__ void x_c2r_block(const cx<T> *in, T *out, int64_t nro
         }
     } else {
         cx<T> w[Rmax];
-        x_c2r_row<T, PL, ROWS, PAD>(w, ea.in2 + r0 * M, valid, t, &sh[p * LD], tw, lt_shift);
+        x_c2r_row<T, PL, ROWS, PAD, PG>(w, ea.in2 + r0 * M, valid, t, &sh[p * LD], tw, lt_shift);
         fft_stages<T, PL, +1>(w, t, lds, tw, lt_shift);
         const cx<T> *pn = reinterpret_cast<const cx<T> *>(ea.psi_n) + r0 * M;
         const cx<T> *pn1 = reinterpret_cast<const cx<T> *>(ea.psi_np1) + r0 * M;
@@ -239,13 +258,13 @@ __device__ __forceinline__ void x_c2r_block(const cx<T> *in, T *out, int64_t nro
     }
 }
 
-template <typename T, class PL, int ROWS, int EPI, bool PAD = false>
+template <typename T, class PL, int ROWS, int EPI, bool PAD = false, bool PG = false>
 __global__ __launch_bounds__(ROWS *PL::Tp) void x_c2r_kernel(const cx<T> *in, T *out, int64_t nrows,
                                                               const cx<T> *__restrict__ tw, int lt_shift, T sc,
                                                               AdjEpi<T> ea)
 {
     __shared__ cx<T> sh[ROWS * XPitch<PL::L, PAD>::value];
-    x_c2r_block<T, PL, ROWS, EPI, PAD>(in, out, nrows, tw, lt_shift, sc, ea, blockIdx.x, sh);
+    x_c2r_block<T, PL, ROWS, EPI, PAD, PG>(in, out, nrows, tw, lt_shift, sc, ea, blockIdx.x, sh);
 }
 
 // ------------------------------------------------------------------------------------------------
@@ -324,6 +343,10 @@ struct SlotInfo {
     bool has_pairs;
 };
 
+// ROWFAST: consecutive workgroups take consecutive rows of the same column tile (measured slightly
+// slower at 512^3 than the default, where consecutive workgroups take adjacent column tiles of one
+// row).
+template <bool ROWFAST = false>
 __device__ __forceinline__ SlotInfo la_slot(int64_t nrows, int TR, int W, int p, int64_t bid)
 {
     SlotInfo s;
@@ -336,8 +359,13 @@ __device__ __forceinline__ SlotInfo la_slot(int64_t nrows, int TR, int W, int p,
     }
     const int64_t n_normal = nrows * (TR - 1);
     if (bid < n_normal) {
-        s.row = bid / (TR - 1);
-        s.kx = (int)(1 + bid % (TR - 1)) * W + p;
+        if constexpr (ROWFAST) {
+            s.row = bid % nrows;
+            s.kx = (int)(1 + bid / nrows) * W + p;
+        } else {
+            s.row = bid / (TR - 1);
+            s.kx = (int)(1 + bid % (TR - 1)) * W + p;
+        }
         s.partner = -1;
         s.has_pairs = false;
         return s;
@@ -353,7 +381,7 @@ __device__ __forceinline__ SlotInfo la_slot(int64_t nrows, int TR, int W, int p,
     return s;
 }
 
-template <typename T, class PL, int WMAX, int MODE, bool PF = true>
+template <typename T, class PL, int WMAX, int MODE, bool PF = true, bool ROWFAST = false>
 __device__ __forceinline__ void last_axis_block(const LastAxisArgs<T> &a, int64_t bid, cx<T> *sh)
 {
     constexpr int L = PL::L, Tp = PL::Tp, Rmax = PL::Rmax;
@@ -362,7 +390,7 @@ __device__ __forceinline__ void last_axis_block(const LastAxisArgs<T> &a, int64_
     const int tid = threadIdx.x, p = tid % WMAX, t = tid / WMAX;
     const int W = a.W;
     const int64_t nrows = a.nrows, M = a.M, estride = nrows * M;
-    const SlotInfo si = la_slot(nrows, a.tiles_per_row, W, p < W ? p : 0, bid);
+    const SlotInfo si = la_slot<ROWFAST>(nrows, a.tiles_per_row, W, p < W ? p : 0, bid);
     const bool valid = p < W;
     const int64_t coloff = si.row * M + si.kx;
     auto lds = [&](int e) -> cx<T> & { return sh[e * WMAX + p]; };
@@ -375,7 +403,8 @@ __device__ __forceinline__ void last_axis_block(const LastAxisArgs<T> &a, int64_
     if constexpr (MODE == LA_C2R_NATURAL) {
         // natural half spectrum in: fold kx = 0 and kx = M (projected) into one plane, inverse FFT
         constexpr int R0 = PR::first;
-        const int64_t prow = (si.partner >= 0) ? la_slot(nrows, a.tiles_per_row, W, si.partner, bid).row : 0;
+        const int64_t prow =
+            (si.partner >= 0) ? la_slot<ROWFAST>(nrows, a.tiles_per_row, W, si.partner, bid).row : 0;
         const int64_t pitch = M + 1;
 #pragma unroll
         for (int b = 0; b < Rmax / R0; ++b)
@@ -597,11 +626,11 @@ __device__ __forceinline__ void last_axis_block(const LastAxisArgs<T> &a, int64_
     }
 }
 
-template <typename T, class PL, int WMAX, int MODE, int OCC = 1, bool PF = true>
+template <typename T, class PL, int WMAX, int MODE, int OCC = 1, bool PF = true, bool ROWFAST = false>
 __global__ __launch_bounds__(WMAX *PL::Tp, OCC) void last_axis_kernel(LastAxisArgs<T> a)
 {
     __shared__ cx<T> sh[PL::L * WMAX];
-    last_axis_block<T, PL, WMAX, MODE, PF>(a, blockIdx.x, sh);
+    last_axis_block<T, PL, WMAX, MODE, PF, ROWFAST>(a, blockIdx.x, sh);
 }
 
 // ------------------------------------------------------------------------------------------------
