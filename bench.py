@@ -281,8 +281,8 @@ def main():
         counters_workload(args.counters)
         return
     if args.gpus != 1:
-        print("bench.py runs on one GPU only: this build has no multi-GPU path (see DESIGN.md for how the "
-              "step would shard).", file=sys.stderr)
+        print("bench.py runs on one GPU only: the library has no multi-GPU path (the step would shard by "
+              "slabs of the slowest axis with two all-to-all transposes per step).", file=sys.stderr)
         sys.exit(2)
 
     import torch

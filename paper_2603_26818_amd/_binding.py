@@ -102,7 +102,7 @@ def load_library():
         return _lib
     path = library_path()
     if not os.path.exists(path):
-        raise ImportError(f"{path} is not built; run __graft_entry__.build() (make -C paper_2603_26818_amd/csrc)")
+        raise ImportError(f"{path} is not built; build it with make -C paper_2603_26818_amd/csrc")
     try:
         import torch  # noqa: F401
     except ImportError:

@@ -26,7 +26,7 @@ def pfc():
 
 
 @pytest.fixture(scope="module")
-def oracle_cfg5():
+def oracle_512sq_2000():
     """FP64 CPU adjoint at the full size (about half a minute on the host)."""
     psi0 = P.pfc_initial_field(5, SHAPE, R0)
     target = oracle.rollout(oracle.Params(SHAPE, r=RT, dt=DT), psi0, NSTEPS)[-1]
@@ -57,9 +57,9 @@ def test_rollout_matches_oracle_small(pfc):
     assert abs(dr - dr_ref) < 1e-10 * abs(dr_ref)
 
 
-def test_rollout_cfg5_fp64_vs_cpu_adjoint(pfc, oracle_cfg5):
-    psi0, target_ref, L_ref, g_ref, dr_ref = oracle_cfg5
-    say(f"[rollout] cfg5 {SHAPE} {NSTEPS} steps FP64 vs CPU adjoint")
+def test_rollout_512sq_2000_fp64_vs_cpu_adjoint(pfc, oracle_512sq_2000):
+    psi0, target_ref, L_ref, g_ref, dr_ref = oracle_512sq_2000
+    say(f"[rollout] {SHAPE} {NSTEPS} steps FP64 vs CPU adjoint")
     target = _gpu_target(pfc, "f64", psi0)
     say(f"          target rel L2 vs oracle {relerr(to_np(target), target_ref):.2e}")
     plan = pfc.Plan(SHAPE, dtype="f64", r=R0, dt=DT)
@@ -71,13 +71,13 @@ def test_rollout_cfg5_fp64_vs_cpu_adjoint(pfc, oracle_cfg5):
     assert abs(dr - dr_ref) < 1e-8 * abs(dr_ref)
 
 
-def test_rollout_cfg5_central_differences(pfc):
+def test_rollout_512sq_2000_central_differences(pfc):
     """<dL/dpsi0, v> and dL/dr against central differences of the GPU FP64 forward.  Each estimate
     is Richardson-extrapolated, (4 D(h/2) - D(h)) / 3, which removes the h^2 truncation term; h is
     taken from a scan where successive extrapolated estimates agree best (the plateau)."""
     import torch
 
-    say(f"[rollout] cfg5 {SHAPE} FP64 central differences, 16 directions")
+    say(f"[rollout] {SHAPE} FP64 central differences, 16 directions")
     psi0 = P.pfc_initial_field(5, SHAPE, R0)
     target = _gpu_target(pfc, "f64", psi0)
     plan = pfc.Plan(SHAPE, dtype="f64", r=R0, dt=DT)
@@ -115,12 +115,12 @@ def test_rollout_cfg5_central_differences(pfc):
     assert worst < 1e-5 and rel_r < 1e-5
 
 
-def test_rollout_cfg5_fp32_vs_fp64(pfc, oracle_cfg5):
+def test_rollout_512sq_2000_fp32_vs_fp64(pfc, oracle_512sq_2000):
     """The FP32 run's gradient against the FP64 CPU adjoint.  Over 2000 steps the FP32 trajectory
     itself departs from FP64 by ~1e-4 (relative L2), and the backward sweep accumulates rounding over
     as many steps again; 1e-2 bounds the observed 1.6e-3 (psi0 gradient) and 3.6e-3 (dL/dr)."""
-    psi0, target_ref, L_ref, g_ref, dr_ref = oracle_cfg5
-    say(f"[rollout] cfg5 {SHAPE} FP32 vs FP64 CPU adjoint")
+    psi0, target_ref, L_ref, g_ref, dr_ref = oracle_512sq_2000
+    say(f"[rollout] {SHAPE} FP32 vs FP64 CPU adjoint")
     p32 = rounded(psi0, "f32")
     target = _gpu_target(pfc, "f32", p32)
     plan = pfc.Plan(SHAPE, dtype="f32", r=R0, dt=DT)

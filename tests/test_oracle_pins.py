@@ -232,7 +232,7 @@ def test_energy_closed_forms():
     assert abs(F - expect) < 1e-13 * abs(expect) and abs(Freal - expect) < 1e-13 * abs(expect)
 
 
-def test_energy_forms_agree_and_decrease_cfg1():
+def test_energy_forms_agree_and_decrease_128sq():
     """128^2 one-mode run (r = -0.25, dt = 0.5, psi0 = -0.25 + U(-0.1, 0.1), seed 1).  A sufficient
     condition for the semi-implicit step to decrease F is
         min_{q>0} [2/(dt q) + r + L(q)] >= 3 max|psi|^2  at both time levels;
