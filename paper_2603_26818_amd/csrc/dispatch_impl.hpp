@@ -36,6 +36,28 @@ static hipError_t by_length(int64_t L, F &&f)
 
 static inline int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
 
+// Calls f(std::bool_constant<nt>).
+template <class F>
+static hipError_t with_nt(bool nt, F &&f)
+{
+    return nt ? f(std::true_type{}) : f(std::false_type{});
+}
+
+// Workgroups per 128-byte line for column tiles of W complex values (1 for whole-line tiles).
+template <typename T>
+static int line_group(int W)
+{
+    const int bytes = W * (int)sizeof(cx<T>);
+    return bytes >= 128 ? 1 : 128 / bytes;
+}
+
+// Rows per workgroup of the x inverse pass: one wavefront (measured faster than 256 threads; the
+// pass's LDS round trips then need no cross-wave barrier).
+template <class PL>
+struct XInvRows {
+    static constexpr int value = (64 / PL::Tp) < 1 ? 1 : 64 / PL::Tp;
+};
+
 template <typename T>
 hipError_t launch_x_r2c(const Geom &g, const T *in, cx<T> *out, bool cube, const cx<T> *tw, hipStream_t s,
                         int variant)
@@ -50,9 +72,12 @@ hipError_t launch_x_r2c(const Geom &g, const T *in, cx<T> *out, bool cube, const
                 constexpr bool CUBE = decltype(cubec)::value;
                 constexpr int ROWS = XRows<PL>::value;
                 const dim3 grid((unsigned)cdiv(g.xrows, ROWS)), block(ROWS * PL::Tp);
-                hipLaunchKernelGGL((x_r2c_kernel<T, PL, ROWS, CUBE>), grid, block, 0, s, in, out, g.xrows, tw,
-                                   g.lt_shift);
-                return hipGetLastError();
+                // non-temporal hints measured faster at M = 256 and slower at M = 1024
+                return with_nt(g.nt && M < 1024, [&](auto ntc) -> hipError_t {
+                    hipLaunchKernelGGL((x_r2c_kernel<T, PL, ROWS, CUBE, false, decltype(ntc)::value>), grid, block, 0,
+                                       s, in, out, g.xrows, tw, g.lt_shift);
+                    return hipGetLastError();
+                });
             };
             if (!cube) return run(typename XFwdPlan<M>::type{}, std::false_type{});
             return with_plan<typename XFwdCands<M>::type>(variant, [&](auto plc) { return run(plc, std::true_type{}); });
@@ -70,13 +95,15 @@ hipError_t launch_x_c2r(const Geom &g, const cx<T> *in, T *out, const cx<T> *tw,
         } else {
             return with_plan<typename XInvCands<M>::type>(variant, [&](auto plc) -> hipError_t {
                 using PL = decltype(plc);
-                constexpr int ROWS = XRows<PL>::value;
+                constexpr int ROWS = XInvRows<PL>::value;
                 const dim3 grid((unsigned)cdiv(g.xrows, ROWS)), block(ROWS * PL::Tp);
                 const T sc = (T)(1.0 / ((double)g.M * (double)g.n0 * (double)g.nrows));
                 AdjEpi<T> ea{};
-                hipLaunchKernelGGL((x_c2r_kernel<T, PL, ROWS, EPI_PLAIN>), grid, block, 0, s, in, out, g.xrows, tw,
-                                   g.lt_shift, sc, ea);
-                return hipGetLastError();
+                return with_nt(g.nt, [&](auto ntc) -> hipError_t {
+                    hipLaunchKernelGGL((x_c2r_kernel<T, PL, ROWS, EPI_PLAIN, false, false, decltype(ntc)::value>), grid,
+                                       block, 0, s, in, out, g.xrows, tw, g.lt_shift, sc, ea);
+                    return hipGetLastError();
+                });
             });
         }
     });
@@ -119,13 +146,18 @@ hipError_t launch_y_c2c(const Geom &g, cx<T> *data, int dir, const cx<T> *tw, hi
                 const int W = (int)(g.M < WM ? g.M : WM);
                 const int64_t tiles = cdiv(g.M, W);
                 const dim3 grid((unsigned)(tiles * g.n0)), block(WM * PL::Tp);
-                if (dir < 0)
-                    hipLaunchKernelGGL((axis_c2c_kernel<T, PL, WM, -1>), grid, block, 0, s, data, data, W, g.M, g.M,
-                                       g.n1 * g.M, tiles, tw, g.lt_shift);
-                else
-                    hipLaunchKernelGGL((axis_c2c_kernel<T, PL, WM, +1>), grid, block, 0, s, data, data, W, g.M, g.M,
-                                       g.n1 * g.M, tiles, tw, g.lt_shift);
-                return hipGetLastError();
+                const int xg = line_group<T>(W);
+                // non-temporal only with whole-line tiles (measured slower on 64-byte tiles)
+                return with_nt(g.nt && xg == 1, [&](auto ntc) -> hipError_t {
+                    constexpr bool NT = decltype(ntc)::value;
+                    if (dir < 0)
+                        hipLaunchKernelGGL((axis_c2c_kernel<T, PL, WM, -1, 1, NT>), grid, block, 0, s, data, data, W,
+                                           g.M, g.M, g.n1 * g.M, tiles, tw, g.lt_shift, xg);
+                    else
+                        hipLaunchKernelGGL((axis_c2c_kernel<T, PL, WM, +1, 1, NT>), grid, block, 0, s, data, data, W,
+                                           g.M, g.M, g.n1 * g.M, tiles, tw, g.lt_shift, xg);
+                    return hipGetLastError();
+                });
             });
         }
     });
@@ -146,7 +178,7 @@ hipError_t launch_last_fwd(const Geom &g, const cx<T> *src, cx<T> *dst, const cx
             const int64_t tiles = cdiv(ncols, W);
             const dim3 grid((unsigned)tiles), block(WM * PL::Tp);
             hipLaunchKernelGGL((axis_c2c_kernel<T, PL, WM, -1>), grid, block, 0, s, src, dst, W, ncols, ncols,
-                               (int64_t)0, tiles, tw, g.lt_shift);
+                               (int64_t)0, tiles, tw, g.lt_shift, 1);
             return hipGetLastError();
         }
     });
@@ -181,8 +213,11 @@ hipError_t launch_last(const Geom &g, int mode, const cx<T> *src, cx<T> *dst, cx
             case LAST_STEP:
                 return with_plan<typename LastCands<L>::type>(variant, [&](auto plc) -> hipError_t {
                     using PL = decltype(plc);
-                    hipLaunchKernelGGL((last_axis_kernel<T, PL, WM, LA_STEP>), grid, dim3(WM * PL::Tp), 0, s, a);
-                    return hipGetLastError();
+                    return with_nt(g.nt && line_group<T>(a.W) == 1, [&](auto ntc) -> hipError_t {
+                        hipLaunchKernelGGL((last_axis_kernel<T, PL, WM, LA_STEP, 1, true, false, decltype(ntc)::value>),
+                                           grid, dim3(WM * PL::Tp), 0, s, a);
+                        return hipGetLastError();
+                    });
                 });
             case LAST_R2C_NATURAL:
                 hipLaunchKernelGGL((last_axis_kernel<T, P0, WM, LA_R2C_NATURAL>), grid, dim3(WM * P0::Tp), 0, s, a);

@@ -10,8 +10,10 @@
 //   thread butterfly j in [0, L/R):  a_r = x[j + r L/R] * W_{Ns R}^{(j mod Ns) r},  r < R
 //                                    y   = DFT_R(a)
 //                                    out[(j / Ns) Ns R + (j mod Ns) + r Ns] = y_r
-// which after the last stage (Ns R = L) writes element j + r L/R.  Twiddles come from one table of
-// W_Lt^e = exp(-2 pi i e / Lt), e < Lt, for a power of two Lt >= L, computed on the host.
+// which after the last stage (Ns R = L) writes element j + r L/R.  Twiddles come from the buffer
+// described in types.hpp (computed on the host): either the table W_Lt^e = exp(-2 pi i e / Lt),
+// e < Lt, for a power of two Lt >= L (TW_LT), or the per-stage tables stored after it, where the
+// R - 1 twiddles of a butterfly are adjacent and need no index arithmetic (TW_STAGE).
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -212,13 +214,41 @@ __device__ __forceinline__ cx<T> twiddle(const cx<T> *__restrict__ tw, int lt_sh
 
 __host__ __device__ constexpr int ilog2c(int v) { return v <= 1 ? 0 : 1 + ilog2c(v / 2); }
 
+enum { TW_LT = 0, TW_STAGE = 1 };
+
+// Multiplies v[r], 0 < r < R, by the twiddles W_{Ns R}^{jj r} (conjugated for the inverse).
+template <typename T, int R, int Ns, int DIR, int TWM>
+__device__ __forceinline__ void apply_twiddles(cx<T> *v, int jj, const cx<T> *__restrict__ tw, int lt_shift)
+{
+    if constexpr (TWM == TW_STAGE) {
+        const cx<T> *st = tw + (1u << lt_shift) + stage_tw_offset(Ns * R, R) + (unsigned)(jj * R);
+        if constexpr (sizeof(T) == 4) {
+            // FP32: two twiddles per 16-byte load (entry 0 is 1 and is skipped)
+            typedef float f32x4 __attribute__((ext_vector_type(4)));
+            const f32x4 *q = reinterpret_cast<const f32x4 *>(st);
+#pragma unroll
+            for (int h = 0; h < R / 2; ++h) {
+                const f32x4 w = q[h];
+                if (h > 0) v[2 * h] = cmul(v[2 * h], cx<T>{w.x, DIR > 0 ? -w.y : w.y});
+                v[2 * h + 1] = cmul(v[2 * h + 1], cx<T>{w.z, DIR > 0 ? -w.w : w.w});
+            }
+        } else {
+#pragma unroll
+            for (int r = 1; r < R; ++r) v[r] = cmul(v[r], DIR > 0 ? conj(st[r]) : st[r]);
+        }
+    } else {
+#pragma unroll
+        for (int r = 1; r < R; ++r) v[r] = cmul(v[r], twiddle<T, DIR>(tw, lt_shift, jj * r, ilog2c(Ns * R)));
+    }
+}
+
 // Runs every stage of the schedule PL for one pencil.
 // On entry: v[b * R0 + r] = x[t + b Tp + r L / R0] for b < Rmax / R0 (R0 = first radix).
 // On exit:  v[b * Rl + r] = X[t + b Tp + r L / Rl] for b < Rmax / Rl (Rl = last radix).
 // `lds(e)` returns a reference to this pencil's LDS slot for element e.  Contains workgroup
 // barriers, so every thread of the workgroup must call it (idle threads included).  The first LDS
 // write is preceded by a barrier, so the caller may have used the same LDS just before.
-template <typename T, class PL, int DIR, class Lds>
+template <typename T, class PL, int DIR, int TWM = TW_STAGE, class Lds>
 __device__ __forceinline__ void fft_stages(cx<T> *v, int t, Lds &&lds, const cx<T> *__restrict__ tw, int lt_shift)
 {
     constexpr int L = PL::L;
@@ -234,10 +264,7 @@ __device__ __forceinline__ void fft_stages(cx<T> *v, int t, Lds &&lds, const cx<
                 const int j = t + b * Tp;
 #pragma unroll
                 for (int r = 0; r < R; ++r) v[b * R + r] = lds(j + r * (L / R));
-                const int jj = j & (Ns - 1);
-#pragma unroll
-                for (int r = 1; r < R; ++r)
-                    v[b * R + r] = cmul(v[b * R + r], twiddle<T, DIR>(tw, lt_shift, jj * r, ilog2c(Ns * R)));
+                apply_twiddles<T, R, Ns, DIR, TWM>(&v[b * R], j & (Ns - 1), tw, lt_shift);
             }
         }
 #pragma unroll

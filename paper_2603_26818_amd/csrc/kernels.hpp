@@ -30,11 +30,43 @@ __device__ __forceinline__ T corr_op(const ModelParams<T> &m, T q)
     return a * (b * b + m.R1);
 }
 
-// A(q) = 1 / (1 + dt q (r + L(q))); exactly 1 at q = 0.
+// A(q) = 1 / (1 + dt q (r + L(q))); exactly 1 at q = 0.  FP32 takes the hardware reciprocal
+// (within 1 ulp, exact for 1); FP64 divides.
 template <typename T>
 __device__ __forceinline__ T amult(const ModelParams<T> &m, T q)
 {
-    return T(1) / (T(1) + m.dt * q * (m.r + corr_op(m, q)));
+    const T d = T(1) + m.dt * q * (m.r + corr_op(m, q));
+    if constexpr (sizeof(T) == 4)
+        return __builtin_amdgcn_rcpf(d);
+    else
+        return T(1) / d;
+}
+
+// Loads and stores of the streamed grids.  NT marks them non-temporal: on grids far larger than
+// the caches, nothing a pass touches is read again before it is evicted.
+template <bool NT, typename T>
+__device__ __forceinline__ cx<T> ld_grid(const cx<T> *p)
+{
+    if constexpr (NT) {
+        typedef T v2 __attribute__((ext_vector_type(2)));
+        const v2 v = __builtin_nontemporal_load(reinterpret_cast<const v2 *>(p));
+        return {v.x, v.y};
+    } else {
+        return *p;
+    }
+}
+template <bool NT, typename T>
+__device__ __forceinline__ void st_grid(cx<T> *p, cx<T> a)
+{
+    if constexpr (NT) {
+        typedef T v2 __attribute__((ext_vector_type(2)));
+        v2 v;
+        v.x = a.x;
+        v.y = a.y;
+        __builtin_nontemporal_store(v, reinterpret_cast<v2 *>(p));
+    } else {
+        *p = a;
+    }
 }
 
 __device__ __forceinline__ int signed_index(int64_t i, int64_t n) { return (int)(i <= n / 2 ? i : i - n); }
@@ -78,7 +110,7 @@ __device__ __forceinline__ int xidx(int e) { return PAD ? xpad(e) : e; }
 
 // One block of ROWS rows (block index `bid`); `sh` holds ROWS * XPitch<M, PAD> LDS slots.
 // Uses threads 0 .. ROWS*Tp-1, which must be all threads of the workgroup.
-template <typename T, class PL, int ROWS, bool CUBE, bool PAD = false>
+template <typename T, class PL, int ROWS, bool CUBE, bool PAD = false, bool NT = false>
 __device__ __forceinline__ void x_r2c_block(const T *__restrict__ in, cx<T> *__restrict__ out, int64_t nrows,
                                             const cx<T> *__restrict__ tw, int lt_shift, int64_t bid, cx<T> *sh)
 {
@@ -93,12 +125,12 @@ __device__ __forceinline__ void x_r2c_block(const T *__restrict__ in, cx<T> *__r
     for (int b = 0; b < Rmax / R0; ++b)
 #pragma unroll
         for (int r = 0; r < R0; ++r) {
-            cx<T> z = valid ? src[t + b * Tp + r * (M / R0)] : cx<T>{T(0), T(0)};
+            cx<T> z = valid ? ld_grid<NT>(&src[t + b * Tp + r * (M / R0)]) : cx<T>{T(0), T(0)};
             if constexpr (CUBE) z = {z.x * z.x * z.x, z.y * z.y * z.y};
             v[b * R0 + r] = z;
         }
     auto lds = [&](int e) -> cx<T> & { return sh[p * LD + xidx<PAD>(e)]; };
-    fft_stages<T, PL, -1>(v, t, lds, tw, lt_shift);
+    fft_stages<T, PL, -1, TW_LT>(v, t, lds, tw, lt_shift);  // measured faster here than TW_STAGE
     __syncthreads();
 #pragma unroll
     for (int b = 0; b < Rmax / Rl; ++b)
@@ -123,17 +155,17 @@ __device__ __forceinline__ void x_r2c_block(const T *__restrict__ in, cx<T> *__r
                 const cx<T> O = {(Zk.y + Zp.y) * h, (Zp.x - Zk.x) * h};
                 X = E + cmul(tw[k << (lt_shift - tshift)], O);
             }
-            if (valid) dst[k] = X;
+            if (valid) st_grid<NT>(&dst[k], X);
         }
 }
 
-template <typename T, class PL, int ROWS, bool CUBE, bool PAD = false>
+template <typename T, class PL, int ROWS, bool CUBE, bool PAD = false, bool NT = false>
 __global__ __launch_bounds__(ROWS *PL::Tp) void x_r2c_kernel(const T *__restrict__ in, cx<T> *__restrict__ out,
                                                               int64_t nrows, const cx<T> *__restrict__ tw,
                                                               int lt_shift)
 {
     __shared__ cx<T> sh[ROWS * XPitch<PL::L, PAD>::value];
-    x_r2c_block<T, PL, ROWS, CUBE, PAD>(in, out, nrows, tw, lt_shift, blockIdx.x, sh);
+    x_r2c_block<T, PL, ROWS, CUBE, PAD, NT>(in, out, nrows, tw, lt_shift, blockIdx.x, sh);
 }
 
 // ------------------------------------------------------------------------------------------------
@@ -159,7 +191,7 @@ struct AdjEpi {
 // Pre-combination of one row for the c2r: own elements X(k) from `src`; the mirror X(M-k) either
 // through LDS (PG = false) or straight from `src` (PG = true: a second, reversed but coalesced load of
 // the same cache lines, without the LDS round trip and its barrier).
-template <typename T, class PL, int ROWS, bool PAD, bool PG = false>
+template <typename T, class PL, int ROWS, bool PAD, bool PG = false, bool NT = false>
 __device__ __forceinline__ void x_c2r_row(cx<T> *v, const cx<T> *src, bool valid, int t, cx<T> *rowlds,
                                           const cx<T> *__restrict__ tw, int lt_shift)
 {
@@ -172,8 +204,8 @@ __device__ __forceinline__ void x_c2r_row(cx<T> *v, const cx<T> *src, bool valid
 #pragma unroll
             for (int r = 0; r < R0; ++r) {
                 const int k = t + b * Tp + r * (M / R0);
-                v[b * R0 + r] = valid ? src[k] : cx<T>{T(0), T(0)};
-                mir[b * R0 + r] = valid ? src[(M - k) & (M - 1)] : cx<T>{T(0), T(0)};
+                v[b * R0 + r] = valid ? ld_grid<NT>(&src[k]) : cx<T>{T(0), T(0)};
+                mir[b * R0 + r] = valid ? ld_grid<NT>(&src[(M - k) & (M - 1)]) : cx<T>{T(0), T(0)};
             }
     } else {
         __syncthreads();
@@ -182,7 +214,7 @@ __device__ __forceinline__ void x_c2r_row(cx<T> *v, const cx<T> *src, bool valid
 #pragma unroll
             for (int r = 0; r < R0; ++r) {
                 const int k = t + b * Tp + r * (M / R0);
-                v[b * R0 + r] = valid ? src[k] : cx<T>{T(0), T(0)};
+                v[b * R0 + r] = valid ? ld_grid<NT>(&src[k]) : cx<T>{T(0), T(0)};
                 rowlds[xidx<PAD>(k)] = v[b * R0 + r];
             }
         __syncthreads();
@@ -210,7 +242,7 @@ __device__ __forceinline__ void x_c2r_row(cx<T> *v, const cx<T> *src, bool valid
         }
 }
 
-template <typename T, class PL, int ROWS, int EPI, bool PAD = false, bool PG = false>
+template <typename T, class PL, int ROWS, int EPI, bool PAD = false, bool PG = false, bool NT = false>
 __device__ __forceinline__ void x_c2r_block(const cx<T> *in, T *out, int64_t nrows, const cx<T> *__restrict__ tw,
                                             int lt_shift, T sc, const AdjEpi<T> &ea, int64_t bid, cx<T> *sh)
 {
@@ -222,7 +254,7 @@ __device__ __forceinline__ void x_c2r_block(const cx<T> *in, T *out, int64_t nro
     const int64_t r0 = valid ? row : 0;
     auto lds = [&](int e) -> cx<T> & { return sh[p * LD + xidx<PAD>(e)]; };
     cx<T> v[Rmax];
-    x_c2r_row<T, PL, ROWS, PAD, PG>(v, in + r0 * M, valid, t, &sh[p * LD], tw, lt_shift);
+    x_c2r_row<T, PL, ROWS, PAD, PG, NT>(v, in + r0 * M, valid, t, &sh[p * LD], tw, lt_shift);
     fft_stages<T, PL, +1>(v, t, lds, tw, lt_shift);
     cx<T> *dst = reinterpret_cast<cx<T> *>(out) + r0 * M;
     if constexpr (EPI == EPI_PLAIN) {
@@ -231,7 +263,7 @@ __device__ __forceinline__ void x_c2r_block(const cx<T> *in, T *out, int64_t nro
             for (int b = 0; b < Rmax / Rl; ++b)
 #pragma unroll
                 for (int r = 0; r < Rl; ++r)
-                    dst[t + b * Tp + r * (M / Rl)] = scale(v[b * Rl + r], sc);
+                    st_grid<NT>(&dst[t + b * Tp + r * (M / Rl)], scale(v[b * Rl + r], sc));
         }
     } else {
         cx<T> w[Rmax];
@@ -258,21 +290,37 @@ __device__ __forceinline__ void x_c2r_block(const cx<T> *in, T *out, int64_t nro
     }
 }
 
-template <typename T, class PL, int ROWS, int EPI, bool PAD = false, bool PG = false>
+template <typename T, class PL, int ROWS, int EPI, bool PAD = false, bool PG = false, bool NT = false>
 __global__ __launch_bounds__(ROWS *PL::Tp) void x_c2r_kernel(const cx<T> *in, T *out, int64_t nrows,
                                                               const cx<T> *__restrict__ tw, int lt_shift, T sc,
                                                               AdjEpi<T> ea)
 {
     __shared__ cx<T> sh[ROWS * XPitch<PL::L, PAD>::value];
-    x_c2r_block<T, PL, ROWS, EPI, PAD, PG>(in, out, nrows, tw, lt_shift, sc, ea, blockIdx.x, sh);
+    x_c2r_block<T, PL, ROWS, EPI, PAD, PG, NT>(in, out, nrows, tw, lt_shift, sc, ea, blockIdx.x, sh);
+}
+
+// ------------------------------------------------------------------------------------------------
+// Workgroup order for column tiles narrower than a 128-byte line.  Consecutive workgroups are
+// dispatched to the 8 XCDs in turn, so workgroups b, b + 8, ..., b + 8 (G - 1) share one XCD and
+// its L2; they are given G adjacent tiles, which then share every line in that L2 instead of
+// fetching and writing it from G XCDs.  A permutation of [0, n): an incomplete last group keeps
+// its indices.
+__device__ __forceinline__ int64_t xcd_tile_order(int64_t b, int64_t n, int G)
+{
+    if (G <= 1) return b;
+    const int64_t span = 8 * (int64_t)G, full = n - n % span;
+    if (b >= full) return b;
+    const int64_t grp = b / span, w = b - grp * span;
+    return (grp * 8 + (w & 7)) * G + (w >> 3);
 }
 
 // ------------------------------------------------------------------------------------------------
 // Strided complex FFT along one axis, out of place or in place (src == dst).
 // Pencil (batch, col) has element e at  batch*bstride + e*estride + col,  col < ncols contiguous.
 // A workgroup handles W adjacent columns (W <= WMAX); its threads are laid out column-fastest so
-// each load/store instruction moves W * sizeof(cx) contiguous bytes per element row.
-template <typename T, class PL, int WMAX, int DIR>
+// each load/store instruction moves W * sizeof(cx) contiguous bytes per element row.  `bid` is the
+// logical tile index (see xcd_tile_order).
+template <typename T, class PL, int WMAX, int DIR, bool NT = false>
 __device__ __forceinline__ void axis_c2c_block(const cx<T> *src, cx<T> *dst, int W, int64_t ncols, int64_t estride,
                                                int64_t bstride, int64_t tiles_per_batch,
                                                const cx<T> *__restrict__ tw, int lt_shift, int64_t bid, cx<T> *sh)
@@ -288,26 +336,28 @@ __device__ __forceinline__ void axis_c2c_block(const cx<T> *src, cx<T> *dst, int
     for (int b = 0; b < Rmax / R0; ++b)
 #pragma unroll
         for (int r = 0; r < R0; ++r)
-            v[b * R0 + r] = valid ? src[base + (int64_t)(t + b * Tp + r * (L / R0)) * estride] : cx<T>{T(0), T(0)};
+            v[b * R0 + r] = valid ? ld_grid<NT>(&src[base + (int64_t)(t + b * Tp + r * (L / R0)) * estride])
+                                  : cx<T>{T(0), T(0)};
     auto lds = [&](int e) -> cx<T> & { return sh[e * WMAX + p]; };
     fft_stages<T, PL, DIR>(v, t, lds, tw, lt_shift);
     if (valid) {
 #pragma unroll
         for (int b = 0; b < Rmax / Rl; ++b)
 #pragma unroll
-            for (int r = 0; r < Rl; ++r) dst[base + (int64_t)(t + b * Tp + r * (L / Rl)) * estride] = v[b * Rl + r];
+            for (int r = 0; r < Rl; ++r)
+                st_grid<NT>(&dst[base + (int64_t)(t + b * Tp + r * (L / Rl)) * estride], v[b * Rl + r]);
     }
 }
 
-template <typename T, class PL, int WMAX, int DIR, int OCC = 1>
+template <typename T, class PL, int WMAX, int DIR, int OCC = 1, bool NT = false>
 __global__ __launch_bounds__(WMAX *PL::Tp, OCC) void axis_c2c_kernel(const cx<T> *src, cx<T> *dst, int W,
                                                                  int64_t ncols, int64_t estride, int64_t bstride,
                                                                  int64_t tiles_per_batch,
-                                                                 const cx<T> *__restrict__ tw, int lt_shift)
+                                                                 const cx<T> *__restrict__ tw, int lt_shift, int xg)
 {
     __shared__ cx<T> sh[PL::L * WMAX];
-    axis_c2c_block<T, PL, WMAX, DIR>(src, dst, W, ncols, estride, bstride, tiles_per_batch, tw, lt_shift, blockIdx.x,
-                                     sh);
+    axis_c2c_block<T, PL, WMAX, DIR, NT>(src, dst, W, ncols, estride, bstride, tiles_per_batch, tw, lt_shift,
+                                         xcd_tile_order(blockIdx.x, gridDim.x, xg), sh);
 }
 
 // ------------------------------------------------------------------------------------------------
@@ -381,7 +431,7 @@ __device__ __forceinline__ SlotInfo la_slot(int64_t nrows, int TR, int W, int p,
     return s;
 }
 
-template <typename T, class PL, int WMAX, int MODE, bool PF = true, bool ROWFAST = false>
+template <typename T, class PL, int WMAX, int MODE, bool PF = true, bool ROWFAST = false, bool NT = false>
 __device__ __forceinline__ void last_axis_block(const LastAxisArgs<T> &a, int64_t bid, cx<T> *sh)
 {
     constexpr int L = PL::L, Tp = PL::Tp, Rmax = PL::Rmax;
@@ -439,6 +489,20 @@ __device__ __forceinline__ void last_axis_block(const LastAxisArgs<T> &a, int64_
         }
         return;
     } else {
+        // Element e = t + k of this lane's pencil lies at (t + k) * estride + coloff.  The address
+        // is split into a wave-uniform part (the tile origin, the wave's first t, and k * estride:
+        // scalar registers) and a per-lane 32-bit byte offset (t below the wave's first t by less
+        // than 64 / WMAX, row and column inside the tile), so no per-element 64-bit vector
+        // arithmetic is needed.
+        const SlotInfo s0 = la_slot<ROWFAST>(nrows, a.tiles_per_row, W, 0, bid);
+        const int t0 = __builtin_amdgcn_readfirstlane(t);
+        const int64_t uoff = (int64_t)t0 * estride + s0.row * M + s0.kx;
+        const uint32_t loff =
+            (uint32_t)(((int64_t)(t - t0) * estride + (si.row - s0.row) * M + (si.kx - s0.kx)) * (int64_t)sizeof(cx<T>));
+        auto gp = [&](const cx<T> *base, int k) -> cx<T> * {
+            return reinterpret_cast<cx<T> *>(
+                reinterpret_cast<char *>(const_cast<cx<T> *>(base) + uoff + (int64_t)k * estride) + loff);
+        };
         // STEP with PF: the state values this thread updates are loaded before the forward FFT so
         // that their latency overlaps the FFT
         cx<T> spre[(MODE == LA_STEP && PF) ? Rmax : 1];
@@ -447,8 +511,7 @@ __device__ __forceinline__ void last_axis_block(const LastAxisArgs<T> &a, int64_
             for (int b = 0; b < Rmax / Rl; ++b)
 #pragma unroll
                 for (int r = 0; r < Rl; ++r)
-                    spre[b * Rl + r] = valid ? a.state[(int64_t)(t + b * Tp + r * (L / Rl)) * estride + coloff]
-                                             : cx<T>{T(0), T(0)};
+                    spre[b * Rl + r] = valid ? ld_grid<NT>(gp(a.state, b * Tp + r * (L / Rl))) : cx<T>{T(0), T(0)};
         }
         // packed input, forward FFT
         constexpr int R0 = PL::first;
@@ -456,8 +519,7 @@ __device__ __forceinline__ void last_axis_block(const LastAxisArgs<T> &a, int64_
         for (int b = 0; b < Rmax / R0; ++b)
 #pragma unroll
             for (int r = 0; r < R0; ++r)
-                v[b * R0 + r] =
-                    valid ? a.src[(int64_t)(t + b * Tp + r * (L / R0)) * estride + coloff] : cx<T>{T(0), T(0)};
+                v[b * R0 + r] = valid ? ld_grid<NT>(gp(a.src, b * Tp + r * (L / R0))) : cx<T>{T(0), T(0)};
         fft_stages<T, PL, -1>(v, t, lds, a.tw, a.lt_shift);
         // forward spectrum in natural order: v[b*Rl + r] = X(e), e = t + b*Tp + r*L/Rl
         if (si.has_pairs) {  // uniform per workgroup
@@ -505,16 +567,16 @@ __device__ __forceinline__ void last_axis_block(const LastAxisArgs<T> &a, int64_
                     const T kz = mp.fk[0] * (T)signed_index(e, L);
                     const cx<T> N = {v[b * Rl + r].x * nl, v[b * Rl + r].y * nl};
                     if (si.partner < 0) {
-                        const int64_t gi = (int64_t)e * estride + coloff;
+                        cx<T> *gi = gp(a.state, b * Tp + r * (L / Rl));
                         cx<T> S;
                         if constexpr (PF)
                             S = spre[b * Rl + r];
                         else
-                            S = valid ? a.state[gi] : cx<T>{T(0), T(0)};
+                            S = valid ? ld_grid<NT>(gi) : cx<T>{T(0), T(0)};
                         const T q = kz * kz + ky * ky + kx * kx;
                         const T A = amult(mp, q), dq = dt * q;
                         const cx<T> Snew = {(S.x - dq * N.x) * A, (S.y - dq * N.y) * A};
-                        if (valid) a.state[gi] = Snew;
+                        if (valid) st_grid<NT>(gi, Snew);
                         v[b * Rl + r] = Snew;
                     } else {
                         const cx<T> Np = {partner_val(e).x * nl, partner_val(e).y * nl};
@@ -537,7 +599,7 @@ __device__ __forceinline__ void last_axis_block(const LastAxisArgs<T> &a, int64_
                             if constexpr (PF)
                                 lds(e) = spre[b * Rl + r];
                             else
-                                lds(e) = a.state[(int64_t)e * estride + coloff];
+                                lds(e) = ld_grid<NT>(gp(a.state, b * Tp + r * (L / Rl)));
                         }
                     }
                 __syncthreads();
@@ -548,12 +610,12 @@ __device__ __forceinline__ void last_axis_block(const LastAxisArgs<T> &a, int64_
                         for (int r = 0; r < Rl; ++r) {
                             const int e = t + b * Tp + r * (L / Rl);
                             const T kz = mp.fk[0] * (T)signed_index(e, L);
-                            const int64_t gi = (int64_t)e * estride + coloff;
+                            cx<T> *gi = gp(a.state, b * Tp + r * (L / Rl));
                             cx<T> S;
                             if constexpr (PF)
                                 S = spre[b * Rl + r];
                             else
-                                S = valid ? a.state[gi] : cx<T>{T(0), T(0)};
+                                S = valid ? ld_grid<NT>(gi) : cx<T>{T(0), T(0)};
                             const cx<T> Sp = partner_val(e);
                             const cx<T> S0 = {(S.x + Sp.x) * h, (S.y - Sp.y) * h};
                             const cx<T> SN = {(S.y + Sp.y) * h, (Sp.x - S.x) * h};
@@ -562,7 +624,7 @@ __device__ __forceinline__ void last_axis_block(const LastAxisArgs<T> &a, int64_
                             const cx<T> G = v[b * Rl + r];
                             // A0 S0 + i AN SN + G
                             const cx<T> Snew = {A0 * S0.x - AN * SN.y + G.x, A0 * S0.y + AN * SN.x + G.y};
-                            if (valid) a.state[gi] = Snew;
+                            if (valid) st_grid<NT>(gi, Snew);
                             v[b * Rl + r] = Snew;
                         }
                 }
@@ -573,8 +635,7 @@ __device__ __forceinline__ void last_axis_block(const LastAxisArgs<T> &a, int64_
 #pragma unroll
                 for (int b = 0; b < Rmax / Rf; ++b)
 #pragma unroll
-                    for (int r = 0; r < Rf; ++r)
-                        a.dst[(int64_t)(t + b * Tp + r * (L / Rf)) * estride + coloff] = v[b * Rf + r];
+                    for (int r = 0; r < Rf; ++r) st_grid<NT>(gp(a.dst, b * Tp + r * (L / Rf)), v[b * Rf + r]);
             }
         } else if constexpr (MODE == LA_ADJOINT) {
             cx<T> w[Rmax];
@@ -626,11 +687,11 @@ __device__ __forceinline__ void last_axis_block(const LastAxisArgs<T> &a, int64_
     }
 }
 
-template <typename T, class PL, int WMAX, int MODE, int OCC = 1, bool PF = true, bool ROWFAST = false>
+template <typename T, class PL, int WMAX, int MODE, int OCC = 1, bool PF = true, bool ROWFAST = false, bool NT = false>
 __global__ __launch_bounds__(WMAX *PL::Tp, OCC) void last_axis_kernel(LastAxisArgs<T> a)
 {
     __shared__ cx<T> sh[PL::L * WMAX];
-    last_axis_block<T, PL, WMAX, MODE, PF, ROWFAST>(a, blockIdx.x, sh);
+    last_axis_block<T, PL, WMAX, MODE, PF, ROWFAST, NT>(a, blockIdx.x, sh);
 }
 
 // ------------------------------------------------------------------------------------------------

@@ -28,11 +28,11 @@ int step_candidates(const Geom &g, int pass)
         return hipSuccess;
     };
     switch (id) {
-    case 0: by_length(g.M, [&](auto l) { return count(l, std::integral_constant<int, 0>{}); }); break;
+    case 0: (void)by_length(g.M, [&](auto l) { return count(l, std::integral_constant<int, 0>{}); }); break;
     case 1:
-    case 3: by_length(g.n1, [&](auto l) { return count(l, std::integral_constant<int, 1>{}); }); break;
-    case 2: by_length(g.n0, [&](auto l) { return count(l, std::integral_constant<int, 2>{}); }); break;
-    case 4: by_length(g.M, [&](auto l) { return count(l, std::integral_constant<int, 3>{}); }); break;
+    case 3: (void)by_length(g.n1, [&](auto l) { return count(l, std::integral_constant<int, 1>{}); }); break;
+    case 2: (void)by_length(g.n0, [&](auto l) { return count(l, std::integral_constant<int, 2>{}); }); break;
+    case 4: (void)by_length(g.M, [&](auto l) { return count(l, std::integral_constant<int, 3>{}); }); break;
     default: break;
     }
     return n;

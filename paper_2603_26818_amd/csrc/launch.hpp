@@ -17,6 +17,7 @@ struct Geom {
     int64_t nrows;       // rows of the last-axis pass: n1 (3D) or 1 (2D)
     int64_t xrows;       // rows of the x pass: n0 * nrows
     int lt_shift;        // log2 of the twiddle table length
+    bool nt;             // non-temporal loads/stores of the grids in the step and FFT passes
 };
 
 // `variant`: candidate schedule of the pass (0 = default); only the step's passes (x r2c with the

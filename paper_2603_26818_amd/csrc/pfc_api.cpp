@@ -164,6 +164,34 @@ void twiddle_value(int64_t e, int64_t Lt, long double *c, long double *s)
     *s = -ss;  // forward sign
 }
 
+// The twiddle buffer (layout in types.hpp): Lt entries of W_Lt^e, then the per-stage tables,
+// every value rounded once from twiddle_value.
+size_t twiddle_count(int64_t Lt) { return (size_t)(Lt + pfc::stage_tw_entries(Lt)); }
+
+template <typename T>
+std::vector<cx<T>> twiddle_table(int64_t Lt)
+{
+    std::vector<cx<T>> tw(twiddle_count(Lt));
+    for (int64_t e = 0; e < Lt; ++e) {
+        long double c, sn;
+        twiddle_value(e, Lt, &c, &sn);
+        tw[e].x = (T)c;
+        tw[e].y = (T)sn;
+    }
+    for (int64_t Np = 2; Np <= Lt; Np *= 2)
+        for (int R = 2; R <= 16 && R <= Np; R *= 2) {
+            cx<T> *blk = tw.data() + Lt + pfc::stage_tw_offset(Np, R);
+            for (int64_t jj = 0; jj < Np / R; ++jj)
+                for (int r = 0; r < R; ++r) blk[jj * R + r] = tw[(jj * r * (Lt / Np)) % Lt];
+        }
+    return tw;
+}
+
+// Grids whose state exceeds this use non-temporal loads and stores in the step and FFT passes:
+// a pass's three grids then no longer fit in the 256 MB memory-side cache, and the hint keeps the
+// caches from holding lines that are not read again.
+constexpr size_t kNonTemporalBytes = size_t(128) << 20;
+
 struct DeviceGuard {
     int prev = -1;
     hipError_t err = hipSuccess;
@@ -555,14 +583,7 @@ pfc_status batch_bind_impl(pfc_batch *b)
 {
     pfc_status st = batch_upload_table<T>(b);
     if (st) return st;
-    const int64_t Lt = int64_t(1) << b->lt_shift;
-    std::vector<cx<T>> tw(Lt);
-    for (int64_t e = 0; e < Lt; ++e) {
-        long double c, sn;
-        twiddle_value(e, Lt, &c, &sn);
-        tw[e].x = (T)c;
-        tw[e].y = (T)sn;
-    }
+    const std::vector<cx<T>> tw = twiddle_table<T>(int64_t(1) << b->lt_shift);
     PFC_TRY(hipMemcpy(b->ws + b->tw_off, tw.data(), tw.size() * sizeof(tw[0]), hipMemcpyHostToDevice),
             "twiddle upload");
     PFC_TRY(hipMemset(b->ws + b->ctl_off, 0, sizeof(pfc::BatchCtl)), "barrier state reset");
@@ -634,6 +655,7 @@ pfc_status batch_state_init_impl(pfc_batch *b, hipStream_t s)
         g.nrows = 1;
         g.xrows = in.n0;
         g.lt_shift = b->lt_shift;
+        g.nt = false;
         cx<T> *scratch = (cx<T> *)(b->ws + b->scratch_off[i]);
         PFC_TRY(pfc::launch_x_r2c<T>(g, (const T *)b->psi[i], scratch, false, tw, s), "x_r2c launch");
         PFC_TRY(pfc::launch_last_fwd<T>(g, scratch, (cx<T> *)b->state[i], tw, s), "last-axis launch");
@@ -747,8 +769,9 @@ pfc_status pfc_plan_create(pfc_plan **out, const pfc_plan_desc *d)
     while ((int64_t(1) << g.lt_shift) < Lt) ++g.lt_shift;
     const size_t cs = cx_size(p);
     p->n_partials = (size_t)std::max<int64_t>(2 * pfc::kReduceBlocks, g.xrows);
+    g.nt = state_bytes(p) >= kNonTemporalBytes;
     p->tw_off = 0;
-    p->partial_off = align256((size_t)Lt * cs);
+    p->partial_off = align256(twiddle_count(Lt) * cs);
     p->watch_off = p->partial_off + align256(p->n_partials * sizeof(double));
     p->scratch_off = p->watch_off + 256;
     p->ws_need = p->scratch_off + align256(state_bytes(p));
@@ -768,19 +791,13 @@ pfc_status pfc_plan_set_workspace(pfc_plan *p, void *dev_ptr, size_t bytes)
     if (((uintptr_t)dev_ptr & 255u) != 0) return fail(PFC_ERR_ALIGNMENT, "workspace must be 256-byte aligned");
     if (bytes < p->ws_need) return fail(PFC_ERR_WORKSPACE, "workspace has %zu bytes, needs %zu", bytes, p->ws_need);
     const int64_t Lt = int64_t(1) << p->g.lt_shift;
-    std::vector<char> host((size_t)Lt * cx_size(p));
-    for (int64_t e = 0; e < Lt; ++e) {
-        long double c, s;
-        twiddle_value(e, Lt, &c, &s);
-        if (p->d.dtype == PFC_F64) {
-            double *t = reinterpret_cast<double *>(host.data()) + 2 * e;
-            t[0] = (double)c;
-            t[1] = (double)s;
-        } else {
-            float *t = reinterpret_cast<float *>(host.data()) + 2 * e;
-            t[0] = (float)c;
-            t[1] = (float)s;
-        }
+    std::vector<char> host;
+    if (p->d.dtype == PFC_F64) {
+        const std::vector<cx<double>> tw = twiddle_table<double>(Lt);
+        host.assign((const char *)tw.data(), (const char *)(tw.data() + tw.size()));
+    } else {
+        const std::vector<cx<float>> tw = twiddle_table<float>(Lt);
+        host.assign((const char *)tw.data(), (const char *)(tw.data() + tw.size()));
     }
     DeviceGuard dg(p->d.device);
     if (dg.err != hipSuccess) return hip_fail(dg.err, "hipSetDevice");
@@ -1007,7 +1024,7 @@ pfc_status pfc_batch_create(pfc_batch **out, const pfc_plan_desc *descs, int cou
     b->ctl_off = 0;
     b->inst_off = 256;
     b->tw_off = b->inst_off + align256(inst_size * count);
-    b->partial_off = b->tw_off + align256((size_t)Lt * cs);
+    b->partial_off = b->tw_off + align256(twiddle_count(Lt) * cs);
     size_t off = b->partial_off + align256(pfc::kReduceBlocks * sizeof(double));
     for (int i = 0; i < count; ++i) {
         b->scratch_off.push_back(off);

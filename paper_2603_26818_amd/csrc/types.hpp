@@ -11,6 +11,23 @@ struct alignas(2 * sizeof(T)) cx {
     T x, y;
 };
 
+// Twiddle buffer layout.  Entries [0, Lt): W_Lt^e = exp(-2 pi i e / Lt) for a power of two Lt.
+// After them, per-stage tables: for every stage size N' = Ns R (power of two, 2 <= N' <= Lt) and
+// radix R in {2, 4, 8, 16} with R <= N', a block of N' entries whose entry jj R + r is
+// W_{N'}^{jj r} (jj < N' / R, r < R).  The R twiddles of one butterfly are adjacent, so a thread
+// fetches them with a few wide loads from one address.  The values equal table entries
+// W_Lt^{jj r Lt / N'}.
+__host__ __device__ constexpr int64_t stage_tw_offset(int64_t Np, int R)
+{
+    int64_t off = 0;
+    for (int64_t n = 2; n < Np; n *= 2)
+        for (int r = 2; r <= 16 && r <= n; r *= 2) off += n;
+    for (int r = 2; r < R; r *= 2) off += Np;
+    return off;
+}
+// entries after the first Lt that the per-stage tables of every N' <= Lt need
+__host__ __device__ constexpr int64_t stage_tw_entries(int64_t Lt) { return stage_tw_offset(2 * Lt, 2); }
+
 // Model parameters in the kernel's precision.  fk[a] = 2 pi / (n_a dx_a): the wavenumber of index
 // m on axis a is fk[a] * m (m signed; x indices are 0..M).  Axis 0 is the last-axis pass's axis,
 // axis 1 the rows (3D y), axis 2 x.
