@@ -95,10 +95,15 @@ __device__ __noinline__ void batch_x_fwd(const BatchInst<T> *in, int item, const
     x_r2c_block<T, PL, BRows<PL>::value, true>(in->psi, in->scratch, in->n0, tw, lt_shift, item, batch_lds<T>());
 }
 
-template <typename T, class PL>
+// Lengths whose single-plan step uses a spread tile (PencilTile) use the same tile here, so that
+// each instance computes exactly what its own plan computes.
+template <typename T, class PL0>
 __device__ __noinline__ void batch_y_step(const BatchInst<T> *in, int item, const cx<T> *tw, int lt_shift)
 {
+    using TL = PencilTile<T, PL0::L>;
+    using PL = SpreadIf<PL0, TL::E>;
     constexpr int WM = kBatchThreads / PL::Tp;
+    static_assert(TL::G == 1 || WM == TL::W, "spread tile must fill the batched workgroup");
     LastAxisArgs<T> la;
     la.src = in->scratch;
     la.dst = in->scratch;
@@ -111,7 +116,7 @@ __device__ __noinline__ void batch_y_step(const BatchInst<T> *in, int item, cons
     la.tw = tw;
     la.lt_shift = lt_shift;
     la.mp = in->mp;
-    last_axis_block<T, PL, WM, LA_STEP>(la, item, batch_lds<T>());
+    last_axis_block<T, PL, WM, LA_STEP, TL::PF, ORD_TILE, false, TL::G>(la, item, batch_lds<T>());
 }
 
 template <typename T, class PL>

@@ -28,7 +28,7 @@ hipError_t batch_blocks_per_cu(int *blocks)
 template hipError_t launch_batch<float>(const BatchArgs<float> &, int, hipStream_t);
 template hipError_t batch_blocks_per_cu<float>(int *);
 
-bool batch_tiles(int n0, int M, int vx, int vy, int vc, int *x_rows, int *c_rows, int *y_pencils)
+bool batch_tiles(int n0, int M, int vx, int vy, int vc, bool f64, int *x_rows, int *c_rows, int *y_pencils)
 {
     if (vx < 0 || vy < 0 || vc < 0 || vx >= batch_candidates(n0, M, 0) || vy >= batch_candidates(n0, M, 1) ||
         vc >= batch_candidates(n0, M, 2))
@@ -50,7 +50,12 @@ bool batch_tiles(int n0, int M, int vx, int vy, int vc, int *x_rows, int *c_rows
         switch (l) {
 #define PFC_YCASE(LL)                                                                                   \
     case LL:                                                                                            \
-        with_plan<typename LastCands<LL>::type>(vy, [&](auto p) { *y_pencils = kBatchThreads / decltype(p)::Tp; return 0; }); \
+        with_plan<typename LastCands<LL>::type>(vy, [&](auto p) {                                         \
+            using P0 = decltype(p);                                                                     \
+            *y_pencils = f64 ? kBatchThreads / SpreadIf<P0, PencilTile<double, LL>::E>::Tp               \
+                             : kBatchThreads / SpreadIf<P0, PencilTile<float, LL>::E>::Tp;               \
+            return 0;                                                                                   \
+        });                                                                                             \
         break;
             PFC_YCASE(32) PFC_YCASE(64) PFC_YCASE(128) PFC_YCASE(256) PFC_YCASE(512) PFC_YCASE(1024)
 #undef PFC_YCASE

@@ -135,6 +135,17 @@ struct Radices {
                                        std::conditional_t<nst == 2, Radices<B, A>, Radices<C, B, A>>>;
 };
 
+// The schedule PL with E >= PL::Rmax elements per thread (E / R butterflies of each stage per
+// thread): Tp = L / E threads per pencil.  Fewer threads per pencil for long pencils, so that a
+// workgroup of several pencils stays within the register and LDS budget of two workgroups per CU.
+template <class PL, int E>
+struct Spread : PL {
+    static_assert(E % PL::Rmax == 0 && E <= PL::L, "E must be a multiple of the largest radix");
+    static constexpr int Rmax = E;
+    static constexpr int Tp = PL::L / E;
+    using Reverse = Spread<typename PL::Reverse, E>;
+};
+
 // Default schedule per length.
 template <int L> struct DefaultPlan;
 template <> struct DefaultPlan<2> { using type = Radices<2>; };
@@ -248,8 +259,11 @@ __device__ __forceinline__ void apply_twiddles(cx<T> *v, int jj, const cx<T> *__
 // `lds(e)` returns a reference to this pencil's LDS slot for element e.  Contains workgroup
 // barriers, so every thread of the workgroup must call it (idle threads included).  The first LDS
 // write is preceded by a barrier, so the caller may have used the same LDS just before.
-template <typename T, class PL, int DIR, int TWM = TW_STAGE, class Lds>
-__device__ __forceinline__ void fft_stages(cx<T> *v, int t, Lds &&lds, const cx<T> *__restrict__ tw, int lt_shift)
+// G > 1: the workgroup's pencils form G groups (this thread's is `grp`) that take turns in one
+// LDS area sized for a single group, so each exchange costs G barrier pairs and 1/G of the LDS.
+template <typename T, class PL, int DIR, int TWM = TW_STAGE, int G = 1, class Lds>
+__device__ __forceinline__ void fft_stages(cx<T> *v, int t, Lds &&lds, const cx<T> *__restrict__ tw, int lt_shift,
+                                           int grp = 0)
 {
     constexpr int L = PL::L;
     constexpr int Tp = PL::Tp;
@@ -258,27 +272,39 @@ __device__ __forceinline__ void fft_stages(cx<T> *v, int t, Lds &&lds, const cx<
         constexpr int R = PL::radix(s);
         constexpr int B = PL::Rmax / R;
         constexpr int Ns = PL::prefix(s);
-        if constexpr (s > 0) {
-#pragma unroll
-            for (int b = 0; b < B; ++b) {
-                const int j = t + b * Tp;
-#pragma unroll
-                for (int r = 0; r < R; ++r) v[b * R + r] = lds(j + r * (L / R));
-                apply_twiddles<T, R, Ns, DIR, TWM>(&v[b * R], j & (Ns - 1), tw, lt_shift);
-            }
-        }
 #pragma unroll
         for (int b = 0; b < B; ++b) dft<T, R, DIR>(&v[b * R]);
         if constexpr (s + 1 < PL::nst) {
-            __syncthreads();
+            // exchange, then the next stage's inputs and twiddles
+            constexpr int R2 = PL::radix(s + 1);
+            constexpr int B2 = PL::Rmax / R2;
+            constexpr int Ns2 = PL::prefix(s + 1);
 #pragma unroll
-            for (int b = 0; b < B; ++b) {
-                const int j = t + b * Tp;
-                const int base = (j / Ns) * Ns * R + (j & (Ns - 1));
+            for (int gg = 0; gg < G; ++gg) {
+                const bool mine = (G == 1) || (grp == gg);
+                __syncthreads();
+                if (mine) {
 #pragma unroll
-                for (int r = 0; r < R; ++r) lds(base + r * Ns) = v[b * R + r];
+                    for (int b = 0; b < B; ++b) {
+                        const int j = t + b * Tp;
+                        const int base = (j / Ns) * Ns * R + (j & (Ns - 1));
+#pragma unroll
+                        for (int r = 0; r < R; ++r) lds(base + r * Ns) = v[b * R + r];
+                    }
+                }
+                __syncthreads();
+                if (mine) {
+#pragma unroll
+                    for (int b = 0; b < B2; ++b) {
+                        const int j = t + b * Tp;
+#pragma unroll
+                        for (int r = 0; r < R2; ++r) v[b * R2 + r] = lds(j + r * (L / R2));
+                    }
+                }
             }
-            __syncthreads();
+#pragma unroll
+            for (int b = 0; b < B2; ++b)
+                apply_twiddles<T, R2, Ns2, DIR, TWM>(&v[b * R2], (t + b * Tp) & (Ns2 - 1), tw, lt_shift);
         }
     });
 }

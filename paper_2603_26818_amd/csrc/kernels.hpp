@@ -300,6 +300,41 @@ __global__ __launch_bounds__(ROWS *PL::Tp) void x_c2r_kernel(const cx<T> *in, T 
 }
 
 // ------------------------------------------------------------------------------------------------
+// Pencils per workgroup of the strided passes: 128-byte rows (16 FP32 / 8 FP64 complex) as long as
+// the workgroup's LDS tile stays within 128 KB.
+template <typename T, int L>
+struct WMax {
+    static constexpr int pref = 128 / (int)sizeof(cx<T>);
+    static constexpr int cap = (131072 / (L * (int)sizeof(cx<T>))) < 2 ? 2 : (131072 / (L * (int)sizeof(cx<T>)));
+    static constexpr int value = pref < cap ? pref : cap;
+};
+
+// Tile of the strided passes (y, and the last-axis step) per length: W pencils per workgroup,
+// E elements per thread (0: the schedule's largest radix), G LDS groups (fft_stages), state
+// prefetch in the step.  Default: WMax pencils, one LDS area.  Long FP32 pencils, measured on
+// MI355X: at 1024, 16 pencils with 32 elements per thread and two LDS groups (512 threads, 64 KB:
+// two workgroups per CU); at 2048 the same with 1024 threads and 128 KB, which keeps the column
+// tile a whole 128-byte line (the default 8 pencils leave 64-byte tiles: y 19.1 -> 15.9 ms and
+// z 63 -> 50 ms at 2048^3).
+template <typename T, int L>
+struct PencilTile {
+    static constexpr int W = WMax<T, L>::value, E = 0, G = 1;
+    static constexpr bool PF = true;
+};
+template <>
+struct PencilTile<float, 1024> {
+    static constexpr int W = 16, E = 32, G = 2;
+    static constexpr bool PF = false;
+};
+template <>
+struct PencilTile<float, 2048> {
+    static constexpr int W = 16, E = 32, G = 2;  // whole 128-byte lines; 1024 threads, 128 KB
+    static constexpr bool PF = false;
+};
+template <class PL, int E>
+using SpreadIf = std::conditional_t<(E > 0), Spread<PL, (E > 0 ? E : PL::Rmax)>, PL>;
+
+// ------------------------------------------------------------------------------------------------
 // Workgroup order for column tiles narrower than a 128-byte line.  Consecutive workgroups are
 // dispatched to the 8 XCDs in turn, so workgroups b, b + 8, ..., b + 8 (G - 1) share one XCD and
 // its L2; they are given G adjacent tiles, which then share every line in that L2 instead of
@@ -320,7 +355,7 @@ __device__ __forceinline__ int64_t xcd_tile_order(int64_t b, int64_t n, int G)
 // A workgroup handles W adjacent columns (W <= WMAX); its threads are laid out column-fastest so
 // each load/store instruction moves W * sizeof(cx) contiguous bytes per element row.  `bid` is the
 // logical tile index (see xcd_tile_order).
-template <typename T, class PL, int WMAX, int DIR, bool NT = false>
+template <typename T, class PL, int WMAX, int DIR, bool NT = false, int G = 1>
 __device__ __forceinline__ void axis_c2c_block(const cx<T> *src, cx<T> *dst, int W, int64_t ncols, int64_t estride,
                                                int64_t bstride, int64_t tiles_per_batch,
                                                const cx<T> *__restrict__ tw, int lt_shift, int64_t bid, cx<T> *sh)
@@ -338,8 +373,9 @@ __device__ __forceinline__ void axis_c2c_block(const cx<T> *src, cx<T> *dst, int
         for (int r = 0; r < R0; ++r)
             v[b * R0 + r] = valid ? ld_grid<NT>(&src[base + (int64_t)(t + b * Tp + r * (L / R0)) * estride])
                                   : cx<T>{T(0), T(0)};
-    auto lds = [&](int e) -> cx<T> & { return sh[e * WMAX + p]; };
-    fft_stages<T, PL, DIR>(v, t, lds, tw, lt_shift);
+    constexpr int GW = WMAX / G;  // pencils per LDS group (see fft_stages)
+    auto lds = [&](int e) -> cx<T> & { return sh[e * GW + p % GW]; };
+    fft_stages<T, PL, DIR, TW_STAGE, G>(v, t, lds, tw, lt_shift, p / GW);
     if (valid) {
 #pragma unroll
         for (int b = 0; b < Rmax / Rl; ++b)
@@ -349,14 +385,15 @@ __device__ __forceinline__ void axis_c2c_block(const cx<T> *src, cx<T> *dst, int
     }
 }
 
-template <typename T, class PL, int WMAX, int DIR, int OCC = 1, bool NT = false>
+template <typename T, class PL, int WMAX, int DIR, int OCC = 1, bool NT = false, int G = 1>
 __global__ __launch_bounds__(WMAX *PL::Tp, OCC) void axis_c2c_kernel(const cx<T> *src, cx<T> *dst, int W,
                                                                  int64_t ncols, int64_t estride, int64_t bstride,
                                                                  int64_t tiles_per_batch,
                                                                  const cx<T> *__restrict__ tw, int lt_shift, int xg)
 {
-    __shared__ cx<T> sh[PL::L * WMAX];
-    axis_c2c_block<T, PL, WMAX, DIR, NT>(src, dst, W, ncols, estride, bstride, tiles_per_batch, tw, lt_shift,
+    static_assert(WMAX % G == 0, "groups of whole pencils");
+    __shared__ cx<T> sh[PL::L * WMAX / G];
+    axis_c2c_block<T, PL, WMAX, DIR, NT, G>(src, dst, W, ncols, estride, bstride, tiles_per_batch, tw, lt_shift,
                                          xcd_tile_order(blockIdx.x, gridDim.x, xg), sh);
 }
 
@@ -393,10 +430,19 @@ struct SlotInfo {
     bool has_pairs;
 };
 
-// ROWFAST: consecutive workgroups take consecutive rows of the same column tile (measured slightly
-// slower at 512^3 than the default, where consecutive workgroups take adjacent column tiles of one
-// row).
-template <bool ROWFAST = false>
+// Order of the workgroups over the column tiles (3D):
+//   ORD_TILE: consecutive workgroups take adjacent column tiles of one row (default);
+//   ORD_ROW: consecutive workgroups take consecutive rows of one column tile (measured slightly
+//            slower at 512^3);
+//   ORD_XCD_ROW: workgroup b runs on XCD b mod 8 (round-robin dispatch); each XCD takes whole rows
+//            (rows r with r mod 8 = its XCD, tiles in order), so that tiles whose rows are not
+//            line-aligned (natural half spectrum, pitch M + 1) share their boundary lines in one
+//            L2.  Needs nrows % 8 == 0, else ORD_TILE.
+// IL: in the pair tiles, slots alternate between the two rows (slot p and its mirror p ^ 1 hold the
+// same column), so that a pencil and its mirror stay in one group of adjacent slots; otherwise the
+// first W/2 slots hold row k_y and the others row -k_y.
+enum { ORD_TILE = 0, ORD_ROW = 1, ORD_XCD_ROW = 2 };
+template <int ORD = ORD_TILE, bool IL = false>
 __device__ __forceinline__ SlotInfo la_slot(int64_t nrows, int TR, int W, int p, int64_t bid)
 {
     SlotInfo s;
@@ -409,9 +455,13 @@ __device__ __forceinline__ SlotInfo la_slot(int64_t nrows, int TR, int W, int p,
     }
     const int64_t n_normal = nrows * (TR - 1);
     if (bid < n_normal) {
-        if constexpr (ROWFAST) {
+        if (ORD == ORD_ROW) {
             s.row = bid % nrows;
             s.kx = (int)(1 + bid / nrows) * W + p;
+        } else if (ORD == ORD_XCD_ROW && (nrows & 7) == 0) {
+            const int64_t k = bid >> 3;
+            s.row = (k / (TR - 1)) * 8 + (bid & 7);
+            s.kx = (int)(1 + k % (TR - 1)) * W + p;
         } else {
             s.row = bid / (TR - 1);
             s.kx = (int)(1 + bid % (TR - 1)) * W + p;
@@ -423,27 +473,39 @@ __device__ __forceinline__ SlotInfo la_slot(int64_t nrows, int TR, int W, int p,
     const int64_t k = bid - n_normal, i = k >> 1;
     const int h = (int)(k & 1), hw = W >> 1;
     const int64_t ra = (i == 0) ? 0 : i, rb = (i == 0) ? nrows / 2 : nrows - i;
-    const bool first = p < hw;
-    s.row = first ? ra : rb;
-    s.kx = h * hw + (first ? p : p - hw);
-    s.partner = (s.kx == 0) ? ((i == 0) ? p : (first ? p + hw : p - hw)) : -1;
+    if constexpr (IL) {
+        const bool first = (p & 1) == 0;
+        s.row = first ? ra : rb;
+        s.kx = h * hw + (p >> 1);
+        s.partner = (s.kx == 0) ? ((i == 0) ? p : (p ^ 1)) : -1;
+    } else {
+        const bool first = p < hw;
+        s.row = first ? ra : rb;
+        s.kx = h * hw + (first ? p : p - hw);
+        s.partner = (s.kx == 0) ? ((i == 0) ? p : (first ? p + hw : p - hw)) : -1;
+    }
     s.has_pairs = (h == 0);
     return s;
 }
 
-template <typename T, class PL, int WMAX, int MODE, bool PF = true, bool ROWFAST = false, bool NT = false>
+// G > 1 (STEP only): the pencils form G groups of WMAX / G adjacent slots that take turns in an LDS
+// area of L * WMAX / G values (see fft_stages); pair tiles then interleave their two rows.
+template <typename T, class PL, int WMAX, int MODE, bool PF = true, int ORD = ORD_TILE, bool NT = false, int G = 1>
 __device__ __forceinline__ void last_axis_block(const LastAxisArgs<T> &a, int64_t bid, cx<T> *sh)
 {
-    constexpr int L = PL::L, Tp = PL::Tp, Rmax = PL::Rmax;
+    static_assert(G == 1 || MODE == LA_STEP, "grouped LDS only in the step");
+    static_assert(WMAX % G == 0 && (G == 1 || (WMAX / G) % 2 == 0), "groups must hold whole pairs");
+    constexpr int L = PL::L, Tp = PL::Tp, Rmax = PL::Rmax, GW = WMAX / G;
+    constexpr bool IL = G > 1;
     using PR = typename PL::Reverse;  // inverse schedule: its first radix is PL's last
     constexpr int Rl = PL::last;
-    const int tid = threadIdx.x, p = tid % WMAX, t = tid / WMAX;
+    const int tid = threadIdx.x, p = tid % WMAX, t = tid / WMAX, grp = p / GW;
     const int W = a.W;
     const int64_t nrows = a.nrows, M = a.M, estride = nrows * M;
-    const SlotInfo si = la_slot<ROWFAST>(nrows, a.tiles_per_row, W, p < W ? p : 0, bid);
+    const SlotInfo si = la_slot<ORD, IL>(nrows, a.tiles_per_row, W, p < W ? p : 0, bid);
     const bool valid = p < W;
     const int64_t coloff = si.row * M + si.kx;
-    auto lds = [&](int e) -> cx<T> & { return sh[e * WMAX + p]; };
+    auto lds = [&](int e) -> cx<T> & { return sh[e * GW + p % GW]; };
     const ModelParams<T> &mp = a.mp;
     const T ky = mp.fk[1] * (T)signed_index(si.row, nrows);
     const T kx = mp.fk[2] * (T)si.kx;
@@ -454,7 +516,7 @@ __device__ __forceinline__ void last_axis_block(const LastAxisArgs<T> &a, int64_
         // natural half spectrum in: fold kx = 0 and kx = M (projected) into one plane, inverse FFT
         constexpr int R0 = PR::first;
         const int64_t prow =
-            (si.partner >= 0) ? la_slot<ROWFAST>(nrows, a.tiles_per_row, W, si.partner, bid).row : 0;
+            (si.partner >= 0) ? la_slot<ORD>(nrows, a.tiles_per_row, W, si.partner, bid).row : 0;
         const int64_t pitch = M + 1;
 #pragma unroll
         for (int b = 0; b < Rmax / R0; ++b)
@@ -494,7 +556,7 @@ __device__ __forceinline__ void last_axis_block(const LastAxisArgs<T> &a, int64_
         // scalar registers) and a per-lane 32-bit byte offset (t below the wave's first t by less
         // than 64 / WMAX, row and column inside the tile), so no per-element 64-bit vector
         // arithmetic is needed.
-        const SlotInfo s0 = la_slot<ROWFAST>(nrows, a.tiles_per_row, W, 0, bid);
+        const SlotInfo s0 = la_slot<ORD, IL>(nrows, a.tiles_per_row, W, 0, bid);
         const int t0 = __builtin_amdgcn_readfirstlane(t);
         const int64_t uoff = (int64_t)t0 * estride + s0.row * M + s0.kx;
         const uint32_t loff =
@@ -520,18 +582,23 @@ __device__ __forceinline__ void last_axis_block(const LastAxisArgs<T> &a, int64_
 #pragma unroll
             for (int r = 0; r < R0; ++r)
                 v[b * R0 + r] = valid ? ld_grid<NT>(gp(a.src, b * Tp + r * (L / R0))) : cx<T>{T(0), T(0)};
-        fft_stages<T, PL, -1>(v, t, lds, a.tw, a.lt_shift);
+        fft_stages<T, PL, -1, TW_STAGE, G>(v, t, lds, a.tw, a.lt_shift, grp);
         // forward spectrum in natural order: v[b*Rl + r] = X(e), e = t + b*Tp + r*L/Rl
-        if (si.has_pairs) {  // uniform per workgroup
-            __syncthreads();
+        auto partner_val = [&](int e) -> cx<T> { return sh[((L - e) & (L - 1)) * GW + si.partner % GW]; };
+        auto spectrum_to_lds = [&]() {
 #pragma unroll
             for (int b = 0; b < Rmax / Rl; ++b)
 #pragma unroll
                 for (int r = 0; r < Rl; ++r) lds(t + b * Tp + r * (L / Rl)) = v[b * Rl + r];
-            __syncthreads();
-        }
-        auto partner_val = [&](int e) -> cx<T> { return sh[((L - e) & (L - 1)) * WMAX + si.partner]; };
+        };
 
+        if constexpr (MODE == LA_R2C_NATURAL || MODE == LA_ADJOINT) {
+            if (si.has_pairs) {  // uniform per workgroup
+                __syncthreads();
+                spectrum_to_lds();
+                __syncthreads();
+            }
+        }
         if constexpr (MODE == LA_R2C_NATURAL) {
             const int64_t pitch = M + 1;
             if (valid) {
@@ -559,14 +626,40 @@ __device__ __forceinline__ void last_axis_block(const LastAxisArgs<T> &a, int64_
             // which another thread owns; the mirror's N comes from LDS now, its S in a second LDS
             // round, so no thread reads a state value that another thread has already updated.
             const T dt = mp.dt, nl = mp.nl, h = T(0.5);
+            if (si.has_pairs) {  // uniform per workgroup
 #pragma unroll
-            for (int b = 0; b < Rmax / Rl; ++b)
+                for (int gg = 0; gg < G; ++gg) {
+                    const bool mine = (G == 1) || (grp == gg);
+                    __syncthreads();
+                    if (mine) spectrum_to_lds();
+                    __syncthreads();
+                    if (mine && si.partner >= 0) {
 #pragma unroll
-                for (int r = 0; r < Rl; ++r) {
-                    const int e = t + b * Tp + r * (L / Rl);
-                    const T kz = mp.fk[0] * (T)signed_index(e, L);
-                    const cx<T> N = {v[b * Rl + r].x * nl, v[b * Rl + r].y * nl};
-                    if (si.partner < 0) {
+                        for (int b = 0; b < Rmax / Rl; ++b)
+#pragma unroll
+                            for (int r = 0; r < Rl; ++r) {
+                                const int e = t + b * Tp + r * (L / Rl);
+                                const T kz = mp.fk[0] * (T)signed_index(e, L);
+                                const cx<T> N = {v[b * Rl + r].x * nl, v[b * Rl + r].y * nl};
+                                const cx<T> Np = {partner_val(e).x * nl, partner_val(e).y * nl};
+                                const cx<T> N0 = {(N.x + Np.x) * h, (N.y - Np.y) * h};
+                                const cx<T> NN = {(N.y + Np.y) * h, (Np.x - N.x) * h};
+                                const T q0 = kz * kz + ky * ky, qn = q0 + kxn * kxn;
+                                const T g0 = dt * q0 * amult(mp, q0), gn = dt * qn * amult(mp, qn);
+                                // G = -(g0 N0 + i gn NN): the cubic term's share of the new value
+                                v[b * Rl + r] = {-g0 * N0.x + gn * NN.y, -g0 * N0.y - gn * NN.x};
+                            }
+                    }
+                }
+            }
+            if (si.partner < 0) {
+#pragma unroll
+                for (int b = 0; b < Rmax / Rl; ++b)
+#pragma unroll
+                    for (int r = 0; r < Rl; ++r) {
+                        const int e = t + b * Tp + r * (L / Rl);
+                        const T kz = mp.fk[0] * (T)signed_index(e, L);
+                        const cx<T> N = {v[b * Rl + r].x * nl, v[b * Rl + r].y * nl};
                         cx<T> *gi = gp(a.state, b * Tp + r * (L / Rl));
                         cx<T> S;
                         if constexpr (PF)
@@ -578,58 +671,54 @@ __device__ __forceinline__ void last_axis_block(const LastAxisArgs<T> &a, int64_
                         const cx<T> Snew = {(S.x - dq * N.x) * A, (S.y - dq * N.y) * A};
                         if (valid) st_grid<NT>(gi, Snew);
                         v[b * Rl + r] = Snew;
-                    } else {
-                        const cx<T> Np = {partner_val(e).x * nl, partner_val(e).y * nl};
-                        const cx<T> N0 = {(N.x + Np.x) * h, (N.y - Np.y) * h};
-                        const cx<T> NN = {(N.y + Np.y) * h, (Np.x - N.x) * h};
-                        const T q0 = kz * kz + ky * ky, qn = q0 + kxn * kxn;
-                        const T g0 = dt * q0 * amult(mp, q0), gn = dt * qn * amult(mp, qn);
-                        // G = -(g0 N0 + i gn NN): the cubic term's share of the new value
-                        v[b * Rl + r] = {-g0 * N0.x + gn * NN.y, -g0 * N0.y - gn * NN.x};
                     }
-                }
+            }
             if (si.has_pairs) {  // uniform per workgroup
-                __syncthreads();  // every mirror N has been read
 #pragma unroll
-                for (int b = 0; b < Rmax / Rl; ++b)
+                for (int gg = 0; gg < G; ++gg) {
+                    const bool mine = (G == 1) || (grp == gg);
+                    __syncthreads();  // every mirror N has been read
+                    if (mine && si.partner >= 0 && valid) {
 #pragma unroll
-                    for (int r = 0; r < Rl; ++r) {
-                        const int e = t + b * Tp + r * (L / Rl);
-                        if (si.partner >= 0 && valid) {
-                            if constexpr (PF)
-                                lds(e) = spre[b * Rl + r];
-                            else
-                                lds(e) = ld_grid<NT>(gp(a.state, b * Tp + r * (L / Rl)));
-                        }
+                        for (int b = 0; b < Rmax / Rl; ++b)
+#pragma unroll
+                            for (int r = 0; r < Rl; ++r) {
+                                const int e = t + b * Tp + r * (L / Rl);
+                                if constexpr (PF)
+                                    lds(e) = spre[b * Rl + r];
+                                else
+                                    lds(e) = ld_grid<NT>(gp(a.state, b * Tp + r * (L / Rl)));
+                            }
                     }
-                __syncthreads();
-                if (si.partner >= 0) {
+                    __syncthreads();
+                    if (mine && si.partner >= 0) {
 #pragma unroll
-                    for (int b = 0; b < Rmax / Rl; ++b)
+                        for (int b = 0; b < Rmax / Rl; ++b)
 #pragma unroll
-                        for (int r = 0; r < Rl; ++r) {
-                            const int e = t + b * Tp + r * (L / Rl);
-                            const T kz = mp.fk[0] * (T)signed_index(e, L);
-                            cx<T> *gi = gp(a.state, b * Tp + r * (L / Rl));
-                            cx<T> S;
-                            if constexpr (PF)
-                                S = spre[b * Rl + r];
-                            else
-                                S = valid ? ld_grid<NT>(gi) : cx<T>{T(0), T(0)};
-                            const cx<T> Sp = partner_val(e);
-                            const cx<T> S0 = {(S.x + Sp.x) * h, (S.y - Sp.y) * h};
-                            const cx<T> SN = {(S.y + Sp.y) * h, (Sp.x - S.x) * h};
-                            const T q0 = kz * kz + ky * ky, qn = q0 + kxn * kxn;
-                            const T A0 = amult(mp, q0), AN = amult(mp, qn);
-                            const cx<T> G = v[b * Rl + r];
-                            // A0 S0 + i AN SN + G
-                            const cx<T> Snew = {A0 * S0.x - AN * SN.y + G.x, A0 * S0.y + AN * SN.x + G.y};
-                            if (valid) st_grid<NT>(gi, Snew);
-                            v[b * Rl + r] = Snew;
-                        }
+                            for (int r = 0; r < Rl; ++r) {
+                                const int e = t + b * Tp + r * (L / Rl);
+                                const T kz = mp.fk[0] * (T)signed_index(e, L);
+                                cx<T> *gi = gp(a.state, b * Tp + r * (L / Rl));
+                                cx<T> S;
+                                if constexpr (PF)
+                                    S = spre[b * Rl + r];
+                                else
+                                    S = valid ? ld_grid<NT>(gi) : cx<T>{T(0), T(0)};
+                                const cx<T> Sp = partner_val(e);
+                                const cx<T> S0 = {(S.x + Sp.x) * h, (S.y - Sp.y) * h};
+                                const cx<T> SN = {(S.y + Sp.y) * h, (Sp.x - S.x) * h};
+                                const T q0 = kz * kz + ky * ky, qn = q0 + kxn * kxn;
+                                const T A0 = amult(mp, q0), AN = amult(mp, qn);
+                                const cx<T> Gt = v[b * Rl + r];
+                                // A0 S0 + i AN SN + G
+                                const cx<T> Snew = {A0 * S0.x - AN * SN.y + Gt.x, A0 * S0.y + AN * SN.x + Gt.y};
+                                if (valid) st_grid<NT>(gi, Snew);
+                                v[b * Rl + r] = Snew;
+                            }
+                    }
                 }
             }
-            fft_stages<T, PR, +1>(v, t, lds, a.tw, a.lt_shift);
+            fft_stages<T, PR, +1, TW_STAGE, G>(v, t, lds, a.tw, a.lt_shift, grp);
             if (valid) {
                 constexpr int Rf = PR::last;
 #pragma unroll
@@ -687,11 +776,12 @@ __device__ __forceinline__ void last_axis_block(const LastAxisArgs<T> &a, int64_
     }
 }
 
-template <typename T, class PL, int WMAX, int MODE, int OCC = 1, bool PF = true, bool ROWFAST = false, bool NT = false>
+template <typename T, class PL, int WMAX, int MODE, int OCC = 1, bool PF = true, int ORD = ORD_TILE, bool NT = false,
+          int G = 1>
 __global__ __launch_bounds__(WMAX *PL::Tp, OCC) void last_axis_kernel(LastAxisArgs<T> a)
 {
-    __shared__ cx<T> sh[PL::L * WMAX];
-    last_axis_block<T, PL, WMAX, MODE, PF, ROWFAST, NT>(a, blockIdx.x, sh);
+    __shared__ cx<T> sh[PL::L * WMAX / G];
+    last_axis_block<T, PL, WMAX, MODE, PF, ORD, NT, G>(a, blockIdx.x, sh);
 }
 
 // ------------------------------------------------------------------------------------------------

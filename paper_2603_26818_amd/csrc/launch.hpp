@@ -72,8 +72,9 @@ hipError_t batch_blocks_per_cu(int *blocks);
 constexpr int kBatchThreadsHost = 512;
 constexpr int kBatchMaxInstHost = 256;
 // rows per x-forward / x-inverse item and pencils per y item of the batched kernel for an n0 x 2M
-// instance with candidate schedules (vx, vy, vc) (returns false for unsupported lengths/candidates)
-bool batch_tiles(int n0, int M, int vx, int vy, int vc, int *x_rows, int *c_rows, int *y_pencils);
+// instance of dtype FP64 (f64) or FP32 with candidate schedules (vx, vy, vc) (returns false for
+// unsupported lengths/candidates)
+bool batch_tiles(int n0, int M, int vx, int vy, int vc, bool f64, int *x_rows, int *c_rows, int *y_pencils);
 // number of candidates of batched pass `pass` (0 x forward, 1 y, 2 x inverse) for an n0 x 2M instance
 int batch_candidates(int n0, int M, int pass);
 

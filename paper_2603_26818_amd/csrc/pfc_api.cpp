@@ -518,7 +518,7 @@ pfc_status batch_layout(pfc_batch *b)
     for (int i = 0; i < b->count; ++i) {
         pfc_batch::Inst &g = b->inst[i];
         int wm = 0;
-        if (!pfc::batch_tiles(g.n0, g.M, g.vx, g.vy, g.vc, &g.x_rows, &g.c_rows, &wm))
+        if (!pfc::batch_tiles(g.n0, g.M, g.vx, g.vy, g.vc, b->dtype == PFC_F64, &g.x_rows, &g.c_rows, &wm))
             return fail(PFC_ERR_UNSUPPORTED, "instance %d: no batched schedule for %d x %d (candidates %d %d %d)", i,
                         g.n0, g.nx, g.vx, g.vy, g.vc);
         g.W = std::min(wm, g.M);
