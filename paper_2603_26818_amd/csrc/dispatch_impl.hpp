@@ -219,10 +219,24 @@ hipError_t launch_last(const Geom &g, int mode, const cx<T> *src, cx<T> *dst, cx
                 });
             // natural layout (rows of M + 1, not line-aligned): whole rows per XCD, so the lines two
             // tiles share meet in one L2 (measured at 512^3: r2c 403 -> 348 us, c2r 274 -> 262 us)
-            case LAST_R2C_NATURAL:
+            case LAST_R2C_NATURAL: {
+                // line-aligned chunks where the geometry allows (3D; measured 348 -> see DESIGN), else
+                // column tiles in whole rows per XCD
+                using TL = PencilTile<T, L>;
+                constexpr int C = 128 / (int)sizeof(cx<T>);
+                if constexpr (TL::W == C) {
+                    if (g.nrows > 1 && (g.nrows * (g.M + 1)) % C == 0 && g.M >= C) {
+                        using PL = SpreadIf<P0, TL::E>;
+                        const int64_t nchunks = g.nrows * (g.M + 1) / C;
+                        hipLaunchKernelGGL((r2c_natural_chunk_kernel<T, PL, C, TL::G>), dim3((unsigned)nchunks),
+                                           dim3(C * PL::Tp), 0, s, src, dst, g.nrows, (int)g.M, tw, g.lt_shift);
+                        break;
+                    }
+                }
                 hipLaunchKernelGGL((last_axis_kernel<T, P0, WM, LA_R2C_NATURAL, 1, true, ORD_XCD_ROW>), grid,
                                    dim3(WM * P0::Tp), 0, s, a);
                 break;
+            }
             case LAST_C2R_NATURAL:
                 hipLaunchKernelGGL((last_axis_kernel<T, P0, WM, LA_C2R_NATURAL, 1, true, ORD_XCD_ROW>), grid,
                                    dim3(WM * P0::Tp), 0, s, a);

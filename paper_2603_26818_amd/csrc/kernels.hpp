@@ -785,6 +785,91 @@ __global__ __launch_bounds__(WMAX *PL::Tp, OCC) void last_axis_kernel(LastAxisAr
 }
 
 // ------------------------------------------------------------------------------------------------
+// Last axis of the 3D r2c into the natural half spectrum (rows of M + 1 values), by line-aligned
+// chunks.  The output plane (nrows rows of M + 1) is cut into chunks of C = 128 / sizeof(cx)
+// consecutive values; workgroup c owns output positions f = cC .. cC + C - 1 of every plane, i.e.
+// one whole 128-byte line per plane (requires nrows (M + 1) % C == 0 and M >= C), so no line is
+// written by two workgroups.  Slot p computes the pencil of position f: row f / (M + 1), column
+// kx = f % (M + 1).  For 1 <= kx < M that is packed column kx; kx = 0 and kx = M are the two planes
+// folded into packed column 0, separated with the mirror pencil (row -k_y, element -k_z), which a
+// second round transforms: X0 = (Z(k) + conj Z(-k)) / 2, XM = -i (Z(k) - conj Z(-k)) / 2.  A chunk
+// holds at most two such slots; the second round runs only in chunks that have one.  The reads of
+// packed columns are not line-aligned; chunks that share input lines run on one XCD.
+template <typename T, class PL, int C, int G>
+__global__ __launch_bounds__(C *PL::Tp) void r2c_natural_chunk_kernel(const cx<T> *__restrict__ src,
+                                                                      cx<T> *__restrict__ dst, int64_t nrows, int M,
+                                                                      const cx<T> *__restrict__ tw, int lt_shift)
+{
+    constexpr int L = PL::L, Tp = PL::Tp, Rmax = PL::Rmax, R0 = PL::first, Rl = PL::last, GW = C / G;
+    __shared__ cx<T> sh[L * GW];
+    const int tid = threadIdx.x, p = tid % C, t = tid / C, grp = p / GW;
+    auto lds = [&](int e) -> cx<T> & { return sh[e * GW + p % GW]; };
+    const int64_t pitch = (int64_t)M + 1, plane = nrows * pitch, nchunks = plane / C;
+    const int64_t chunk = xcd_tile_order(blockIdx.x, nchunks, 16);
+    const int64_t f = chunk * C + p;
+    const int64_t row = f / pitch;
+    const int kx = (int)(f - row * pitch);
+    const bool fold = (kx == 0 || kx == M);
+    const int64_t estride = nrows * M;
+    cx<T> v[Rmax];
+    // round 1: own pencil (folded slots: packed column 0 of this row)
+    {
+        const cx<T> *col = src + row * M + (fold ? 0 : kx);
+#pragma unroll
+        for (int b = 0; b < Rmax / R0; ++b)
+#pragma unroll
+            for (int r = 0; r < R0; ++r) v[b * R0 + r] = col[(int64_t)(t + b * Tp + r * (L / R0)) * estride];
+    }
+    fft_stages<T, PL, -1, TW_STAGE, G>(v, t, lds, tw, lt_shift, grp);
+    if (!fold) {
+#pragma unroll
+        for (int b = 0; b < Rmax / Rl; ++b)
+#pragma unroll
+            for (int r = 0; r < Rl; ++r) dst[(int64_t)(t + b * Tp + r * (L / Rl)) * plane + f] = v[b * Rl + r];
+    }
+    if (!__syncthreads_or(fold)) return;  // uniform: the chunk has no folded slot
+    // round 2: mirror pencils of the folded slots
+    cx<T> z[Rmax];
+#pragma unroll
+    for (int i = 0; i < Rmax; ++i) z[i] = v[i];
+    {
+        const int64_t mrow = (nrows - row) % nrows;
+        const cx<T> *col = src + mrow * M;
+#pragma unroll
+        for (int b = 0; b < Rmax / R0; ++b)
+#pragma unroll
+            for (int r = 0; r < R0; ++r)
+                v[b * R0 + r] = fold ? col[(int64_t)(t + b * Tp + r * (L / R0)) * estride] : cx<T>{T(0), T(0)};
+    }
+    fft_stages<T, PL, -1, TW_STAGE, G>(v, t, lds, tw, lt_shift, grp);
+    const T h = T(0.5);
+#pragma unroll
+    for (int gg = 0; gg < G; ++gg) {
+        const bool mine = (G == 1) || (grp == gg);
+        __syncthreads();
+        if (mine) {
+#pragma unroll
+            for (int b = 0; b < Rmax / Rl; ++b)
+#pragma unroll
+                for (int r = 0; r < Rl; ++r) lds(t + b * Tp + r * (L / Rl)) = v[b * Rl + r];
+        }
+        __syncthreads();
+        if (mine && fold) {
+#pragma unroll
+            for (int b = 0; b < Rmax / Rl; ++b)
+#pragma unroll
+                for (int r = 0; r < Rl; ++r) {
+                    const int e = t + b * Tp + r * (L / Rl);
+                    const cx<T> a = z[b * Rl + r], m = lds((L - e) & (L - 1));
+                    const cx<T> out = (kx == 0) ? cx<T>{(a.x + m.x) * h, (a.y - m.y) * h}
+                                                : cx<T>{(a.y + m.y) * h, (m.x - a.x) * h};
+                    dst[(int64_t)e * plane + f] = out;
+                }
+        }
+    }
+}
+
+// ------------------------------------------------------------------------------------------------
 // Reductions (FP64 accumulation, fixed grid and order: deterministic).
 
 // partial[block] = sum of x over a grid-stride range.

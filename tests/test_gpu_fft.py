@@ -12,7 +12,7 @@ from gpu_common import TOL_FFT, relerr, rounded, say, to_dev, to_np
 pytestmark = pytest.mark.gpu
 
 SHAPES = [(4, 4), (8, 8), (16, 64), (64, 16), (128, 128), (256, 32), (4, 4, 4), (8, 8, 8), (16, 8, 32), (4, 16, 8),
-          (32, 32, 32), (64, 64, 64), (128, 64, 32), (32, 256, 16)]
+          (32, 32, 32), (64, 64, 64), (128, 64, 32), (32, 256, 16), (1024, 32, 32), (2048, 16, 32)]
 
 
 @pytest.fixture(scope="module")
