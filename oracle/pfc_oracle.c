@@ -8,8 +8,9 @@
  * phase-field crystal simulations"):
  *   - the discrete Fourier transform used by the Fourier pseudo-spectral method (section "Fourier
  *     pseudo-spectral method", Eq. (2) and the paragraph after it): forward e^{-ikx} unnormalised,
- *     inverse with 1/N, computed by a textbook recursive radix-2 Cooley-Tukey FFT applied
- *     row-column along every axis;
+ *     inverse with 1/N, computed by a textbook recursive Cooley-Tukey FFT (decimation in time over
+ *     the smallest prime factor of the length: radix 2 for powers of two, a plain p-point DFT per
+ *     output group otherwise) applied row-column along every axis;
  *   - the PFC free energy, Eq. (3), and the PFC dynamics, Eq. (4), with the correlation operator
  *     written as a polynomial in q = |k|^2 (Eq. (2): a derivative of order n becomes (ik)^n);
  *   - the semi-implicit step of Listing 1 (the update of psiF): the cubic term is evaluated
@@ -62,13 +63,12 @@ typedef struct {
     int no_projection; /* 1: skip the Hermitian projection (demonstrates the drift) */
 } or_params;
 
-static int is_pow2(int64_t v) { return v >= 1 && (v & (v - 1)) == 0; }
-
+/* Every axis even (so that kx = n/2 is a self-conjugate plane of the half spectrum) and >= 2. */
 static int check_dims(int ndim, const int64_t *n)
 {
     if (ndim < 1 || ndim > 3) return 0;
     for (int a = 0; a < ndim; ++a)
-        if (!is_pow2(n[a]) || n[a] < 2) return 0;
+        if (n[a] < 2 || n[a] % 2 != 0) return 0;
     return 1;
 }
 
@@ -79,38 +79,63 @@ static int64_t total_size(int ndim, const int64_t *n)
     return t;
 }
 
-/* ---------------------------------------------------------------- 1D FFT (recursive radix-2) */
+/* ---------------------------------------------------------------- 1D FFT (recursive Cooley-Tukey) */
 
-/* w[j] = exp(sign * 2 pi i j / N), j < N/2.  Each entry from cos/sin of its own angle. */
+/* w[j] = exp(sign * 2 pi i j / N), j < N.  Each entry from cos/sin of its own angle. */
 static cplx *twiddles(int64_t N, int sign)
 {
-    int64_t h = N / 2 > 0 ? N / 2 : 1;
-    cplx *w = (cplx *)malloc(sizeof(cplx) * (size_t)h);
+    cplx *w = (cplx *)malloc(sizeof(cplx) * (size_t)N);
     if (!w) return NULL;
-    for (int64_t j = 0; j < h; ++j) {
+    for (int64_t j = 0; j < N; ++j) {
         double ang = 2.0 * PI * (double)j / (double)N;
         w[j] = cos(ang) + (double)sign * sin(ang) * I;
     }
     return w;
 }
 
-/* Decimation in time: out[0..n) = DFT of in[0], in[stride], ..., in[(n-1) stride].
- * W_n^k = w[k * wstep] where wstep = N/n for the top-level length N. */
-static void fft_rec(const cplx *in, int64_t stride, cplx *out, int64_t n, const cplx *w, int64_t wstep)
+/* Smallest prime factor of n >= 2. */
+static int64_t smallest_factor(int64_t n)
+{
+    for (int64_t f = 2; f * f <= n; ++f)
+        if (n % f == 0) return f;
+    return n;
+}
+
+/* Decimation in time: out[0..n) = DFT of in[0], in[stride], ..., in[(n-1) stride], for the
+ * top-level length N whose powers w[] holds; W_n^x = w[(x * wstep) mod N] with wstep = N / n.
+ * With p the smallest prime factor of n and q = n / p, the p interleaved subsequences
+ * in[r], in[r + p], ... (r < p) have q-point DFTs Y_r, and
+ *     X[k + q s] = sum_{r < p} W_p^{r s} (W_n^{r k} Y_r[k]),   k < q, s < p.
+ * p = 2 is the radix-2 butterfly X[k] = Y_0[k] + W_n^k Y_1[k], X[k + q] = Y_0[k] - W_n^k Y_1[k]. */
+static void fft_rec(const cplx *in, int64_t stride, cplx *out, int64_t n, const cplx *w, int64_t wstep, int64_t N)
 {
     if (n == 1) {
         out[0] = in[0];
         return;
     }
-    int64_t h = n / 2;
-    fft_rec(in, 2 * stride, out, h, w, 2 * wstep);          /* even samples -> out[0..h)  */
-    fft_rec(in + stride, 2 * stride, out + h, h, w, 2 * wstep); /* odd samples -> out[h..n) */
-    for (int64_t k = 0; k < h; ++k) {
-        cplx e = out[k];
-        cplx t = w[k * wstep] * out[k + h];
-        out[k] = e + t;
-        out[k + h] = e - t;
+    const int64_t p = smallest_factor(n), q = n / p;
+    for (int64_t r = 0; r < p; ++r) fft_rec(in + r * stride, p * stride, out + r * q, q, w, p * wstep, N);
+    if (p == 2) {
+        for (int64_t k = 0; k < q; ++k) {
+            cplx e = out[k];
+            cplx t = w[k * wstep] * out[k + q];
+            out[k] = e + t;
+            out[k + q] = e - t;
+        }
+        return;
     }
+    cplx *t = (cplx *)malloc(sizeof(cplx) * (size_t)p);
+    if (!t) abort();
+    const int64_t wp = N / p; /* W_p^x = w[x * wp] */
+    for (int64_t k = 0; k < q; ++k) {
+        for (int64_t r = 0; r < p; ++r) t[r] = w[(r * k * wstep) % N] * out[r * q + k];
+        for (int64_t s2 = 0; s2 < p; ++s2) {
+            cplx acc = 0;
+            for (int64_t r = 0; r < p; ++r) acc += w[((r * s2) % p) * wp] * t[r];
+            out[k + q * s2] = acc;
+        }
+    }
+    free(t);
 }
 
 /* In-place complex FFT along one axis of an nd complex array. sign = -1 forward, +1 inverse
@@ -137,7 +162,7 @@ static int fft_axis(cplx *data, int ndim, const int64_t *n, int axis, int sign)
                 int64_t outer = l / inner, in = l % inner;
                 cplx *base = data + outer * len * inner + in;
                 for (int64_t j = 0; j < len; ++j) src[j] = base[j * inner];
-                fft_rec(src, 1, dst, len, w, 1);
+                fft_rec(src, 1, dst, len, w, 1, len);
                 for (int64_t j = 0; j < len; ++j) base[j * inner] = dst[j];
             }
         }

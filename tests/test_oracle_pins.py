@@ -33,7 +33,9 @@ def relerr(a, b):
     return np.linalg.norm((a - b).ravel()) / np.linalg.norm(np.asarray(b).ravel())
 
 
-SHAPES = [(16,), (8, 4), (4, 8), (8, 16, 4), (4, 4, 8), (2, 8, 16)]
+SHAPES = [(16,), (8, 4), (4, 8), (8, 16, 4), (4, 4, 8), (2, 8, 16),
+          # lengths with factors 3, 5, 7 (the paper's grids 750 = 2 3 5^3 and 1400 = 2^3 5^2 7)
+          (6,), (10,), (14,), (30,), (6, 10), (12, 14), (2, 6, 10), (10, 4, 6), (42,), (70, 2)]
 
 
 # ------------------------------------------------------------------------------------ FFT pins
@@ -51,7 +53,8 @@ def test_c2c_both_signs_equal_brute_force(shape):
     assert relerr(oracle.fft_c2c(z, +1), np.conj(brute_dft(np.conj(z)))) < 1e-13
 
 
-@pytest.mark.parametrize("shape", [(64, 32), (16, 32, 64), (128, 128), (32, 16, 8)])
+@pytest.mark.parametrize("shape", [(64, 32), (16, 32, 64), (128, 128), (32, 16, 8), (30, 20, 14), (750, 12),
+                                   (12, 1400), (6, 10, 750), (150, 210)])
 def test_rfftn_equals_numpy(shape):
     f = P.normal(14, shape)
     assert relerr(oracle.rfftn(f), np.fft.rfftn(f)) < 1e-13
@@ -71,7 +74,7 @@ def test_single_mode_is_exact():
     assert np.abs(X - expect).max() < 1e-14 * N
 
 
-@pytest.mark.parametrize("shape", [(8, 16, 4), (32, 64), (64,)])
+@pytest.mark.parametrize("shape", [(8, 16, 4), (32, 64), (64,), (30, 20, 14), (750,), (28, 10)])
 def test_parseval_roundtrip_linearity(shape):
     f, g = P.normal(15, shape), P.normal(16, shape)
     F, G = oracle.rfftn(f), oracle.rfftn(g)
@@ -124,11 +127,10 @@ def kgrid_q(shape, dx=DX):
     return sum(g * g for g in grids)
 
 
-@pytest.mark.parametrize("model", [0, 1])
-def test_linear_decay_closed_form(model):
+@pytest.mark.parametrize("model,shape", [(0, (16, 32)), (1, (16, 32)), (0, (30, 14)), (1, (6, 10, 14))])
+def test_linear_decay_closed_form(model, shape):
     """With the cubic term off, Eq. (4) is d/dt psi_k = -q (r + L(q)) psi_k per Fourier mode; the
     implicit linear step multiplies mode k by 1/(1 + dt q (r + L(q))) per step."""
-    shape = (16, 32)
     p = oracle.Params(shape, model=model, r=-0.25, dt=0.5, q1sq=2.0, R1=0.05, linear_only=True)
     psi0 = P.pfc_initial_field(1, shape, -0.25)
     S0 = oracle.rfftn(psi0)
@@ -137,7 +139,7 @@ def test_linear_decay_closed_form(model):
     growth = 1.0 / (1.0 + 0.5 * q * (-0.25 + corr))
     psi, S = oracle.step(p, psi0, S0, 7)
     assert relerr(S, S0 * growth**7) < 1e-13
-    assert relerr(psi, np.fft.irfftn(S0 * growth**7, shape, axes=(0, 1))) < 1e-13
+    assert relerr(psi, np.fft.irfftn(S0 * growth**7, shape, axes=tuple(range(len(shape))))) < 1e-13
 
 
 def test_step_consistent_with_pde_as_dt_to_zero():
@@ -201,14 +203,18 @@ def test_translation_commutes_with_step():
     assert np.abs(a - np.roll(b, (5, 3, 11), axis=(0, 1, 2))).max() < 1e-13
 
 
-def test_tiling_invariance():
-    p_small = oracle.Params((16, 16), r=-0.25)
-    p_big = oracle.Params((32, 64), r=-0.25)
-    psi0 = P.pfc_initial_field(4, (16, 16), -0.25)
-    big0 = np.tile(psi0, (2, 4))
+@pytest.mark.parametrize("small,reps", [((16, 16), (2, 4)), ((10, 6), (3, 5)), ((4, 6, 10), (7, 5, 3))])
+def test_tiling_invariance(small, reps):
+    """A field tiled k times along an axis evolves as the tiles of the small run (the big grid's
+    spectrum lives on multiples of k); factors 3, 5, 7 exercise the non-radix-2 recursion."""
+    big = tuple(n * k for n, k in zip(small, reps))
+    p_small = oracle.Params(small, r=-0.25)
+    p_big = oracle.Params(big, r=-0.25)
+    psi0 = P.pfc_initial_field(4, small, -0.25)
+    big0 = np.tile(psi0, reps)
     a, _ = oracle.step(p_small, psi0, oracle.rfftn(psi0), 20)
     b, _ = oracle.step(p_big, big0, oracle.rfftn(big0), 20)
-    assert np.abs(np.tile(a, (2, 4)) - b).max() < 1e-13
+    assert np.abs(np.tile(a, reps) - b).max() < 1e-13
 
 
 # ------------------------------------------------------------------------------------ energy pins
