@@ -21,6 +21,17 @@ static hipError_t by_length(int64_t L, F &&f)
     case 512: return f(std::integral_constant<int, 512>{});
     case 1024: return f(std::integral_constant<int, 1024>{});
     case 2048: return f(std::integral_constant<int, 2048>{});
+    case 6: return f(std::integral_constant<int, 6>{});
+    case 10: return f(std::integral_constant<int, 10>{});
+    case 12: return f(std::integral_constant<int, 12>{});
+    case 14: return f(std::integral_constant<int, 14>{});
+    case 15: return f(std::integral_constant<int, 15>{});
+    case 20: return f(std::integral_constant<int, 20>{});
+    case 30: return f(std::integral_constant<int, 30>{});
+    case 60: return f(std::integral_constant<int, 60>{});
+    case 150: return f(std::integral_constant<int, 150>{});
+    case 375: return f(std::integral_constant<int, 375>{});
+    case 750: return f(std::integral_constant<int, 750>{});
     default: return hipErrorInvalidValue;
     }
 }
@@ -33,6 +44,9 @@ static hipError_t with_nt(bool nt, F &&f)
 {
     return nt ? f(std::true_type{}) : f(std::false_type{});
 }
+
+// Largest even width <= w (w >= 2).
+static inline int even_width(int w) { return w > 1 ? (w & ~1) : w; }
 
 // Workgroups per 128-byte line for column tiles of W complex values (1 for whole-line tiles).
 template <typename T>
@@ -66,7 +80,7 @@ hipError_t launch_x_r2c(const Geom &g, const T *in, cx<T> *out, bool cube, const
                 // non-temporal hints measured faster at M = 256 and slower at M = 1024
                 return with_nt(g.nt && M < 1024, [&](auto ntc) -> hipError_t {
                     hipLaunchKernelGGL((x_r2c_kernel<T, PL, ROWS, CUBE, false, decltype(ntc)::value>), grid, block, 0,
-                                       s, in, out, g.xrows, tw, g.lt_shift);
+                                       s, in, out, g.xrows, tw + g.tw_x, g.lt_shift);
                     return hipGetLastError();
                 });
             };
@@ -92,7 +106,7 @@ hipError_t launch_x_c2r(const Geom &g, const cx<T> *in, T *out, const cx<T> *tw,
                 AdjEpi<T> ea{};
                 return with_nt(g.nt, [&](auto ntc) -> hipError_t {
                     hipLaunchKernelGGL((x_c2r_kernel<T, PL, ROWS, EPI_PLAIN, false, false, decltype(ntc)::value>), grid,
-                                       block, 0, s, in, out, g.xrows, tw, g.lt_shift, sc, ea);
+                                       block, 0, s, in, out, g.xrows, tw + g.tw_x, g.lt_shift, sc, ea);
                     return hipGetLastError();
                 });
             });
@@ -116,8 +130,8 @@ hipError_t launch_x_c2r_adjoint(const Geom &g, const cx<T> *mu, const cx<T> *nu,
             const dim3 grid((unsigned)nb), block(ROWS * PL::Tp);
             const T sc = (T)(1.0 / ((double)g.M * (double)g.n0 * (double)g.nrows));
             AdjEpi<T> ea{nu, psi_n, psi_np1, c3, partial};
-            hipLaunchKernelGGL((x_c2r_kernel<T, PL, ROWS, EPI_ADJOINT>), grid, block, 0, s, mu, out, g.xrows, tw,
-                               g.lt_shift, sc, ea);
+            hipLaunchKernelGGL((x_c2r_kernel<T, PL, ROWS, EPI_ADJOINT>), grid, block, 0, s, mu, out, g.xrows,
+                               tw + g.tw_x, g.lt_shift, sc, ea);
             return hipGetLastError();
         }
     });
@@ -144,10 +158,10 @@ hipError_t launch_y_c2c(const Geom &g, cx<T> *data, int dir, const cx<T> *tw, hi
                     constexpr bool NT = decltype(ntc)::value;
                     if (dir < 0)
                         hipLaunchKernelGGL((axis_c2c_kernel<T, PL, WM, -1, 1, NT, TL::G>), grid, block, 0, s, data,
-                                           data, W, g.M, g.M, g.n1 * g.M, tiles, tw, g.lt_shift, xg);
+                                           data, W, g.M, g.M, g.n1 * g.M, tiles, tw + g.tw_y, g.lt_shift, xg);
                     else
                         hipLaunchKernelGGL((axis_c2c_kernel<T, PL, WM, +1, 1, NT, TL::G>), grid, block, 0, s, data,
-                                           data, W, g.M, g.M, g.n1 * g.M, tiles, tw, g.lt_shift, xg);
+                                           data, W, g.M, g.M, g.n1 * g.M, tiles, tw + g.tw_y, g.lt_shift, xg);
                     return hipGetLastError();
                 });
             });
@@ -170,7 +184,7 @@ hipError_t launch_last_fwd(const Geom &g, const cx<T> *src, cx<T> *dst, const cx
             const int64_t tiles = cdiv(ncols, W);
             const dim3 grid((unsigned)tiles), block(WM * PL::Tp);
             hipLaunchKernelGGL((axis_c2c_kernel<T, PL, WM, -1>), grid, block, 0, s, src, dst, W, ncols, ncols,
-                               (int64_t)0, tiles, tw, g.lt_shift, 1);
+                               (int64_t)0, tiles, tw + g.tw_last, g.lt_shift, 1);
             return hipGetLastError();
         }
     });
@@ -193,9 +207,10 @@ hipError_t launch_last(const Geom &g, int mode, const cx<T> *src, cx<T> *dst, cx
             a.state = state;
             a.nrows = g.nrows;
             a.M = (int)g.M;
-            a.W = (int)(g.M < WM ? g.M : WM);
-            a.tiles_per_row = (int)(g.M / a.W);
-            a.tw = tw;
+            // even tile width: the pair tiles split it between the rows k_y and -k_y
+            a.W = even_width(g.M < WM ? (int)g.M : WM);
+            a.tiles_per_row = (int)cdiv(g.M, a.W);
+            a.tw = tw + g.tw_last;
             a.lt_shift = g.lt_shift;
             a.mp = mp;
             const int64_t nblocks = (g.nrows == 1) ? a.tiles_per_row : g.nrows * a.tiles_per_row;
@@ -207,8 +222,8 @@ hipError_t launch_last(const Geom &g, int mode, const cx<T> *src, cx<T> *dst, cx
                     using TL = PencilTile<T, L>;
                     using PL = SpreadIf<decltype(plc), TL::E>;
                     LastAxisArgs<T> b = a;
-                    b.W = (int)(g.M < TL::W ? g.M : TL::W);
-                    b.tiles_per_row = (int)(g.M / b.W);
+                    b.W = even_width(g.M < TL::W ? (int)g.M : TL::W);
+                    b.tiles_per_row = (int)cdiv(g.M, b.W);
                     const int64_t nb = (g.nrows == 1) ? b.tiles_per_row : g.nrows * b.tiles_per_row;
                     return with_nt(g.nt && line_group<T>(b.W) == 1, [&](auto ntc) -> hipError_t {
                         hipLaunchKernelGGL((last_axis_kernel<T, PL, TL::W, LA_STEP, 1, TL::PF, ORD_TILE,
@@ -224,12 +239,13 @@ hipError_t launch_last(const Geom &g, int mode, const cx<T> *src, cx<T> *dst, cx
                 // column tiles in whole rows per XCD
                 using TL = PencilTile<T, L>;
                 constexpr int C = 128 / (int)sizeof(cx<T>);
-                if constexpr (TL::W == C) {
+                if constexpr (TL::W == C && L <= 1024) {  // at 2048 the two rounds' registers would spill
                     if (g.nrows > 1 && (g.nrows * (g.M + 1)) % C == 0 && g.M >= C) {
                         using PL = SpreadIf<P0, TL::E>;
                         const int64_t nchunks = g.nrows * (g.M + 1) / C;
                         hipLaunchKernelGGL((r2c_natural_chunk_kernel<T, PL, C, TL::G>), dim3((unsigned)nchunks),
-                                           dim3(C * PL::Tp), 0, s, src, dst, g.nrows, (int)g.M, tw, g.lt_shift);
+                                           dim3(C * PL::Tp), 0, s, src, dst, g.nrows, (int)g.M, tw + g.tw_last,
+                                           g.lt_shift);
                         break;
                     }
                 }

@@ -92,12 +92,132 @@ __device__ __forceinline__ cx<T> rot(cx<T> a)
     }
 }
 
-// In-register DFT of size R (power of two <= 16), natural order in and out.  Radix-2 decimation
-// in time, fully unrolled.
+// cos and sin of 2 pi a / b, computed at compile time in long double: the angle is reduced to the
+// first octant exactly in integers (units of 2 pi / 8b), then Taylor series (|x| <= pi / 4, 24
+// terms: far below long double rounding).  Constants of the in-register DFTs of radices with
+// factors 3, 5, 7.
+__host__ __device__ constexpr long double taylor_sin(long double x)
+{
+    long double term = x, sum = x;
+    for (int n = 1; n < 24; ++n) {
+        term *= -x * x / ((long double)(2 * n) * (long double)(2 * n + 1));
+        sum += term;
+    }
+    return sum;
+}
+__host__ __device__ constexpr long double taylor_cos(long double x)
+{
+    long double term = 1.0L, sum = 1.0L;
+    for (int n = 1; n < 24; ++n) {
+        term *= -x * x / ((long double)(2 * n - 1) * (long double)(2 * n));
+        sum += term;
+    }
+    return sum;
+}
+// which = 0: cos(2 pi a / b), 1: sin(2 pi a / b)
+__host__ __device__ constexpr long double cs2pi(long long a, long long b, int which)
+{
+    long long u = ((a % b) + b) % b * 8;  // angle = 2 pi u / (8 b), u in [0, 8b)
+    long double sc = 1.0L, ss = 1.0L;
+    bool swap = false;
+    if (u > 4 * b) {  // (pi, 2 pi): reflect, sin changes sign
+        u = 8 * b - u;
+        ss = -ss;
+    }
+    if (u > 2 * b) {  // (pi/2, pi]: cos changes sign
+        u = 4 * b - u;
+        sc = -sc;
+    }
+    if (u > b) {  // (pi/4, pi/2]: cos and sin exchange
+        u = 2 * b - u;
+        swap = true;
+    }
+    const long double x = 6.283185307179586476925286766559005768L * (long double)u / (long double)(8 * b);
+    const long double c = swap ? taylor_sin(x) : taylor_cos(x), sn = swap ? taylor_cos(x) : taylor_sin(x);
+    return which == 0 ? sc * c : ss * sn;
+}
+
+__host__ __device__ constexpr bool is_pow2c(int v) { return v > 0 && (v & (v - 1)) == 0; }
+__host__ __device__ constexpr int smallest_factor(int v)
+{
+    for (int f = 2; f * f <= v; ++f)
+        if (v % f == 0) return f;
+    return v;
+}
+__host__ __device__ constexpr int gcdc(int a, int b) { return b == 0 ? a : gcdc(b, a % b); }
+__host__ __device__ constexpr int lcmc(int a, int b) { return a / gcdc(a, b) * b; }
+
+// a * exp(DIR * 2 pi i K / R) for any R (exact for multiples of a quarter turn).
+template <typename T, int R, int K, int DIR>
+__device__ __forceinline__ cx<T> rotg(cx<T> a)
+{
+    constexpr int k = ((K % R) + R) % R;
+    if constexpr (16 % R == 0) {
+        return rot<T, R, k, DIR>(a);
+    } else if constexpr (k == 0) {
+        return a;
+    } else if constexpr (2 * k == R) {
+        return {-a.x, -a.y};
+    } else if constexpr (4 * k == R) {
+        return DIR > 0 ? mul_i(a) : mul_mi(a);
+    } else if constexpr (4 * k == 3 * R) {
+        return DIR > 0 ? mul_mi(a) : mul_i(a);
+    } else {
+        constexpr T c = (T)cs2pi(k, R, 0);
+        constexpr T sn = (T)(DIR * cs2pi(k, R, 1));
+        return {a.x * c - a.y * sn, a.x * sn + a.y * c};
+    }
+}
+
+// In-register DFT of size R, natural order in and out, fully unrolled.  Powers of two: radix-2
+// decimation in time.  Other R (factors 2, 3, 5, 7): decimation in time over the smallest prime
+// factor p (q = R / p): X[k + q s] = sum_r W_p^{r s} W_R^{r k} DFT_q(v[r], v[r + p], ...)[k]; a
+// prime R is summed directly.
 template <typename T, int R, int DIR>
 __device__ __forceinline__ void dft(cx<T> *v)
 {
-    if constexpr (R == 2) {
+    if constexpr (!is_pow2c(R)) {
+        constexpr int p = smallest_factor(R), q = R / p;
+        if constexpr (q == 1) {
+            cx<T> in[R];
+#pragma unroll
+            for (int r = 0; r < R; ++r) in[r] = v[r];
+            static_for<0, R>([&](auto sc) {
+                constexpr int s2 = decltype(sc)::value;
+                cx<T> acc = in[0];
+                static_for<1, R>([&](auto rc) {
+                    constexpr int r = decltype(rc)::value;
+                    acc = acc + rotg<T, R, r * s2, DIR>(in[r]);
+                });
+                v[s2] = acc;
+            });
+        } else {
+            cx<T> e[p][q];
+#pragma unroll
+            for (int r = 0; r < p; ++r) {
+#pragma unroll
+                for (int j = 0; j < q; ++j) e[r][j] = v[r + p * j];
+                dft<T, q, DIR>(e[r]);
+            }
+            static_for<0, q>([&](auto kc) {
+                constexpr int k = decltype(kc)::value;
+                cx<T> tt[p];
+                static_for<0, p>([&](auto rc) {
+                    constexpr int r = decltype(rc)::value;
+                    tt[r] = rotg<T, R, r * k, DIR>(e[r][k]);
+                });
+                static_for<0, p>([&](auto sc) {
+                    constexpr int s2 = decltype(sc)::value;
+                    cx<T> acc = tt[0];
+                    static_for<1, p>([&](auto rc) {
+                        constexpr int r = decltype(rc)::value;
+                        acc = acc + rotg<T, p, r * s2, DIR>(tt[r]);
+                    });
+                    v[k + q * s2] = acc;
+                });
+            });
+        }
+    } else if constexpr (R == 2) {
         cx<T> a = v[0], b = v[1];
         v[0] = a + b;
         v[1] = a - b;
@@ -119,12 +239,13 @@ __device__ __forceinline__ void dft(cx<T> *v)
     }
 }
 
-// Radix schedule of a length-L FFT: up to three stages.
+// Radix schedule of a length-L FFT: up to three stages.  Each thread holds Rmax = lcm of the
+// radices elements (the largest radix for powers of two), i.e. Rmax / R butterflies of every stage.
 template <int A, int B = 1, int C = 1>
 struct Radices {
     static constexpr int nst = (B == 1) ? 1 : (C == 1 ? 2 : 3);
     static constexpr int L = A * B * C;
-    static constexpr int Rmax = (A > B ? (A > C ? A : C) : (B > C ? B : C));
+    static constexpr int Rmax = lcmc(lcmc(A, B), C);
     static constexpr int Tp = L / Rmax;  // threads per pencil
     __host__ __device__ static constexpr int radix(int s) { return s == 0 ? A : s == 1 ? B : C; }
     __host__ __device__ static constexpr int prefix(int s) { return s == 0 ? 1 : s == 1 ? A : A * B; }
@@ -134,6 +255,23 @@ struct Radices {
     using Reverse = std::conditional_t<nst == 1, Radices<A>,
                                        std::conditional_t<nst == 2, Radices<B, A>, Radices<C, B, A>>>;
 };
+
+// Offset of stage s in a table of per-stage blocks (prefix(s) * radix(s) entries each).
+template <class P>
+__host__ __device__ constexpr int stage_blocks_off(int s)
+{
+    int o = 0;
+    for (int i = 0; i < s; ++i) o += P::prefix(i) * P::radix(i);
+    return o;
+}
+template <class P, class Q>
+__host__ __device__ constexpr bool same_stages()
+{
+    if (P::nst != Q::nst) return false;
+    for (int i = 0; i < P::nst; ++i)
+        if (P::radix(i) != Q::radix(i)) return false;
+    return true;
+}
 
 // The schedule PL with E >= PL::Rmax elements per thread (E / R butterflies of each stage per
 // thread): Tp = L / E threads per pencil.  Fewer threads per pencil for long pencils, so that a
@@ -159,6 +297,30 @@ template <> struct DefaultPlan<256> { using type = Radices<16, 16>; };
 template <> struct DefaultPlan<512> { using type = Radices<8, 8, 8>; };
 template <> struct DefaultPlan<1024> { using type = Radices<8, 8, 16>; };
 template <> struct DefaultPlan<2048> { using type = Radices<8, 16, 16>; };
+// lengths with factors 3, 5, 7 (one schedule each; elements per thread = lcm of the radices)
+template <> struct DefaultPlan<6> { using type = Radices<6>; };
+template <> struct DefaultPlan<10> { using type = Radices<10>; };
+template <> struct DefaultPlan<12> { using type = Radices<12>; };
+template <> struct DefaultPlan<14> { using type = Radices<14>; };
+template <> struct DefaultPlan<15> { using type = Radices<15>; };
+template <> struct DefaultPlan<20> { using type = Radices<10, 2>; };
+template <> struct DefaultPlan<30> { using type = Radices<10, 3>; };
+template <> struct DefaultPlan<60> { using type = Radices<10, 6>; };
+template <> struct DefaultPlan<150> { using type = Radices<10, 15>; };
+template <> struct DefaultPlan<375> { using type = Radices<15, 5, 5>; };
+template <> struct DefaultPlan<750> { using type = Radices<10, 15, 5>; };
+// the schedule whose twiddle table a non-power-of-two length carries
+template <int L>
+struct MixPlan {
+    using type = typename DefaultPlan<L>::type;
+};
+template <int L>
+struct MixTable {
+    using F = typename MixPlan<L>::type;
+    using Rv = typename F::Reverse;
+    static constexpr int split = stage_blocks_off<F>(F::nst) + stage_blocks_off<Rv>(Rv::nst);
+    static constexpr int size = split + L;  // entries, with the x-pass split twiddles
+};
 
 // Candidate schedules per pass kind and length.  Candidate 0 is the default (measured best on
 // MI355X at 512^3 FP32 where the lengths occur there); the autotuner may pick another per plan.
@@ -225,13 +387,25 @@ __device__ __forceinline__ cx<T> twiddle(const cx<T> *__restrict__ tw, int lt_sh
 
 __host__ __device__ constexpr int ilog2c(int v) { return v <= 1 ? 0 : 1 + ilog2c(v / 2); }
 
-enum { TW_LT = 0, TW_STAGE = 1 };
+enum { TW_LT = 0, TW_STAGE = 1, TW_MIX = 2 };
 
-// Multiplies v[r], 0 < r < R, by the twiddles W_{Ns R}^{jj r} (conjugated for the inverse).
-template <typename T, int R, int Ns, int DIR, int TWM>
+// Twiddle table of a length L that is not a power of two (TW_MIX; one table per such length of a
+// plan, at the pointer the kernel receives): for the length's schedule F and then for F's reverse,
+// per stage s a block of prefix(s) * radix(s) entries, entry jj R + r = W_{Ns R}^{jj r}; then the
+// x-pass split twiddles W_{2L}^k, k < L.
+// Multiplies v[r], 0 < r < R, by the twiddles W_{Ns R}^{jj r} of stage s of schedule PL
+// (conjugated for the inverse).
+template <typename T, class PL, int s, int DIR, int TWM>
 __device__ __forceinline__ void apply_twiddles(cx<T> *v, int jj, const cx<T> *__restrict__ tw, int lt_shift)
 {
-    if constexpr (TWM == TW_STAGE) {
+    constexpr int R = PL::radix(s), Ns = PL::prefix(s);
+    if constexpr (TWM == TW_MIX) {
+        using F = typename MixPlan<PL::L>::type;
+        constexpr int base = same_stages<PL, F>() ? 0 : stage_blocks_off<F>(F::nst);
+        const cx<T> *st = tw + base + stage_blocks_off<PL>(s) + (unsigned)(jj * R);
+#pragma unroll
+        for (int r = 1; r < R; ++r) v[r] = cmul(v[r], DIR > 0 ? conj(st[r]) : st[r]);
+    } else if constexpr (TWM == TW_STAGE) {
         const cx<T> *st = tw + (1u << lt_shift) + stage_tw_offset(Ns * R, R) + (unsigned)(jj * R);
         if constexpr (sizeof(T) == 4) {
             // FP32: two twiddles per 16-byte load (entry 0 is 1 and is skipped)
@@ -261,12 +435,14 @@ __device__ __forceinline__ void apply_twiddles(cx<T> *v, int jj, const cx<T> *__
 // write is preceded by a barrier, so the caller may have used the same LDS just before.
 // G > 1: the workgroup's pencils form G groups (this thread's is `grp`) that take turns in one
 // LDS area sized for a single group, so each exchange costs G barrier pairs and 1/G of the LDS.
+// Lengths that are not powers of two always take their own table (TW_MIX).
 template <typename T, class PL, int DIR, int TWM = TW_STAGE, int G = 1, class Lds>
 __device__ __forceinline__ void fft_stages(cx<T> *v, int t, Lds &&lds, const cx<T> *__restrict__ tw, int lt_shift,
                                            int grp = 0)
 {
     constexpr int L = PL::L;
     constexpr int Tp = PL::Tp;
+    constexpr int TW = is_pow2c(L) ? TWM : TW_MIX;
     static_for<0, PL::nst>([&](auto sc) {
         constexpr int s = decltype(sc)::value;
         constexpr int R = PL::radix(s);
@@ -278,7 +454,7 @@ __device__ __forceinline__ void fft_stages(cx<T> *v, int t, Lds &&lds, const cx<
             // exchange, then the next stage's inputs and twiddles
             constexpr int R2 = PL::radix(s + 1);
             constexpr int B2 = PL::Rmax / R2;
-            constexpr int Ns2 = PL::prefix(s + 1);
+            constexpr unsigned Ns2 = PL::prefix(s + 1);
 #pragma unroll
             for (int gg = 0; gg < G; ++gg) {
                 const bool mine = (G == 1) || (grp == gg);
@@ -286,8 +462,8 @@ __device__ __forceinline__ void fft_stages(cx<T> *v, int t, Lds &&lds, const cx<
                 if (mine) {
 #pragma unroll
                     for (int b = 0; b < B; ++b) {
-                        const int j = t + b * Tp;
-                        const int base = (j / Ns) * Ns * R + (j & (Ns - 1));
+                        const unsigned j = t + b * Tp;
+                        const int base = (int)((j / Ns) * Ns * R + j % Ns);
 #pragma unroll
                         for (int r = 0; r < R; ++r) lds(base + r * Ns) = v[b * R + r];
                     }
@@ -304,7 +480,7 @@ __device__ __forceinline__ void fft_stages(cx<T> *v, int t, Lds &&lds, const cx<
             }
 #pragma unroll
             for (int b = 0; b < B2; ++b)
-                apply_twiddles<T, R2, Ns2, DIR, TWM>(&v[b * R2], (t + b * Tp) & (Ns2 - 1), tw, lt_shift);
+                apply_twiddles<T, PL, s + 1, DIR, TW>(&v[b * R2], (int)((unsigned)(t + b * Tp) % Ns2), tw, lt_shift);
         }
     });
 }

@@ -71,6 +71,27 @@ __device__ __forceinline__ void st_grid(cx<T> *p, cx<T> a)
 
 __device__ __forceinline__ int signed_index(int64_t i, int64_t n) { return (int)(i <= n / 2 ? i : i - n); }
 
+// (-e) mod L for 0 <= e < L
+template <int L>
+__device__ __forceinline__ int neg_mod(int e)
+{
+    if constexpr (is_pow2c(L))
+        return (L - e) & (L - 1);
+    else
+        return e == 0 ? 0 : L - e;
+}
+
+// x-pass split twiddle W_{2M}^k, 0 <= k < M: from the W_Lt table, or from the length's own table
+// (lengths that are not powers of two; layout in fft_core.hpp)
+template <typename T, int M>
+__device__ __forceinline__ cx<T> split_twiddle(const cx<T> *__restrict__ tw, int lt_shift, int k)
+{
+    if constexpr (is_pow2c(M))
+        return tw[k << (lt_shift - ilog2c(2 * M))];
+    else
+        return tw[MixTable<M>::split + k];
+}
+
 // ------------------------------------------------------------------------------------------------
 // Block-wide FP64 sum; the result is valid in thread 0.  red: >= blockDim.x/64 doubles of LDS.
 __device__ __forceinline__ double block_sum(double v, double *red)
@@ -138,7 +159,6 @@ __device__ __forceinline__ void x_r2c_block(const T *__restrict__ in, cx<T> *__r
         for (int r = 0; r < Rl; ++r) lds(t + b * Tp + r * (M / Rl)) = v[b * Rl + r];
     __syncthreads();
     cx<T> *dst = out + (valid ? row : 0) * M;
-    constexpr int tshift = ilog2c(2 * M);
     const T h = T(0.5);
 #pragma unroll
     for (int b = 0; b < Rmax / Rl; ++b)
@@ -153,7 +173,7 @@ __device__ __forceinline__ void x_r2c_block(const T *__restrict__ in, cx<T> *__r
                 const cx<T> Zp = lds(M - k);
                 const cx<T> E = {(Zk.x + Zp.x) * h, (Zk.y - Zp.y) * h};
                 const cx<T> O = {(Zk.y + Zp.y) * h, (Zp.x - Zk.x) * h};
-                X = E + cmul(tw[k << (lt_shift - tshift)], O);
+                X = E + cmul(split_twiddle<T, M>(tw, lt_shift, k), O);
             }
             if (valid) st_grid<NT>(&dst[k], X);
         }
@@ -196,7 +216,6 @@ __device__ __forceinline__ void x_c2r_row(cx<T> *v, const cx<T> *src, bool valid
                                           const cx<T> *__restrict__ tw, int lt_shift)
 {
     constexpr int M = PL::L, Tp = PL::Tp, R0 = PL::first, Rmax = PL::Rmax;
-    constexpr int tshift = ilog2c(2 * M);
     cx<T> mir[PG ? Rmax : 1];
     if constexpr (PG) {
 #pragma unroll
@@ -205,7 +224,7 @@ __device__ __forceinline__ void x_c2r_row(cx<T> *v, const cx<T> *src, bool valid
             for (int r = 0; r < R0; ++r) {
                 const int k = t + b * Tp + r * (M / R0);
                 v[b * R0 + r] = valid ? ld_grid<NT>(&src[k]) : cx<T>{T(0), T(0)};
-                mir[b * R0 + r] = valid ? ld_grid<NT>(&src[(M - k) & (M - 1)]) : cx<T>{T(0), T(0)};
+                mir[b * R0 + r] = valid ? ld_grid<NT>(&src[neg_mod<M>(k)]) : cx<T>{T(0), T(0)};
             }
     } else {
         __syncthreads();
@@ -236,7 +255,7 @@ __device__ __forceinline__ void x_c2r_row(cx<T> *v, const cx<T> *src, bool valid
                     c = rowlds[xidx<PAD>(M - k)];
                 const cx<T> E = {(a.x + c.x) * h, (a.y - c.y) * h};
                 const cx<T> D = {(a.x - c.x) * h, (a.y + c.y) * h};
-                const cx<T> O = cmul(conj(tw[k << (lt_shift - tshift)]), D);
+                const cx<T> O = cmul(conj(split_twiddle<T, M>(tw, lt_shift, k)), D);
                 v[b * R0 + r] = {E.x - O.y, E.y + O.x};
             }
         }
@@ -319,7 +338,7 @@ struct WMax {
 template <typename T, int L>
 struct PencilTile {
     static constexpr int W = WMax<T, L>::value, E = 0, G = 1;
-    static constexpr bool PF = true;
+    static constexpr bool PF = is_pow2c(L);  // mixed radices hold up to 30 elements per thread
 };
 template <>
 struct PencilTile<float, 1024> {
@@ -503,7 +522,7 @@ __device__ __forceinline__ void last_axis_block(const LastAxisArgs<T> &a, int64_
     const int W = a.W;
     const int64_t nrows = a.nrows, M = a.M, estride = nrows * M;
     const SlotInfo si = la_slot<ORD, IL>(nrows, a.tiles_per_row, W, p < W ? p : 0, bid);
-    const bool valid = p < W;
+    const bool valid = p < W && si.kx < M;  // the last column tile of a row may be partial
     const int64_t coloff = si.row * M + si.kx;
     auto lds = [&](int e) -> cx<T> & { return sh[e * GW + p % GW]; };
     const ModelParams<T> &mp = a.mp;
@@ -529,7 +548,7 @@ __device__ __forceinline__ void last_axis_block(const LastAxisArgs<T> &a, int64_
                     if (si.partner < 0) {
                         z = a.src[i0 + si.kx];
                     } else {
-                        const int ep = (L - e) & (L - 1);
+                        const int ep = neg_mod<L>(e);
                         const int64_t i1 = ((int64_t)ep * nrows + prow) * pitch;
                         const cx<T> x0 = a.src[i0], x0p = a.src[i1], xn = a.src[i0 + M], xnp = a.src[i1 + M];
                         const T h = T(0.5);
@@ -584,7 +603,7 @@ __device__ __forceinline__ void last_axis_block(const LastAxisArgs<T> &a, int64_
                 v[b * R0 + r] = valid ? ld_grid<NT>(gp(a.src, b * Tp + r * (L / R0))) : cx<T>{T(0), T(0)};
         fft_stages<T, PL, -1, TW_STAGE, G>(v, t, lds, a.tw, a.lt_shift, grp);
         // forward spectrum in natural order: v[b*Rl + r] = X(e), e = t + b*Tp + r*L/Rl
-        auto partner_val = [&](int e) -> cx<T> { return sh[((L - e) & (L - 1)) * GW + si.partner % GW]; };
+        auto partner_val = [&](int e) -> cx<T> { return sh[neg_mod<L>(e) * GW + si.partner % GW]; };
         auto spectrum_to_lds = [&]() {
 #pragma unroll
             for (int b = 0; b < Rmax / Rl; ++b)
@@ -860,7 +879,7 @@ __global__ __launch_bounds__(C *PL::Tp) void r2c_natural_chunk_kernel(const cx<T
 #pragma unroll
                 for (int r = 0; r < Rl; ++r) {
                     const int e = t + b * Tp + r * (L / Rl);
-                    const cx<T> a = z[b * Rl + r], m = lds((L - e) & (L - 1));
+                    const cx<T> a = z[b * Rl + r], m = lds(neg_mod<L>(e));
                     const cx<T> out = (kx == 0) ? cx<T>{(a.x + m.x) * h, (a.y - m.y) * h}
                                                 : cx<T>{(a.y + m.y) * h, (m.x - a.x) * h};
                     dst[(int64_t)e * plane + f] = out;

@@ -18,7 +18,20 @@ struct Geom {
     int64_t xrows;       // rows of the x pass: n0 * nrows
     int lt_shift;        // log2 of the twiddle table length
     bool nt;             // non-temporal loads/stores of the grids in the step and FFT passes
+    // twiddle table of each pass, as an entry offset from the plan's twiddle buffer: 0 (the
+    // power-of-two tables) or the own table of a length that is not a power of two
+    int64_t tw_x, tw_y, tw_last;
 };
+
+// Lengths other than powers of two that have compiled schedules (factors 2, 3, 5, 7); a grid axis
+// of length n needs n here (y and last axis) or n / 2 here (x).
+constexpr int kMixedLengths[] = {6, 10, 12, 14, 15, 20, 30, 60, 150, 375, 750};
+inline bool mixed_length(int64_t n)
+{
+    for (int m : kMixedLengths)
+        if (n == m) return true;
+    return false;
+}
 
 // `variant`: candidate schedule of the pass (0 = default); only the step's passes (x r2c with the
 // cube, y forward/inverse, last-axis STEP, x c2r) have more than one candidate.

@@ -15,6 +15,7 @@
 #include <string>
 #include <vector>
 
+#include "fft_core.hpp"
 #include "launch.hpp"
 #include "types.hpp"
 
@@ -27,6 +28,7 @@ struct pfc_plan {
     double fk[3];  // 2 pi / (n dx) for axes (last-axis, rows, x)
     double dV;
     size_t tw_off, partial_off, watch_off, scratch_off, ws_need;
+    size_t tw_entries;  // power-of-two tables plus the own tables of non-power-of-two lengths
     size_t n_partials;
     char *ws = nullptr;
     size_t ws_bytes = 0;
@@ -120,9 +122,15 @@ pfc_status validate_desc(const pfc_plan_desc *d)
     if (!d) return fail(PFC_ERR_INVALID_ARG, "desc is NULL");
     if (d->ndim != 2 && d->ndim != 3) return fail(PFC_ERR_UNSUPPORTED, "ndim must be 2 or 3 (got %d)", d->ndim);
     for (int a = 0; a < d->ndim; ++a) {
-        if (!is_pow2(d->n[a]) || d->n[a] < 4 || d->n[a] > 2048)
-            return fail(PFC_ERR_UNSUPPORTED, "n[%d] = %lld: sizes must be powers of two in [4, 2048]", a,
-                        (long long)d->n[a]);
+        // axis lengths: powers of two in [4, 2048], or even lengths whose own (y, last axis) or half
+        // (x) length has a compiled mixed-radix schedule
+        const int64_t n = d->n[a], L = (a == d->ndim - 1) ? n / 2 : n;
+        const bool ok = (is_pow2(n) && n >= 4 && n <= 2048) || (n % 2 == 0 && n <= 2048 && pfc::mixed_length(L));
+        if (!ok)
+            return fail(PFC_ERR_UNSUPPORTED,
+                        "n[%d] = %lld: sizes must be powers of two in [4, 2048] or even lengths with a mixed-radix "
+                        "schedule",
+                        a, (long long)n);
         if (!(d->dx[a] > 0.0) || !std::isfinite(d->dx[a])) return fail(PFC_ERR_INVALID_ARG, "dx[%d] must be > 0", a);
     }
     if (d->dtype != PFC_F32 && d->dtype != PFC_F64) return fail(PFC_ERR_INVALID_ARG, "unknown dtype %d", (int)d->dtype);
@@ -185,6 +193,49 @@ std::vector<cx<T>> twiddle_table(int64_t Lt)
                 for (int r = 0; r < R; ++r) blk[jj * R + r] = tw[(jj * r * (Lt / Np)) % Lt];
         }
     return tw;
+}
+
+// Own twiddle table of a length L that is not a power of two (layout: MixTable in fft_core.hpp).
+template <typename T>
+cx<T> unit_root(int64_t m, int64_t N)  // exp(-2 pi i m / N)
+{
+    return {(T)pfc::cs2pi(m, N, 0), (T)(-pfc::cs2pi(m, N, 1))};
+}
+template <typename T, int L>
+void fill_mix_table(cx<T> *out)
+{
+    using MT = pfc::MixTable<L>;
+    auto blocks = [&](auto pc, int base) {
+        using P = decltype(pc);
+        for (int st = 0; st < P::nst; ++st) {
+            const int Ns = P::prefix(st), R = P::radix(st);
+            cx<T> *blk = out + base + pfc::stage_blocks_off<P>(st);
+            for (int jj = 0; jj < Ns; ++jj)
+                for (int r = 0; r < R; ++r) blk[jj * R + r] = unit_root<T>((int64_t)jj * r, (int64_t)Ns * R);
+        }
+    };
+    blocks(typename MT::F{}, 0);
+    blocks(typename MT::Rv{}, pfc::stage_blocks_off<typename MT::F>(MT::F::nst));
+    for (int k = 0; k < L; ++k) out[MT::split + k] = unit_root<T>(k, 2 * (int64_t)L);
+}
+// calls f(std::integral_constant<int, L>) for a supported non-power-of-two length
+template <class F>
+bool with_mixed_length(int64_t L, F &&f)
+{
+    switch (L) {
+#define PFC_MIXCASE(LL)                                                                                    \
+    case LL: f(std::integral_constant<int, LL>{}); return true;
+        PFC_MIXCASE(6) PFC_MIXCASE(10) PFC_MIXCASE(12) PFC_MIXCASE(14) PFC_MIXCASE(15) PFC_MIXCASE(20)
+        PFC_MIXCASE(30) PFC_MIXCASE(60) PFC_MIXCASE(150) PFC_MIXCASE(375) PFC_MIXCASE(750)
+#undef PFC_MIXCASE
+    default: return false;
+    }
+}
+size_t mix_table_entries(int64_t L)
+{
+    size_t n = 0;
+    with_mixed_length(L, [&](auto lc) { n = (size_t)pfc::MixTable<decltype(lc)::value>::size; });
+    return (n + 1) & ~size_t(1);  // keep the next table 16-byte aligned
 }
 
 // Grids whose state exceeds this use non-temporal loads and stores in the step and FFT passes:
@@ -656,6 +707,7 @@ pfc_status batch_state_init_impl(pfc_batch *b, hipStream_t s)
         g.xrows = in.n0;
         g.lt_shift = b->lt_shift;
         g.nt = false;
+        g.tw_x = g.tw_y = g.tw_last = 0;
         cx<T> *scratch = (cx<T> *)(b->ws + b->scratch_off[i]);
         PFC_TRY(pfc::launch_x_r2c<T>(g, (const T *)b->psi[i], scratch, false, tw, s), "x_r2c launch");
         PFC_TRY(pfc::launch_last_fwd<T>(g, scratch, (cx<T> *)b->state[i], tw, s), "last-axis launch");
@@ -770,8 +822,23 @@ pfc_status pfc_plan_create(pfc_plan **out, const pfc_plan_desc *d)
     const size_t cs = cx_size(p);
     p->n_partials = (size_t)std::max<int64_t>(2 * pfc::kReduceBlocks, g.xrows);
     g.nt = state_bytes(p) >= kNonTemporalBytes;
+    // after the power-of-two tables: one own table per distinct non-power-of-two pass length
+    size_t tw_entries = twiddle_count(Lt);
+    std::vector<std::pair<int64_t, int64_t>> mixed;  // (length, entry offset)
+    auto table_of = [&](int64_t L) -> int64_t {
+        if (!pfc::mixed_length(L)) return 0;
+        for (auto &m : mixed)
+            if (m.first == L) return m.second;
+        mixed.emplace_back(L, (int64_t)tw_entries);
+        tw_entries += mix_table_entries(L);
+        return mixed.back().second;
+    };
+    g.tw_x = table_of(g.M);
+    g.tw_y = (d->ndim == 3) ? table_of(g.n1) : 0;
+    g.tw_last = table_of(g.n0);
+    p->tw_entries = tw_entries;
     p->tw_off = 0;
-    p->partial_off = align256(twiddle_count(Lt) * cs);
+    p->partial_off = align256(tw_entries * cs);
     p->watch_off = p->partial_off + align256(p->n_partials * sizeof(double));
     p->scratch_off = p->watch_off + 256;
     p->ws_need = p->scratch_off + align256(state_bytes(p));
@@ -792,13 +859,21 @@ pfc_status pfc_plan_set_workspace(pfc_plan *p, void *dev_ptr, size_t bytes)
     if (bytes < p->ws_need) return fail(PFC_ERR_WORKSPACE, "workspace has %zu bytes, needs %zu", bytes, p->ws_need);
     const int64_t Lt = int64_t(1) << p->g.lt_shift;
     std::vector<char> host;
-    if (p->d.dtype == PFC_F64) {
-        const std::vector<cx<double>> tw = twiddle_table<double>(Lt);
+    auto build = [&](auto tc) {
+        using T = decltype(tc);
+        std::vector<cx<T>> tw = twiddle_table<T>(Lt);
+        tw.resize(p->tw_entries);
+        const int64_t lens[3] = {p->g.M, p->d.ndim == 3 ? p->g.n1 : 0, p->g.n0};
+        const int64_t offs[3] = {p->g.tw_x, p->g.tw_y, p->g.tw_last};
+        for (int i = 0; i < 3; ++i)
+            if (offs[i] > 0)
+                with_mixed_length(lens[i], [&](auto lc) { fill_mix_table<T, decltype(lc)::value>(tw.data() + offs[i]); });
         host.assign((const char *)tw.data(), (const char *)(tw.data() + tw.size()));
-    } else {
-        const std::vector<cx<float>> tw = twiddle_table<float>(Lt);
-        host.assign((const char *)tw.data(), (const char *)(tw.data() + tw.size()));
-    }
+    };
+    if (p->d.dtype == PFC_F64)
+        build(double{});
+    else
+        build(float{});
     DeviceGuard dg(p->d.device);
     if (dg.err != hipSuccess) return hip_fail(dg.err, "hipSetDevice");
     hipError_t e = hipMemcpy((char *)dev_ptr + p->tw_off, host.data(), host.size(), hipMemcpyHostToDevice);
