@@ -114,17 +114,17 @@ def bench_batched(nsteps):
             "separate_launches_steps_per_s": round(1000.0 / ms_sep, 1)}
 
 
-def bench_big(nsteps):
-    """3D one-mode PFC at 2048^3 FP32 (r = -0.30, dt = 0.5, psi0 seed 3): steps/s and per-pass GB/s."""
+def bench_big(nsteps, n=2048, seed=3):
+    """3D one-mode PFC at n^3 FP32 (r = -0.30, dt = 0.5): steps/s and per-pass GB/s.  n = 2048: the
+    full single-GPU size; n = 750: the paper's smaller 3D grid (mixed radix, 750 = 2 3 5^3)."""
     import torch
 
     import paper_2603_26818_amd as pfc
     import pfc_inputs
 
-    n = 2048
     shape = (n, n, n)
     plan = pfc.Plan(shape, dtype="f32", r=R, dt=DT)
-    psi = pfc_inputs.pfc_initial_field_torch(3, shape, R, torch.float32, "cuda:0")
+    psi = pfc_inputs.pfc_initial_field_torch(seed, shape, R, torch.float32, "cuda:0")
     state = plan.state_init(psi)
     plan.step(psi, state, 2)
     stream = torch.cuda.current_stream()
@@ -143,7 +143,7 @@ def bench_big(nsteps):
                "frac": round(b / (t / 3) / 1e6 / PEAK_HBM_GBPS, 4)} for k, t, b in zip(PASS_NAMES, pass_ms, alg)]
     del psi, state, plan
     torch.cuda.empty_cache()
-    return {"workload": "3D one-mode PFC 2048^3 FP32, r=-0.30, dt=0.5, psi0 seed 3", "steps": nsteps,
+    return {"workload": f"3D one-mode PFC {n}^3 FP32, r=-0.30, dt=0.5, psi0 seed {seed}", "steps": nsteps,
             "ms_per_step": round(ms, 3), "steps_per_s": round(1000.0 / ms, 2),
             "alg_gbps": round(12 * Rb / ms / 1e6, 1), "frac": round(12 * Rb / ms / 1e6 / PEAK_HBM_GBPS, 4),
             "passes": passes, "energy_finite": all(math.isfinite(v) for v in F)}
@@ -277,6 +277,8 @@ def main():
     ap.add_argument("--batch-steps", type=int, default=500, help="steps of the batched form (0: skip)")
     ap.add_argument("--adjoint-steps", type=int, default=2000, help="steps of the adjoint form (0: skip)")
     ap.add_argument("--big-steps", type=int, default=50, help="timed steps at 2048^3 (0: skip)")
+    ap.add_argument("--paper-steps", type=int, default=20,
+                    help="timed steps at 750^3 and 1400^3, the paper's 3D grids (0: skip)")
     ap.add_argument("--counters", type=int, default=0, metavar="STEPS",
                     help="run only the workload of the rocprofv3 --pmc runs (copy calibration + STEPS steps)")
     ap.add_argument("--write-traffic", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
@@ -382,6 +384,13 @@ def main():
         log(f"[bench] 2048^3 FP32: {args.big_steps} steps")
         big = bench_big(args.big_steps)
         log(f"[bench] 2048^3: {big['steps_per_s']} steps/s ({big['frac']:.3f} of peak)")
+    paper = None
+    if args.paper_steps > 0:
+        paper = {}
+        for n, seed in ((750, 7), (1400, 8)):
+            log(f"[bench] {n}^3 FP32 (mixed radix): {args.paper_steps} steps")
+            paper[str(n)] = bench_big(args.paper_steps, n=n, seed=seed)
+            log(f"[bench] {n}^3: {paper[str(n)]['steps_per_s']} steps/s ({paper[str(n)]['frac']:.3f} of peak)")
     batched = None
     if args.batch_steps > 0:
         log(f"[bench] batched form: 48 instances, {args.batch_steps} steps")
@@ -407,7 +416,7 @@ def main():
         cpu = {"value": round(args.cpu_steps / dt_cpu, 4), "unit": "steps/s", "cores": oracle.num_threads(),
                "kind": "oracle",
                "sample": f"{args.cpu_steps} steps of the 512^3 workload by the FP64 C oracle "
-                         f"(recursive radix-2 FFT, OpenMP), {dt_cpu:.1f} s"}
+                         f"(recursive Cooley-Tukey FFT, radix 2 at this size, OpenMP), {dt_cpu:.1f} s"}
         log(f"[bench] CPU oracle {cpu['value']} steps/s on {cpu['cores']} threads")
 
     out = {
@@ -417,6 +426,7 @@ def main():
         "config": {"workload": "3D one-mode PFC step, 512^3 periodic grid, FP32, dx=pi/4, r=-0.30, dt=0.5, "
                                "psi0=-0.30+U(-0.1,0.1) SplitMix64 seed 23", "grid": list(shape)},
         "roofline": roofline, "cpu_baseline": cpu, "fft": fft, "passes": passes, "big_2048": big,
+        "paper_grids": paper,
         "batched": batched, "adjoint": adjoint,
         "step_alg_gbps": round(step_bytes / ms_per_step / 1e6, 1),
         "step_frac": round(step_bytes / ms_per_step / 1e6 / PEAK_HBM_GBPS, 4),

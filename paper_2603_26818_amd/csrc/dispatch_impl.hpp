@@ -31,7 +31,9 @@ static hipError_t by_length(int64_t L, F &&f)
     case 60: return f(std::integral_constant<int, 60>{});
     case 150: return f(std::integral_constant<int, 150>{});
     case 375: return f(std::integral_constant<int, 375>{});
+    case 700: return f(std::integral_constant<int, 700>{});
     case 750: return f(std::integral_constant<int, 750>{});
+    case 1400: return f(std::integral_constant<int, 1400>{});
     default: return hipErrorInvalidValue;
     }
 }

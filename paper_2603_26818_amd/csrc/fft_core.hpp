@@ -1,7 +1,7 @@
 // fft_core.hpp -- device building blocks of the pencil FFTs (gfx950, wave64).
 //
 // A length-L complex FFT of one "pencil" is done by Tp = L / Rmax threads with a Stockham
-// autosort schedule: stage s has radix R_s; each thread runs Rmax / R_s radix-R_s butterflies from
+// autosort schedule: stage s has radix R_s; each thread runs up to nb(R_s) radix-R_s butterflies from
 // registers, and the stages exchange data through LDS.  The first stage reads its inputs straight
 // from the caller (global memory, coalesced) and the last stage leaves its outputs in registers in
 // natural order, so an FFT costs (stages - 1) LDS round trips and no extra HBM traffic.
@@ -239,21 +239,29 @@ __device__ __forceinline__ void dft(cx<T> *v)
     }
 }
 
-// Radix schedule of a length-L FFT: up to three stages.  Each thread holds Rmax = lcm of the
-// radices elements (the largest radix for powers of two), i.e. Rmax / R butterflies of every stage.
-template <int A, int B = 1, int C = 1>
+// Radix schedule of a length-L FFT: up to three stages, Tp threads per pencil.  Stage s has L / R_s
+// butterflies; thread t runs butterflies j = t + b Tp, b < nb(R_s) = ceil(L / R_s / Tp), those with
+// j < L / R_s ("ragged" stages when Tp does not divide L / R_s).  TP = 0: Tp = L / lcm of the
+// radices, so that every stage divides evenly (the largest radix for powers of two).  Rmax: the
+// elements a thread holds, max over stages of nb(R) R.
+template <int A, int B = 1, int C = 1, int TP = 0>
 struct Radices {
     static constexpr int nst = (B == 1) ? 1 : (C == 1 ? 2 : 3);
     static constexpr int L = A * B * C;
-    static constexpr int Rmax = lcmc(lcmc(A, B), C);
-    static constexpr int Tp = L / Rmax;  // threads per pencil
+    static constexpr int Tp = TP > 0 ? TP : L / lcmc(lcmc(A, B), C);  // threads per pencil
+    __host__ __device__ static constexpr int nb(int R) { return (L / R + Tp - 1) / Tp; }
+    __host__ __device__ static constexpr bool even(int R) { return (L / R) % Tp == 0; }
+    // butterfly j of a radix-R stage exists
+    __host__ __device__ static constexpr bool jok(int j, int R) { return even(R) || j < L / R; }
+    static constexpr int Rmax = (nb(A) * A > nb(B) * B ? (nb(A) * A > nb(C) * C ? nb(A) * A : nb(C) * C)
+                                                       : (nb(B) * B > nb(C) * C ? nb(B) * B : nb(C) * C));
     __host__ __device__ static constexpr int radix(int s) { return s == 0 ? A : s == 1 ? B : C; }
     __host__ __device__ static constexpr int prefix(int s) { return s == 0 ? 1 : s == 1 ? A : A * B; }
     static constexpr int first = A;
     static constexpr int last = (nst == 1) ? A : (nst == 2 ? B : C);
     // the same stages in reverse order: its first radix is this schedule's last
-    using Reverse = std::conditional_t<nst == 1, Radices<A>,
-                                       std::conditional_t<nst == 2, Radices<B, A>, Radices<C, B, A>>>;
+    using Reverse = std::conditional_t<nst == 1, Radices<A, 1, 1, TP>,
+                                       std::conditional_t<nst == 2, Radices<B, A, 1, TP>, Radices<C, B, A, TP>>>;
 };
 
 // Offset of stage s in a table of per-stage blocks (prefix(s) * radix(s) entries each).
@@ -278,9 +286,12 @@ __host__ __device__ constexpr bool same_stages()
 // workgroup of several pencils stays within the register and LDS budget of two workgroups per CU.
 template <class PL, int E>
 struct Spread : PL {
-    static_assert(E % PL::Rmax == 0 && E <= PL::L, "E must be a multiple of the largest radix");
+    static_assert(E % PL::Rmax == 0 && E <= PL::L && PL::even(PL::first), "E must be a multiple of every radix");
     static constexpr int Rmax = E;
     static constexpr int Tp = PL::L / E;
+    __host__ __device__ static constexpr int nb(int R) { return E / R; }
+    __host__ __device__ static constexpr bool even(int) { return true; }
+    __host__ __device__ static constexpr bool jok(int, int) { return true; }
     using Reverse = Spread<typename PL::Reverse, E>;
 };
 
@@ -309,6 +320,9 @@ template <> struct DefaultPlan<60> { using type = Radices<10, 6>; };
 template <> struct DefaultPlan<150> { using type = Radices<10, 15>; };
 template <> struct DefaultPlan<375> { using type = Radices<15, 5, 5>; };
 template <> struct DefaultPlan<750> { using type = Radices<10, 15, 5>; };
+// 700 = 7 10 10 and 1400 = 14 10 10 have lcm 70: 50 threads per pencil with ragged stages instead
+template <> struct DefaultPlan<700> { using type = Radices<7, 10, 10, 50>; };
+template <> struct DefaultPlan<1400> { using type = Radices<14, 10, 10, 50>; };
 // the schedule whose twiddle table a non-power-of-two length carries
 template <int L>
 struct MixPlan {
@@ -428,8 +442,9 @@ __device__ __forceinline__ void apply_twiddles(cx<T> *v, int jj, const cx<T> *__
 }
 
 // Runs every stage of the schedule PL for one pencil.
-// On entry: v[b * R0 + r] = x[t + b Tp + r L / R0] for b < Rmax / R0 (R0 = first radix).
-// On exit:  v[b * Rl + r] = X[t + b Tp + r L / Rl] for b < Rmax / Rl (Rl = last radix).
+// On entry: v[b * R0 + r] = x[t + b Tp + r L / R0] for b < nb(R0) (R0 = first radix), where that
+// butterfly exists (jok).  On exit: v[b * Rl + r] = X[t + b Tp + r L / Rl] for b < nb(Rl) likewise
+// (Rl = last radix).
 // `lds(e)` returns a reference to this pencil's LDS slot for element e.  Contains workgroup
 // barriers, so every thread of the workgroup must call it (idle threads included).  The first LDS
 // write is preceded by a barrier, so the caller may have used the same LDS just before.
@@ -446,14 +461,14 @@ __device__ __forceinline__ void fft_stages(cx<T> *v, int t, Lds &&lds, const cx<
     static_for<0, PL::nst>([&](auto sc) {
         constexpr int s = decltype(sc)::value;
         constexpr int R = PL::radix(s);
-        constexpr int B = PL::Rmax / R;
+        constexpr int B = PL::nb(R);
         constexpr int Ns = PL::prefix(s);
 #pragma unroll
-        for (int b = 0; b < B; ++b) dft<T, R, DIR>(&v[b * R]);
+        for (int b = 0; b < B; ++b) dft<T, R, DIR>(&v[b * R]);  // (absent butterflies: unused values)
         if constexpr (s + 1 < PL::nst) {
             // exchange, then the next stage's inputs and twiddles
             constexpr int R2 = PL::radix(s + 1);
-            constexpr int B2 = PL::Rmax / R2;
+            constexpr int B2 = PL::nb(R2);
             constexpr unsigned Ns2 = PL::prefix(s + 1);
 #pragma unroll
             for (int gg = 0; gg < G; ++gg) {
@@ -464,8 +479,10 @@ __device__ __forceinline__ void fft_stages(cx<T> *v, int t, Lds &&lds, const cx<
                     for (int b = 0; b < B; ++b) {
                         const unsigned j = t + b * Tp;
                         const int base = (int)((j / Ns) * Ns * R + j % Ns);
+                        if (PL::jok(j, R)) {
 #pragma unroll
-                        for (int r = 0; r < R; ++r) lds(base + r * Ns) = v[b * R + r];
+                            for (int r = 0; r < R; ++r) lds(base + r * Ns) = v[b * R + r];
+                        }
                     }
                 }
                 __syncthreads();
@@ -473,8 +490,10 @@ __device__ __forceinline__ void fft_stages(cx<T> *v, int t, Lds &&lds, const cx<
 #pragma unroll
                     for (int b = 0; b < B2; ++b) {
                         const int j = t + b * Tp;
+                        if (PL::jok(j, R2)) {
 #pragma unroll
-                        for (int r = 0; r < R2; ++r) v[b * R2 + r] = lds(j + r * (L / R2));
+                            for (int r = 0; r < R2; ++r) v[b * R2 + r] = lds(j + r * (L / R2));
+                        }
                     }
                 }
             }

@@ -143,7 +143,8 @@ __device__ __forceinline__ void x_r2c_block(const T *__restrict__ in, cx<T> *__r
     const cx<T> *src = reinterpret_cast<const cx<T> *>(in) + (valid ? row : 0) * M;
     cx<T> v[Rmax];
 #pragma unroll
-    for (int b = 0; b < Rmax / R0; ++b)
+    for (int b = 0; b < PL::nb(R0); ++b)
+        if (PL::jok(t + b * Tp, R0))
 #pragma unroll
         for (int r = 0; r < R0; ++r) {
             cx<T> z = valid ? ld_grid<NT>(&src[t + b * Tp + r * (M / R0)]) : cx<T>{T(0), T(0)};
@@ -154,14 +155,16 @@ __device__ __forceinline__ void x_r2c_block(const T *__restrict__ in, cx<T> *__r
     fft_stages<T, PL, -1, TW_LT>(v, t, lds, tw, lt_shift);  // measured faster here than TW_STAGE
     __syncthreads();
 #pragma unroll
-    for (int b = 0; b < Rmax / Rl; ++b)
+    for (int b = 0; b < PL::nb(Rl); ++b)
+        if (PL::jok(t + b * Tp, Rl))
 #pragma unroll
         for (int r = 0; r < Rl; ++r) lds(t + b * Tp + r * (M / Rl)) = v[b * Rl + r];
     __syncthreads();
     cx<T> *dst = out + (valid ? row : 0) * M;
     const T h = T(0.5);
 #pragma unroll
-    for (int b = 0; b < Rmax / Rl; ++b)
+    for (int b = 0; b < PL::nb(Rl); ++b)
+        if (PL::jok(t + b * Tp, Rl))
 #pragma unroll
         for (int r = 0; r < Rl; ++r) {
             const int k = t + b * Tp + r * (M / Rl);
@@ -219,7 +222,8 @@ __device__ __forceinline__ void x_c2r_row(cx<T> *v, const cx<T> *src, bool valid
     cx<T> mir[PG ? Rmax : 1];
     if constexpr (PG) {
 #pragma unroll
-        for (int b = 0; b < Rmax / R0; ++b)
+        for (int b = 0; b < PL::nb(R0); ++b)
+            if (PL::jok(t + b * Tp, R0))
 #pragma unroll
             for (int r = 0; r < R0; ++r) {
                 const int k = t + b * Tp + r * (M / R0);
@@ -229,7 +233,8 @@ __device__ __forceinline__ void x_c2r_row(cx<T> *v, const cx<T> *src, bool valid
     } else {
         __syncthreads();
 #pragma unroll
-        for (int b = 0; b < Rmax / R0; ++b)
+        for (int b = 0; b < PL::nb(R0); ++b)
+            if (PL::jok(t + b * Tp, R0))
 #pragma unroll
             for (int r = 0; r < R0; ++r) {
                 const int k = t + b * Tp + r * (M / R0);
@@ -240,7 +245,8 @@ __device__ __forceinline__ void x_c2r_row(cx<T> *v, const cx<T> *src, bool valid
     }
     const T h = T(0.5);
 #pragma unroll
-    for (int b = 0; b < Rmax / R0; ++b)
+    for (int b = 0; b < PL::nb(R0); ++b)
+        if (PL::jok(t + b * Tp, R0))
 #pragma unroll
         for (int r = 0; r < R0; ++r) {
             const int k = t + b * Tp + r * (M / R0);
@@ -279,7 +285,8 @@ __device__ __forceinline__ void x_c2r_block(const cx<T> *in, T *out, int64_t nro
     if constexpr (EPI == EPI_PLAIN) {
         if (valid) {
 #pragma unroll
-            for (int b = 0; b < Rmax / Rl; ++b)
+            for (int b = 0; b < PL::nb(Rl); ++b)
+                if (PL::jok(t + b * Tp, Rl))
 #pragma unroll
                 for (int r = 0; r < Rl; ++r)
                     st_grid<NT>(&dst[t + b * Tp + r * (M / Rl)], scale(v[b * Rl + r], sc));
@@ -293,7 +300,8 @@ __device__ __forceinline__ void x_c2r_block(const cx<T> *in, T *out, int64_t nro
         double acc = 0.0;
         if (valid) {
 #pragma unroll
-            for (int b = 0; b < Rmax / Rl; ++b)
+            for (int b = 0; b < PL::nb(Rl); ++b)
+                if (PL::jok(t + b * Tp, Rl))
 #pragma unroll
                 for (int r = 0; r < Rl; ++r) {
                     const int m = t + b * Tp + r * (M / Rl);
@@ -346,6 +354,16 @@ struct PencilTile<float, 1024> {
     static constexpr bool PF = false;
 };
 template <>
+struct PencilTile<float, 1400> {  // 16 pencils of 1400 (800 threads) in two LDS groups (88 KB)
+    static constexpr int W = 16, E = 0, G = 2;
+    static constexpr bool PF = false;
+};
+template <>
+struct PencilTile<double, 1400> {  // 8 pencils (128-byte tiles) in two LDS groups (88 KB)
+    static constexpr int W = 8, E = 0, G = 2;
+    static constexpr bool PF = false;
+};
+template <>
 struct PencilTile<float, 2048> {
     static constexpr int W = 16, E = 32, G = 2;  // whole 128-byte lines; 1024 threads, 128 KB
     static constexpr bool PF = false;
@@ -387,7 +405,8 @@ __device__ __forceinline__ void axis_c2c_block(const cx<T> *src, cx<T> *dst, int
     const int64_t base = batch * bstride + (valid ? col : 0);
     cx<T> v[Rmax];
 #pragma unroll
-    for (int b = 0; b < Rmax / R0; ++b)
+    for (int b = 0; b < PL::nb(R0); ++b)
+        if (PL::jok(t + b * Tp, R0))
 #pragma unroll
         for (int r = 0; r < R0; ++r)
             v[b * R0 + r] = valid ? ld_grid<NT>(&src[base + (int64_t)(t + b * Tp + r * (L / R0)) * estride])
@@ -397,7 +416,8 @@ __device__ __forceinline__ void axis_c2c_block(const cx<T> *src, cx<T> *dst, int
     fft_stages<T, PL, DIR, TW_STAGE, G>(v, t, lds, tw, lt_shift, p / GW);
     if (valid) {
 #pragma unroll
-        for (int b = 0; b < Rmax / Rl; ++b)
+        for (int b = 0; b < PL::nb(Rl); ++b)
+            if (PL::jok(t + b * Tp, Rl))
 #pragma unroll
             for (int r = 0; r < Rl; ++r)
                 st_grid<NT>(&dst[base + (int64_t)(t + b * Tp + r * (L / Rl)) * estride], v[b * Rl + r]);
@@ -538,7 +558,8 @@ __device__ __forceinline__ void last_axis_block(const LastAxisArgs<T> &a, int64_
             (si.partner >= 0) ? la_slot<ORD>(nrows, a.tiles_per_row, W, si.partner, bid).row : 0;
         const int64_t pitch = M + 1;
 #pragma unroll
-        for (int b = 0; b < Rmax / R0; ++b)
+        for (int b = 0; b < PL::nb(R0); ++b)
+            if (PL::jok(t + b * Tp, R0))
 #pragma unroll
             for (int r = 0; r < R0; ++r) {
                 const int e = t + b * Tp + r * (L / R0);
@@ -563,7 +584,8 @@ __device__ __forceinline__ void last_axis_block(const LastAxisArgs<T> &a, int64_
         if (valid) {
             constexpr int Rf = PR::last;
 #pragma unroll
-            for (int b = 0; b < Rmax / Rf; ++b)
+            for (int b = 0; b < PL::nb(Rf); ++b)
+                if (PL::jok(t + b * Tp, Rf))
 #pragma unroll
                 for (int r = 0; r < Rf; ++r)
                     a.dst[(int64_t)(t + b * Tp + r * (L / Rf)) * estride + coloff] = v[b * Rf + r];
@@ -589,7 +611,8 @@ __device__ __forceinline__ void last_axis_block(const LastAxisArgs<T> &a, int64_
         cx<T> spre[(MODE == LA_STEP && PF) ? Rmax : 1];
         if constexpr (MODE == LA_STEP && PF) {
 #pragma unroll
-            for (int b = 0; b < Rmax / Rl; ++b)
+            for (int b = 0; b < PL::nb(Rl); ++b)
+                if (PL::jok(t + b * Tp, Rl))
 #pragma unroll
                 for (int r = 0; r < Rl; ++r)
                     spre[b * Rl + r] = valid ? ld_grid<NT>(gp(a.state, b * Tp + r * (L / Rl))) : cx<T>{T(0), T(0)};
@@ -597,7 +620,8 @@ __device__ __forceinline__ void last_axis_block(const LastAxisArgs<T> &a, int64_
         // packed input, forward FFT
         constexpr int R0 = PL::first;
 #pragma unroll
-        for (int b = 0; b < Rmax / R0; ++b)
+        for (int b = 0; b < PL::nb(R0); ++b)
+            if (PL::jok(t + b * Tp, R0))
 #pragma unroll
             for (int r = 0; r < R0; ++r)
                 v[b * R0 + r] = valid ? ld_grid<NT>(gp(a.src, b * Tp + r * (L / R0))) : cx<T>{T(0), T(0)};
@@ -606,7 +630,8 @@ __device__ __forceinline__ void last_axis_block(const LastAxisArgs<T> &a, int64_
         auto partner_val = [&](int e) -> cx<T> { return sh[neg_mod<L>(e) * GW + si.partner % GW]; };
         auto spectrum_to_lds = [&]() {
 #pragma unroll
-            for (int b = 0; b < Rmax / Rl; ++b)
+            for (int b = 0; b < PL::nb(Rl); ++b)
+                if (PL::jok(t + b * Tp, Rl))
 #pragma unroll
                 for (int r = 0; r < Rl; ++r) lds(t + b * Tp + r * (L / Rl)) = v[b * Rl + r];
         };
@@ -622,7 +647,8 @@ __device__ __forceinline__ void last_axis_block(const LastAxisArgs<T> &a, int64_
             const int64_t pitch = M + 1;
             if (valid) {
 #pragma unroll
-                for (int b = 0; b < Rmax / Rl; ++b)
+                for (int b = 0; b < PL::nb(Rl); ++b)
+                    if (PL::jok(t + b * Tp, Rl))
 #pragma unroll
                     for (int r = 0; r < Rl; ++r) {
                         const int e = t + b * Tp + r * (L / Rl);
@@ -654,7 +680,8 @@ __device__ __forceinline__ void last_axis_block(const LastAxisArgs<T> &a, int64_
                     __syncthreads();
                     if (mine && si.partner >= 0) {
 #pragma unroll
-                        for (int b = 0; b < Rmax / Rl; ++b)
+                        for (int b = 0; b < PL::nb(Rl); ++b)
+                            if (PL::jok(t + b * Tp, Rl))
 #pragma unroll
                             for (int r = 0; r < Rl; ++r) {
                                 const int e = t + b * Tp + r * (L / Rl);
@@ -673,7 +700,8 @@ __device__ __forceinline__ void last_axis_block(const LastAxisArgs<T> &a, int64_
             }
             if (si.partner < 0) {
 #pragma unroll
-                for (int b = 0; b < Rmax / Rl; ++b)
+                for (int b = 0; b < PL::nb(Rl); ++b)
+                    if (PL::jok(t + b * Tp, Rl))
 #pragma unroll
                     for (int r = 0; r < Rl; ++r) {
                         const int e = t + b * Tp + r * (L / Rl);
@@ -699,7 +727,8 @@ __device__ __forceinline__ void last_axis_block(const LastAxisArgs<T> &a, int64_
                     __syncthreads();  // every mirror N has been read
                     if (mine && si.partner >= 0 && valid) {
 #pragma unroll
-                        for (int b = 0; b < Rmax / Rl; ++b)
+                        for (int b = 0; b < PL::nb(Rl); ++b)
+                            if (PL::jok(t + b * Tp, Rl))
 #pragma unroll
                             for (int r = 0; r < Rl; ++r) {
                                 const int e = t + b * Tp + r * (L / Rl);
@@ -712,7 +741,8 @@ __device__ __forceinline__ void last_axis_block(const LastAxisArgs<T> &a, int64_
                     __syncthreads();
                     if (mine && si.partner >= 0) {
 #pragma unroll
-                        for (int b = 0; b < Rmax / Rl; ++b)
+                        for (int b = 0; b < PL::nb(Rl); ++b)
+                            if (PL::jok(t + b * Tp, Rl))
 #pragma unroll
                             for (int r = 0; r < Rl; ++r) {
                                 const int e = t + b * Tp + r * (L / Rl);
@@ -741,14 +771,16 @@ __device__ __forceinline__ void last_axis_block(const LastAxisArgs<T> &a, int64_
             if (valid) {
                 constexpr int Rf = PR::last;
 #pragma unroll
-                for (int b = 0; b < Rmax / Rf; ++b)
+                for (int b = 0; b < PL::nb(Rf); ++b)
+                    if (PL::jok(t + b * Tp, Rf))
 #pragma unroll
                     for (int r = 0; r < Rf; ++r) st_grid<NT>(gp(a.dst, b * Tp + r * (L / Rf)), v[b * Rf + r]);
             }
         } else if constexpr (MODE == LA_ADJOINT) {
             cx<T> w[Rmax];
 #pragma unroll
-            for (int b = 0; b < Rmax / Rl; ++b)
+            for (int b = 0; b < PL::nb(Rl); ++b)
+                if (PL::jok(t + b * Tp, Rl))
 #pragma unroll
                 for (int r = 0; r < Rl; ++r) {
                     const int e = t + b * Tp + r * (L / Rl);
@@ -778,7 +810,8 @@ __device__ __forceinline__ void last_axis_block(const LastAxisArgs<T> &a, int64_
             fft_stages<T, PR, +1>(v, t, lds, a.tw, a.lt_shift);
             if (valid) {
 #pragma unroll
-                for (int b = 0; b < Rmax / Rf; ++b)
+                for (int b = 0; b < PL::nb(Rf); ++b)
+                    if (PL::jok(t + b * Tp, Rf))
 #pragma unroll
                     for (int r = 0; r < Rf; ++r)
                         a.dst[(int64_t)(t + b * Tp + r * (L / Rf)) * estride + coloff] = v[b * Rf + r];
@@ -786,7 +819,8 @@ __device__ __forceinline__ void last_axis_block(const LastAxisArgs<T> &a, int64_
             fft_stages<T, PR, +1>(w, t, lds, a.tw, a.lt_shift);
             if (valid) {
 #pragma unroll
-                for (int b = 0; b < Rmax / Rf; ++b)
+                for (int b = 0; b < PL::nb(Rf); ++b)
+                    if (PL::jok(t + b * Tp, Rf))
 #pragma unroll
                     for (int r = 0; r < Rf; ++r)
                         a.dst2[(int64_t)(t + b * Tp + r * (L / Rf)) * estride + coloff] = w[b * Rf + r];
@@ -835,14 +869,16 @@ __global__ __launch_bounds__(C *PL::Tp) void r2c_natural_chunk_kernel(const cx<T
     {
         const cx<T> *col = src + row * M + (fold ? 0 : kx);
 #pragma unroll
-        for (int b = 0; b < Rmax / R0; ++b)
+        for (int b = 0; b < PL::nb(R0); ++b)
+            if (PL::jok(t + b * Tp, R0))
 #pragma unroll
             for (int r = 0; r < R0; ++r) v[b * R0 + r] = col[(int64_t)(t + b * Tp + r * (L / R0)) * estride];
     }
     fft_stages<T, PL, -1, TW_STAGE, G>(v, t, lds, tw, lt_shift, grp);
     if (!fold) {
 #pragma unroll
-        for (int b = 0; b < Rmax / Rl; ++b)
+        for (int b = 0; b < PL::nb(Rl); ++b)
+            if (PL::jok(t + b * Tp, Rl))
 #pragma unroll
             for (int r = 0; r < Rl; ++r) dst[(int64_t)(t + b * Tp + r * (L / Rl)) * plane + f] = v[b * Rl + r];
     }
@@ -855,7 +891,8 @@ __global__ __launch_bounds__(C *PL::Tp) void r2c_natural_chunk_kernel(const cx<T
         const int64_t mrow = (nrows - row) % nrows;
         const cx<T> *col = src + mrow * M;
 #pragma unroll
-        for (int b = 0; b < Rmax / R0; ++b)
+        for (int b = 0; b < PL::nb(R0); ++b)
+            if (PL::jok(t + b * Tp, R0))
 #pragma unroll
             for (int r = 0; r < R0; ++r)
                 v[b * R0 + r] = fold ? col[(int64_t)(t + b * Tp + r * (L / R0)) * estride] : cx<T>{T(0), T(0)};
@@ -868,14 +905,16 @@ __global__ __launch_bounds__(C *PL::Tp) void r2c_natural_chunk_kernel(const cx<T
         __syncthreads();
         if (mine) {
 #pragma unroll
-            for (int b = 0; b < Rmax / Rl; ++b)
+            for (int b = 0; b < PL::nb(Rl); ++b)
+                if (PL::jok(t + b * Tp, Rl))
 #pragma unroll
                 for (int r = 0; r < Rl; ++r) lds(t + b * Tp + r * (L / Rl)) = v[b * Rl + r];
         }
         __syncthreads();
         if (mine && fold) {
 #pragma unroll
-            for (int b = 0; b < Rmax / Rl; ++b)
+            for (int b = 0; b < PL::nb(Rl); ++b)
+                if (PL::jok(t + b * Tp, Rl))
 #pragma unroll
                 for (int r = 0; r < Rl; ++r) {
                     const int e = t + b * Tp + r * (L / Rl);

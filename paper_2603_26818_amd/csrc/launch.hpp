@@ -25,7 +25,7 @@ struct Geom {
 
 // Lengths other than powers of two that have compiled schedules (factors 2, 3, 5, 7); a grid axis
 // of length n needs n here (y and last axis) or n / 2 here (x).
-constexpr int kMixedLengths[] = {6, 10, 12, 14, 15, 20, 30, 60, 150, 375, 750};
+constexpr int kMixedLengths[] = {6, 10, 12, 14, 15, 20, 30, 60, 150, 375, 700, 750, 1400};
 inline bool mixed_length(int64_t n)
 {
     for (int m : kMixedLengths)

@@ -226,7 +226,8 @@ bool with_mixed_length(int64_t L, F &&f)
 #define PFC_MIXCASE(LL)                                                                                    \
     case LL: f(std::integral_constant<int, LL>{}); return true;
         PFC_MIXCASE(6) PFC_MIXCASE(10) PFC_MIXCASE(12) PFC_MIXCASE(14) PFC_MIXCASE(15) PFC_MIXCASE(20)
-        PFC_MIXCASE(30) PFC_MIXCASE(60) PFC_MIXCASE(150) PFC_MIXCASE(375) PFC_MIXCASE(750)
+        PFC_MIXCASE(30) PFC_MIXCASE(60) PFC_MIXCASE(150) PFC_MIXCASE(375) PFC_MIXCASE(700) PFC_MIXCASE(750)
+        PFC_MIXCASE(1400)
 #undef PFC_MIXCASE
     default: return false;
     }

@@ -66,7 +66,7 @@ def test_struct_layout_matches_c():
 
 
 @pytest.mark.parametrize("shape,dtype", [((64, 64), 0), ((8, 16, 32), 1), ((2048, 2048, 2048), 0), ((4, 4), 1),
-                                         ((750, 750, 750), 0), ((30, 20, 12), 1), ((20, 750), 0)])
+                                         ((750, 750, 750), 0), ((30, 20, 12), 1), ((20, 750), 0), ((1400, 1400, 1400), 0)])
 def test_plan_create_and_sizes(shape, dtype):
     b, lib = _lib()
     st, h = _create(b, lib, _desc(b, shape, dtype))
@@ -82,7 +82,7 @@ def test_plan_create_and_sizes(shape, dtype):
 
 
 @pytest.mark.parametrize("shape,code", [((64,), 2), ((4, 4, 4, 4), 2), ((48, 64), 2), ((64, 4096), 2), ((2, 64), 2),
-                                        ((18, 64), 2), ((6, 22), 2), ((16, 15), 2), ((1400, 8), 2)])
+                                        ((18, 64), 2), ((6, 22), 2), ((16, 15), 2), ((1050, 8), 2)])
 def test_plan_rejects_unsupported_shapes(shape, code):
     b, lib = _lib()
     d = _desc(b, shape[:3])

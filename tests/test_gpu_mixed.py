@@ -1,8 +1,8 @@
 """Grids whose lengths have factors 3, 5 and 7 (the paper's grids 750^3 and 1400^3 are of this
 kind: 750 = 2 3 5^3).  GPU transforms and PFC steps against the FP64 oracle, whose mixed-radix
 recursion is pinned in test_oracle_pins.py.  Shapes cover every compiled non-power-of-two length on
-each pass kind (x half-lengths 6, 10, 14, 15, 375; y and last-axis lengths 6, 10, 12, 14, 20, 30,
-60, 150, 750), partial column tiles (M = 375 is not a multiple of the 16-column tile), 2D and 3D,
+each pass kind (x half-lengths 6, 10, 14, 15, 375, 700; y and last-axis lengths 6, 10, 12, 14, 20,
+30, 60, 150, 700, 750, 1400), partial column tiles (M = 375 is not a multiple of the 16-column tile), 2D and 3D,
 FP32 and FP64; then one step at 750^3, the paper's smaller 3D grid."""
 import numpy as np
 import pytest
@@ -14,7 +14,10 @@ from gpu_common import TOL_FFT, TOL_STEP, relerr, rounded, say, to_dev, to_np
 pytestmark = pytest.mark.gpu
 
 FFT_SHAPES = [(30, 20, 12), (14, 10, 28), (750, 6, 20), (10, 750, 12), (6, 10, 750), (150, 60, 30), (12, 14, 20),
-              (750, 20), (20, 750), (60, 300), (30, 28)]
+              (750, 20), (20, 750), (60, 300), (30, 28),
+              # 1400 and 700: 50 threads per pencil, stages of 14, 10, 10 (or 7, 10, 10) butterflies
+              # that do not divide evenly among the threads
+              (1400, 6, 20), (10, 1400, 12), (6, 10, 1400), (700, 12, 20), (1400, 20), (20, 1400)]
 STEP_CASES = [
     # (shape, dtype, nsteps, seed)
     ((30, 20, 12), "f64", 40, 41),
@@ -28,6 +31,12 @@ STEP_CASES = [
     ((750, 20), "f64", 40, 47),
     ((20, 750), "f32", 40, 48),
     ((60, 300), "f64", 40, 49),
+    ((1400, 6, 20), "f64", 20, 54),
+    ((1400, 6, 20), "f32", 20, 54),
+    ((6, 10, 1400), "f64", 20, 55),
+    ((10, 1400, 12), "f32", 20, 56),
+    ((20, 1400), "f64", 30, 57),
+    ((1400, 20), "f32", 30, 58),
 ]
 
 
