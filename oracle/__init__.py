@@ -46,11 +46,16 @@ def _load():
     lib.or_energy.argtypes = [pp, dp, dp, dp]
     lib.or_step_backward.argtypes = [pp, dp, dp, dp, dp, dp]
     lib.or_num_threads.argtypes = []
+    lib.or_hydro_step.argtypes = [pp, ctypes.POINTER(_OrHydro), dp, dp, dp, dp, ctypes.c_int64]
     for f in ("or_fft_c2c", "or_rfftn", "or_irfftn", "or_state_init", "or_step", "or_energy",
-              "or_step_backward", "or_num_threads"):
+              "or_step_backward", "or_num_threads", "or_hydro_step"):
         getattr(lib, f).restype = ctypes.c_int
     _lib = lib
     return lib
+
+
+class _OrHydro(ctypes.Structure):
+    _fields_ = [("rho0", ctypes.c_double), ("gamma", ctypes.c_double), ("a0", ctypes.c_double)]
 
 
 class _OrParams(ctypes.Structure):
@@ -199,3 +204,32 @@ def loss_and_grad(p: Params, psi0: np.ndarray, target: np.ndarray, nsteps: int):
 
 def num_threads() -> int:
     return int(_load().or_num_threads())
+
+
+@dataclass
+class Hydro:
+    """Hydrodynamic PFC parameters (multiphysics section, Eq. (5)-(6)): mass density rho0,
+    viscosity gamma, Gaussian averaging width a0."""
+
+    rho0: float = 1.0
+    gamma: float = 1.0
+    a0: float = 1.0
+
+    def c(self) -> _OrHydro:
+        return _OrHydro(float(self.rho0), float(self.gamma), float(self.a0))
+
+
+def hydro_step(p: Params, h: Hydro, psi: np.ndarray, psi_state: np.ndarray, v: np.ndarray, v_state: np.ndarray,
+               nsteps: int):
+    """nsteps hydrodynamic PFC steps.  v: [ndim, *shape] velocity components (axis order as the
+    grid: component j is the velocity along axis j); v_state: their half spectra.  Returns new
+    (psi, psi_state, v, v_state)."""
+    psi = np.ascontiguousarray(psi, dtype=np.float64).copy()
+    S = np.ascontiguousarray(psi_state, dtype=np.complex128).copy()
+    v = np.ascontiguousarray(v, dtype=np.float64).copy()
+    V = np.ascontiguousarray(v_state, dtype=np.complex128).copy()
+    assert v.shape == (len(p.shape),) + tuple(p.shape) and V.shape == (len(p.shape),) + p.half_shape
+    hc = h.c()
+    _check(_load().or_hydro_step(ctypes.byref(p.c()), ctypes.byref(hc), _dp(psi), _dp(S.view(np.float64)), _dp(v),
+                                 _dp(V.view(np.float64)), int(nsteps)), "hydro_step")
+    return psi, S, v, V

@@ -17,7 +17,8 @@
  *     pointwise in real space and transformed, the linear part is treated implicitly,
  *         psiF <- (psiF + dt*lap*FFT(psi^3)) / (1 - dt*lin),   lap = -q,   lin = -q (eps + L(q)),
  *     followed by the inverse transform back to real space;
- *   - the discrete adjoint (transpose of the Jacobian) of that step, used for gradients.
+ *   - the discrete adjoint (transpose of the Jacobian) of that step, used for gradients;
+ *   - the hydrodynamic PFC step of the multiphysics section (Eq. (5), (6), Listing 2).
  *
  * Readings where the paper is silent (each is listed with its reason in the design notes):
  *   - fields are real, so the spectral state is the half spectrum [n0][n1][n2/2+1]; after every
@@ -499,6 +500,121 @@ int or_step_backward(const or_params *p, const double *psi_n, const double *psi_
     free(Kh);
     free(mu);
     free(nu);
+    return e;
+}
+
+/* ---------------------------------------------------------------- hydrodynamic PFC */
+
+/* Hydrodynamic PFC (section "Multiple GPU usage for Multiphysics PFC", Eq. (5) with the local
+ * average of Eq. (6), time stepping of Listing 2).  Density psi and velocity v = (v_1 .. v_d),
+ *     d_t psi = lap(dF/dpsi) - v . grad psi,
+ *     rho0 d_t v = Gamma lap v - < psi grad(dF/dpsi) >,
+ * dF/dpsi = (r + L)psi + psi^3, <.> a Gaussian average of width a0, in Fourier space the factor
+ * G(q) = exp(-a0^2 q / 2).  One step, in the order of Listing 2 (psi first; the velocity update
+ * then uses the new psi):
+ *     psiF <- (psiF + dt (lap FFT(psi^3) - FFT(sum_j v_j IFFT(D_j psiF)))) / (1 - dt lin)
+ *     mu   =  FFT(psi^3) + (r + L(q)) psiF                       (the new psi)
+ *     vjF  <- (vjF - dt/rho0 G FFT(psi IFFT(D_j mu))) / (1 + dt/rho0 Gamma q)
+ * with D_j = i k_j the spectral first derivative.  Readings: k_j is taken as 0 at the Nyquist
+ * index of each axis (a first derivative of a real field has no real Nyquist component); both
+ * updates use the same dt; every spectrum is projected like the PFC state. */
+typedef struct {
+    double rho0;  /* mass density */
+    double gamma; /* viscosity Gamma */
+    double a0;    /* width of the Gaussian average (lattice spacing) */
+} or_hydro;
+
+/* wavenumber of index m with the Nyquist index mapped to 0 (first derivatives) */
+static double odd_wavenumber(int64_t m, int64_t n, double dx)
+{
+    if (2 * m == n) return 0.0;
+    return wavenumber(m, n, dx);
+}
+
+/* odd wavenumber of axis a at half-spectrum point idx */
+static double kodd_at(const or_params *p, int64_t idx, int a)
+{
+    int64_t h[3], m[3] = {0, 0, 0};
+    half_dims(p->ndim, p->n, h);
+    unflatten(idx, p->ndim, h, m);
+    return odd_wavenumber(m[a], p->n[a], p->dx[a]);
+}
+
+/* psi: real field; psi_state: its half spectrum; v: ndim real fields (component j at v + j N);
+ * v_state: ndim half spectra (component j at v_state + 2 j H doubles).  All updated in place. */
+int or_hydro_step(const or_params *p, const or_hydro *hp, double *psi, double *psi_state, double *v,
+                  double *v_state, int64_t nsteps)
+{
+    if (!check_params(p) || !hp || !(hp->rho0 > 0.0) || nsteps < 0) return OR_ERR_ARG;
+    const int ndim = p->ndim;
+    const int64_t N = total_size(ndim, p->n), H = half_size(ndim, p->n);
+    cplx *S = (cplx *)psi_state, *V = (cplx *)v_state;
+    double *cube = (double *)malloc(sizeof(double) * (size_t)N), *a = (double *)malloc(sizeof(double) * (size_t)N),
+           *tr = (double *)malloc(sizeof(double) * (size_t)N);
+    cplx *NF = (cplx *)malloc(sizeof(cplx) * (size_t)H), *th = (cplx *)malloc(sizeof(cplx) * (size_t)H),
+         *mu = (cplx *)malloc(sizeof(cplx) * (size_t)H);
+    int e = (cube && a && tr && NF && th && mu) ? OR_OK : OR_ERR_MEM;
+    const double dt = p->dt, c = p->dt / hp->rho0;
+    for (int64_t st = 0; st < nsteps && !e; ++st) {
+        /* density: cubic term and advection term, both transformed from real space */
+#pragma omp parallel for schedule(static)
+        for (int64_t i = 0; i < N; ++i) {
+            cube[i] = p->linear_only ? 0.0 : psi[i] * psi[i] * psi[i];
+            a[i] = 0.0;
+        }
+        e = rfftn_impl(ndim, p->n, cube, NF, 1);
+        for (int j = 0; j < ndim && !e; ++j) {
+#pragma omp parallel for schedule(static)
+            for (int64_t i = 0; i < H; ++i) th[i] = I * kodd_at(p, i, j) * S[i];
+            e = irfftn_impl(ndim, p->n, th, tr);
+            if (e) break;
+#pragma omp parallel for schedule(static)
+            for (int64_t i = 0; i < N; ++i) a[i] += v[j * N + i] * tr[i];
+        }
+        if (!e) e = rfftn_impl(ndim, p->n, a, th, 1);
+        if (e) break;
+#pragma omp parallel for schedule(static)
+        for (int64_t i = 0; i < H; ++i) {
+            double q = q_at(p, i);
+            double lap = -q, lin = -q * (p->r + corr_op(p, q));
+            S[i] = (S[i] + dt * (lap * NF[i] - th[i])) / (1.0 - dt * lin);
+        }
+        project_hermitian(S, ndim, p->n);
+        e = irfftn_impl(ndim, p->n, S, psi);
+        if (e) break;
+        /* velocity: mu = FFT(psi^3) + (r + L) psiF of the new psi */
+#pragma omp parallel for schedule(static)
+        for (int64_t i = 0; i < N; ++i) cube[i] = p->linear_only ? 0.0 : psi[i] * psi[i] * psi[i];
+        e = rfftn_impl(ndim, p->n, cube, mu, 1);
+        if (e) break;
+#pragma omp parallel for schedule(static)
+        for (int64_t i = 0; i < H; ++i) mu[i] += (p->r + corr_op(p, q_at(p, i))) * S[i];
+        for (int j = 0; j < ndim && !e; ++j) {
+#pragma omp parallel for schedule(static)
+            for (int64_t i = 0; i < H; ++i) th[i] = I * kodd_at(p, i, j) * mu[i];
+            e = irfftn_impl(ndim, p->n, th, tr);
+            if (e) break;
+#pragma omp parallel for schedule(static)
+            for (int64_t i = 0; i < N; ++i) tr[i] *= psi[i];
+            e = rfftn_impl(ndim, p->n, tr, th, 1);
+            if (e) break;
+            cplx *Vj = V + j * H;
+#pragma omp parallel for schedule(static)
+            for (int64_t i = 0; i < H; ++i) {
+                double q = q_at(p, i);
+                double G = exp(-0.5 * hp->a0 * hp->a0 * q);
+                Vj[i] = (Vj[i] - c * G * th[i]) / (1.0 + c * hp->gamma * q);
+            }
+            project_hermitian(Vj, ndim, p->n);
+            e = irfftn_impl(ndim, p->n, Vj, v + j * N);
+        }
+    }
+    free(cube);
+    free(a);
+    free(tr);
+    free(NF);
+    free(th);
+    free(mu);
     return e;
 }
 
