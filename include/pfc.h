@@ -160,6 +160,39 @@ pfc_status pfc_step_backward(pfc_plan *p, const void *psi_n, const void *psi_np1
  * from the k = 0 mode.  Accumulation in FP64 in both dtypes.  out_dev: 2 device doubles. */
 pfc_status pfc_energy(pfc_plan *p, const void *psi, const void *state, double *out_dev, void *stream);
 
+/* ---- Hydrodynamic PFC (section "Multiple GPU usage for Multiphysics PFC", Eq. (5), the Gaussian
+ * average of Eq. (6), the time stepping of Listing 2) ----------------------------------------------
+ * Density psi and velocity v = (v_0 .. v_{d-1}), component j along grid axis j (C order: axis 0 is
+ * the slowest), d = ndim:
+ *     d_t psi = lap(dF/dpsi) - v . grad psi,      rho0 d_t v = Gamma lap v - < psi grad(dF/dpsi) >,
+ * dF/dpsi = (r + L)psi + psi^3 (the plan's model, r and dt), <.> the Gaussian average of width a0
+ * (Fourier factor exp(-a0^2 q / 2)).  One step, psi first, then v from the new psi:
+ *     psi_hat <- (psi_hat + dt (-q FFT(psi^3) - FFT(sum_j v_j IFFT(D_j psi_hat)))) / (1 + dt q (r + L))
+ *     v_j_hat <- (v_j_hat - dt/rho0 G FFT(psi IFFT(D_j mu_hat))) / (1 + dt/rho0 Gamma q),
+ *     mu_hat = FFT(psi^3) + (r + L) psi_hat,
+ * D_j = i k_j the spectral first derivative with k_j = 0 at the Nyquist index. */
+typedef struct {
+    double rho0;  /* mass density, > 0 */
+    double gamma; /* viscosity Gamma, >= 0 */
+    double a0;    /* width of the Gaussian average (lattice spacing), >= 0 */
+} pfc_hydro_params;
+
+/* Device scratch the hydrodynamic step needs besides the plan's workspace: two native spectra and
+ * two real fields (each 256-byte aligned). */
+size_t pfc_hydro_work_bytes(const pfc_plan *p);
+
+/* States of psi and of the d velocity components (as pfc_state_init for each).  v: d real fields
+ * back to back; v_state: d native states back to back (pfc_plan_real_bytes / _state_bytes apart). */
+pfc_status pfc_hydro_state_init(pfc_plan *p, const void *psi, void *psi_state, const void *v, void *v_state,
+                                void *stream);
+
+/* Advance `nsteps` >= 0 hydrodynamic steps; psi, psi_state, v, v_state (layouts as above) are
+ * updated in place.  work: caller-owned device scratch of at least pfc_hydro_work_bytes bytes,
+ * 256-byte aligned, not overlapping the fields.  Returns PFC_ERR_INVALID_ARG for bad parameters,
+ * PFC_ERR_WORKSPACE for a missing or short work buffer. */
+pfc_status pfc_hydro_step(pfc_plan *p, const pfc_hydro_params *hp, void *psi, void *psi_state, void *v,
+                          void *v_state, void *work, size_t work_bytes, int64_t nsteps, void *stream);
+
 /* ---- Batched form: many independent 2D runs of mixed sizes in one persistent launch ----------
  * Each instance is a 2D grid n0 x n1 (each a power of two in [32, 1024]) with its own model, r and
  * dt; all instances share the dtype and device.  pfc_batch_step advances every instance by nsteps

@@ -14,6 +14,7 @@ from ._binding import (  # noqa: F401
     PFC_ONE_MODE,
     PFC_TWO_MODE,
     Batch,
+    HydroParams,
     PfcError,
     Plan,
     library_path,
@@ -21,6 +22,8 @@ from ._binding import (  # noqa: F401
     pfc_energy,
     pfc_fft_c2r,
     pfc_fft_r2c,
+    pfc_hydro_state_init,
+    pfc_hydro_step,
     pfc_plan_create,
     pfc_plan_destroy,
     pfc_plan_set_params,

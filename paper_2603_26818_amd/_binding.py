@@ -74,6 +74,9 @@ _SIGS = {
     "pfc_plan_get_tuning": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int)]),
     "pfc_plan_set_tuning": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_int), ctypes.c_int]),
     "pfc_energy": (ctypes.c_int, [ctypes.c_void_p] * 5),
+    "pfc_hydro_work_bytes": (ctypes.c_size_t, [ctypes.c_void_p]),
+    "pfc_hydro_state_init": (ctypes.c_int, [ctypes.c_void_p] * 6),
+    "pfc_hydro_step": (ctypes.c_int, [ctypes.c_void_p] * 7 + [ctypes.c_size_t, ctypes.c_int64, ctypes.c_void_p]),
     "pfc_batch_create": (ctypes.c_int, [ctypes.POINTER(ctypes.c_void_p), ctypes.POINTER(PlanDesc), ctypes.c_int]),
     "pfc_batch_workspace_bytes": (ctypes.c_size_t, [ctypes.c_void_p]),
     "pfc_batch_bind": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_void_p), ctypes.POINTER(ctypes.c_void_p),
@@ -281,6 +284,39 @@ class Plan:
             ctypes.c_void_p(dLdr.data_ptr()), _stream_ptr(self.device)), "pfc_step_backward")
         return lambda_n, dLdr
 
+    def hydro_state_init(self, psi, v, psi_state=None, v_state=None):
+        """States of the density and of the ndim velocity components (v: [ndim, *shape])."""
+        torch = _torch()
+        d = len(self.shape)
+        psi_state = self.empty_state() if psi_state is None else psi_state
+        v_state = (torch.empty((d,) + tuple(self.state_shape), dtype=self.complex_dtype, device=self.device)
+                   if v_state is None else v_state)
+        _check(self._lib.pfc_hydro_state_init(
+            self._h, self._tensor(psi, self.shape, self.real_dtype, "psi"),
+            self._tensor(psi_state, self.state_shape, self.complex_dtype, "psi_state"),
+            self._tensor(v, (d,) + tuple(self.shape), self.real_dtype, "v"),
+            self._tensor(v_state, (d,) + tuple(self.state_shape), self.complex_dtype, "v_state"),
+            _stream_ptr(self.device)), "pfc_hydro_state_init")
+        return psi_state, v_state
+
+    def hydro_step(self, psi, psi_state, v, v_state, nsteps=1, rho0=1.0, gamma=1.0, a0=1.0, work=None):
+        """nsteps hydrodynamic PFC steps, all four fields updated in place; `work` (uint8 device tensor
+        of pfc_hydro_work_bytes) is allocated here when not given."""
+        torch = _torch()
+        d = len(self.shape)
+        nbytes = int(self._lib.pfc_hydro_work_bytes(self._h))
+        if work is None:
+            work = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+        hp = HydroParams(float(rho0), float(gamma), float(a0))
+        _check(self._lib.pfc_hydro_step(
+            self._h, ctypes.byref(hp), self._tensor(psi, self.shape, self.real_dtype, "psi"),
+            self._tensor(psi_state, self.state_shape, self.complex_dtype, "psi_state"),
+            self._tensor(v, (d,) + tuple(self.shape), self.real_dtype, "v"),
+            self._tensor(v_state, (d,) + tuple(self.state_shape), self.complex_dtype, "v_state"),
+            ctypes.c_void_p(work.data_ptr()), ctypes.c_size_t(work.numel()), int(nsteps),
+            _stream_ptr(self.device)), "pfc_hydro_step")
+        return psi, psi_state, v, v_state
+
     def energy(self, psi, state, out=None):
         torch = _torch()
         out = torch.empty(2, dtype=torch.float64, device=self.device) if out is None else out
@@ -478,6 +514,12 @@ class Batch:
             pass
 
 
+class HydroParams(ctypes.Structure):
+    """pfc_hydro_params: mass density, viscosity, width of the Gaussian average."""
+
+    _fields_ = [("rho0", ctypes.c_double), ("gamma", ctypes.c_double), ("a0", ctypes.c_double)]
+
+
 # Module-level functions with the C names (same arguments, Plan in place of the handle).
 def pfc_plan_create(shape, **kw) -> Plan:
     return Plan(shape, **kw)
@@ -521,3 +563,11 @@ def pfc_step_backward(plan: Plan, psi_n, psi_np1, lambda_np1, lambda_n=None, dLd
 
 def pfc_energy(plan: Plan, psi, state, out=None):
     return plan.energy(psi, state, out)
+
+
+def pfc_hydro_state_init(plan: Plan, psi, v, psi_state=None, v_state=None):
+    return plan.hydro_state_init(psi, v, psi_state, v_state)
+
+
+def pfc_hydro_step(plan: Plan, psi, psi_state, v, v_state, nsteps=1, rho0=1.0, gamma=1.0, a0=1.0, work=None):
+    return plan.hydro_step(psi, psi_state, v, v_state, nsteps, rho0, gamma, a0, work)

@@ -140,6 +140,61 @@ hipError_t launch_x_c2r_adjoint(const Geom &g, const cx<T> *mu, const cx<T> *nu,
 }
 
 template <typename T>
+hipError_t launch_x_c2r_mac(const Geom &g, const cx<T> *in, T *out, const T *w, bool add, const cx<T> *tw,
+                            hipStream_t s)
+{
+    return by_length(g.M, [&](auto Mc) -> hipError_t {
+        constexpr int M = decltype(Mc)::value;
+        if constexpr (M > 1024) {
+            return hipErrorInvalidValue;
+        } else {
+            using PL = typename XInvPlan<M>::type;
+            constexpr int ROWS = XInvRows<PL>::value;
+            const dim3 grid((unsigned)cdiv(g.xrows, ROWS)), block(ROWS * PL::Tp);
+            const T sc = (T)(1.0 / ((double)g.M * (double)g.n0 * (double)g.nrows));
+            AdjEpi<T> ea{};
+            ea.w = w;
+            ea.add = add ? 1 : 0;
+            hipLaunchKernelGGL((x_c2r_kernel<T, PL, ROWS, EPI_MAC>), grid, block, 0, s, in, out, g.xrows, tw + g.tw_x,
+                               g.lt_shift, sc, ea);
+            return hipGetLastError();
+        }
+    });
+}
+
+template <typename T>
+hipError_t launch_spec_deriv(const Geom &g, const cx<T> *in, cx<T> *out, int role, double fk, hipStream_t s)
+{
+    const int64_t n = g.n0 * g.nrows * g.M;
+    const int64_t blocks = cdiv(n, 256) < 16384 ? cdiv(n, 256) : 16384;
+    hipLaunchKernelGGL((spec_deriv_kernel<T>), dim3((unsigned)blocks), dim3(256), 0, s, in, out, g.n0, g.nrows, g.M, role,
+                       fk);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_spec_update(const Geom &g, int op, cx<T> *out, const cx<T> *x0, const cx<T> *x1,
+                              const HydroArgs &h, hipStream_t s)
+{
+    static_assert(HYDRO_PSI == HY_PSI && HYDRO_MU == HY_MU && HYDRO_VEL == HY_VEL, "mode codes");
+    const int64_t n = g.n0 * g.nrows * g.M;
+    const dim3 grid((unsigned)(cdiv(n, 256) < 16384 ? cdiv(n, 256) : 16384)), block(256);
+    switch (op) {
+    case HY_PSI:
+        hipLaunchKernelGGL((spec_update_kernel<T, HY_PSI>), grid, block, 0, s, out, x0, x1, g.n0, g.nrows, g.M, h);
+        break;
+    case HY_MU:
+        hipLaunchKernelGGL((spec_update_kernel<T, HY_MU>), grid, block, 0, s, out, x0, x1, g.n0, g.nrows, g.M, h);
+        break;
+    case HY_VEL:
+        hipLaunchKernelGGL((spec_update_kernel<T, HY_VEL>), grid, block, 0, s, out, x0, x1, g.n0, g.nrows, g.M, h);
+        break;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+template <typename T>
 hipError_t launch_y_c2c(const Geom &g, cx<T> *data, int dir, const cx<T> *tw, hipStream_t s, int variant)
 {
     return by_length(g.n1, [&](auto Lc) -> hipError_t {
@@ -174,6 +229,12 @@ hipError_t launch_y_c2c(const Geom &g, cx<T> *data, int dir, const cx<T> *tw, hi
 template <typename T>
 hipError_t launch_last_fwd(const Geom &g, const cx<T> *src, cx<T> *dst, const cx<T> *tw, hipStream_t s)
 {
+    return launch_last_c2c<T>(g, src, dst, -1, tw, s);
+}
+
+template <typename T>
+hipError_t launch_last_c2c(const Geom &g, const cx<T> *src, cx<T> *dst, int dir, const cx<T> *tw, hipStream_t s)
+{
     return by_length(g.n0, [&](auto Lc) -> hipError_t {
         constexpr int L = decltype(Lc)::value;
         if constexpr (L < 4) {
@@ -185,8 +246,12 @@ hipError_t launch_last_fwd(const Geom &g, const cx<T> *src, cx<T> *dst, const cx
             const int W = (int)(ncols < WM ? ncols : WM);
             const int64_t tiles = cdiv(ncols, W);
             const dim3 grid((unsigned)tiles), block(WM * PL::Tp);
-            hipLaunchKernelGGL((axis_c2c_kernel<T, PL, WM, -1>), grid, block, 0, s, src, dst, W, ncols, ncols,
-                               (int64_t)0, tiles, tw + g.tw_last, g.lt_shift, 1);
+            if (dir < 0)
+                hipLaunchKernelGGL((axis_c2c_kernel<T, PL, WM, -1>), grid, block, 0, s, src, dst, W, ncols, ncols,
+                                   (int64_t)0, tiles, tw + g.tw_last, g.lt_shift, 1);
+            else
+                hipLaunchKernelGGL((axis_c2c_kernel<T, PL, WM, +1>), grid, block, 0, s, src, dst, W, ncols, ncols,
+                                   (int64_t)0, tiles, tw + g.tw_last, g.lt_shift, 1);
             return hipGetLastError();
         }
     });
@@ -312,6 +377,12 @@ hipError_t launch_export(const Geom &g, const cx<T> *state, cx<T> *out, hipStrea
                                                 T, double *, int64_t *, const cx<T> *, hipStream_t);                  \
     template hipError_t launch_y_c2c<T>(const Geom &, cx<T> *, int, const cx<T> *, hipStream_t, int);                 \
     template hipError_t launch_last_fwd<T>(const Geom &, const cx<T> *, cx<T> *, const cx<T> *, hipStream_t);         \
+    template hipError_t launch_last_c2c<T>(const Geom &, const cx<T> *, cx<T> *, int, const cx<T> *, hipStream_t);    \
+    template hipError_t launch_x_c2r_mac<T>(const Geom &, const cx<T> *, T *, const T *, bool, const cx<T> *,         \
+                                            hipStream_t);                                                             \
+    template hipError_t launch_spec_deriv<T>(const Geom &, const cx<T> *, cx<T> *, int, double, hipStream_t);        \
+    template hipError_t launch_spec_update<T>(const Geom &, int, cx<T> *, const cx<T> *, const cx<T> *,               \
+                                              const HydroArgs &, hipStream_t);                                        \
     template hipError_t launch_last<T>(const Geom &, int, const cx<T> *, cx<T> *, cx<T> *, cx<T> *,                   \
                                        const ModelParams<T> &, const cx<T> *, hipStream_t, int);                      \
     template hipError_t launch_set_mass<T>(const T *, int64_t, double *, cx<T> *, hipStream_t);                       \

@@ -200,7 +200,8 @@ __global__ __launch_bounds__(ROWS *PL::Tp) void x_r2c_kernel(const T *__restrict
 // EPI_PLAIN stores x.  EPI_ADJOINT transforms two spectra (mu from `in`, nu from `in2`) and stores
 //   out = mu - c3 * psi_n^2 * nu,   and writes the block's FP64 sum of nu * psi_np1 to partial[].
 // `in2` and `out` may be the same buffer: each block reads its rows completely before writing.
-enum { EPI_PLAIN = 0, EPI_ADJOINT = 1 };
+// EPI_MAC (hydrodynamic step) stores out = w * x (+ out when `add`), w a real field.
+enum { EPI_PLAIN = 0, EPI_ADJOINT = 1, EPI_MAC = 2 };
 
 template <typename T>
 struct AdjEpi {
@@ -209,6 +210,8 @@ struct AdjEpi {
     const T *psi_np1;
     T c3;
     double *partial;
+    const T *w;  // EPI_MAC
+    int add;     // EPI_MAC
 };
 
 // Pre-combination of one row for the c2r: own elements X(k) from `src`; the mirror X(M-k) either
@@ -282,7 +285,22 @@ __device__ __forceinline__ void x_c2r_block(const cx<T> *in, T *out, int64_t nro
     x_c2r_row<T, PL, ROWS, PAD, PG, NT>(v, in + r0 * M, valid, t, &sh[p * LD], tw, lt_shift);
     fft_stages<T, PL, +1>(v, t, lds, tw, lt_shift);
     cx<T> *dst = reinterpret_cast<cx<T> *>(out) + r0 * M;
-    if constexpr (EPI == EPI_PLAIN) {
+    if constexpr (EPI == EPI_MAC) {
+        if (valid) {
+            const cx<T> *wr = reinterpret_cast<const cx<T> *>(ea.w) + r0 * M;
+#pragma unroll
+            for (int b = 0; b < PL::nb(Rl); ++b)
+                if (PL::jok(t + b * Tp, Rl))
+#pragma unroll
+                    for (int r = 0; r < Rl; ++r) {
+                        const int m = t + b * Tp + r * (M / Rl);
+                        const cx<T> x = scale(v[b * Rl + r], sc), w = wr[m];
+                        cx<T> o = {w.x * x.x, w.y * x.y};
+                        if (ea.add) o = o + dst[m];
+                        dst[m] = o;
+                    }
+        }
+    } else if constexpr (EPI == EPI_PLAIN) {
         if (valid) {
 #pragma unroll
             for (int b = 0; b < PL::nb(Rl); ++b)
@@ -835,6 +853,103 @@ __global__ __launch_bounds__(WMAX *PL::Tp, OCC) void last_axis_kernel(LastAxisAr
 {
     __shared__ cx<T> sh[PL::L * WMAX / G];
     last_axis_block<T, PL, WMAX, MODE, PF, ORD, NT, G>(a, blockIdx.x, sh);
+}
+
+// ------------------------------------------------------------------------------------------------
+// Hydrodynamic PFC: pointwise operations on packed spectra (layout: element (e, row, kx) at
+// (e nrows + row) M + kx; column kx = 0 holds the planes kx = 0 and kx = M as X0 + i XN).
+
+__device__ __forceinline__ double hy_corr(const HydroArgs &h, double q)
+{
+    const double a = (1.0 - q) * (1.0 - q);
+    if (h.model == 0) return a;
+    const double b = h.q1sq - q;
+    return a * (b * b + h.R1);
+}
+
+// out = D in, D = i k the first derivative along `role` (0: last axis, 1: rows, 2: x), with k = 0
+// at the Nyquist index (a first derivative of a real field has no real Nyquist component).  On the
+// folded column the multiplier is the same for both planes (0 for x), so it applies to X0 + i XN.
+template <typename T>
+__global__ __launch_bounds__(256) void spec_deriv_kernel(const cx<T> *__restrict__ in, cx<T> *__restrict__ out,
+                                                         int64_t L, int64_t nrows, int64_t M, int role, double fk)
+{
+    const int64_t n = L * nrows * M;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t kx = i % M, rest = i / M, row = rest % nrows, e = rest / nrows;
+        double k;
+        if (role == 0)
+            k = (2 * e == L) ? 0.0 : fk * signed_index(e, L);
+        else if (role == 1)
+            k = (2 * row == nrows) ? 0.0 : fk * signed_index(row, nrows);
+        else
+            k = fk * (double)kx;  // kx < M: never the Nyquist index; 0 on the folded column
+        const cx<T> z = in[i];
+        out[i] = {(T)(-k * (double)z.y), (T)(k * (double)z.x)};
+    }
+}
+
+enum { HY_PSI = 0, HY_MU = 1, HY_VEL = 2 };
+
+// The update of one mode for its q, with real coefficients (so it maps Hermitian planes to
+// Hermitian planes):
+//   HY_PSI: S <- (S - dt q nl N - dt B) / (1 + dt q (r + L(q)))    (out = S, x0 = N, x1 = B)
+//   HY_MU:  A <- nl A + (r + L(q)) S                                 (out = A, x0 = S)
+//   HY_VEL: V <- (V - c G(q) B) / (1 + c Gamma q), G = exp(-a0^2 q/2) (out = V, x0 = B)
+template <int OP>
+__device__ __forceinline__ void hy_mode(const HydroArgs &h, double q, double o[2], const double a[2], const double b[2])
+{
+    if constexpr (OP == HY_PSI) {
+        const double den = 1.0 + h.dt * q * (h.r + hy_corr(h, q)), f = -h.dt * q * h.nl;
+        for (int c = 0; c < 2; ++c) o[c] = (o[c] + f * a[c] - h.dt * b[c]) / den;
+    } else if constexpr (OP == HY_MU) {
+        const double m = h.r + hy_corr(h, q);
+        for (int c = 0; c < 2; ++c) o[c] = h.nl * o[c] + m * a[c];
+    } else {
+        const double g = h.c * exp(-0.5 * h.a0 * h.a0 * q), den = 1.0 + h.c * h.gamma * q;
+        for (int c = 0; c < 2; ++c) o[c] = (o[c] - g * a[c]) / den;
+    }
+}
+
+// Applies hy_mode to every mode of a packed spectrum, in place on `out`.  On the folded column a
+// thread takes the pair (k, -k): it separates X0 and XN of every operand with the mirror element,
+// updates each plane with its own q (q0 or q0 + kx_Nyquist^2) and writes both elements.
+template <typename T, int OP>
+__global__ __launch_bounds__(256) void spec_update_kernel(cx<T> *out, const cx<T> *__restrict__ x0,
+                                                          const cx<T> *__restrict__ x1, int64_t L, int64_t nrows,
+                                                          int64_t M, HydroArgs h)
+{
+    const int64_t n = L * nrows * M;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t kx = i % M, rest = i / M, row = rest % nrows, e = rest / nrows;
+        const double kz = h.fk[0] * signed_index(e, L), ky = h.fk[1] * signed_index(row, nrows);
+        const cx<T> zx1 = x1 ? x1[i] : cx<T>{T(0), T(0)};
+        if (kx != 0) {
+            const double kk = h.fk[2] * (double)kx, q = kz * kz + ky * ky + kk * kk;
+            double o[2] = {(double)out[i].x, (double)out[i].y}, a[2] = {(double)x0[i].x, (double)x0[i].y},
+                   b[2] = {(double)zx1.x, (double)zx1.y};
+            hy_mode<OP>(h, q, o, a, b);
+            out[i] = {(T)o[0], (T)o[1]};
+            continue;
+        }
+        const int64_t im = (((L - e) % L) * nrows + (nrows - row) % nrows) * M;
+        if (im < i) continue;  // the pair is updated by the thread of its lower index
+        const cx<T> mx1 = x1 ? x1[im] : cx<T>{T(0), T(0)};
+        const cx<T> Z[3] = {out[i], x0[i], zx1}, Zm[3] = {out[im], x0[im], mx1};
+        double p0[3][2], pn[3][2];  // X0 and XN of each operand at k
+        for (int j = 0; j < 3; ++j) {
+            p0[j][0] = 0.5 * ((double)Z[j].x + (double)Zm[j].x);
+            p0[j][1] = 0.5 * ((double)Z[j].y - (double)Zm[j].y);
+            pn[j][0] = 0.5 * ((double)Z[j].y + (double)Zm[j].y);
+            pn[j][1] = 0.5 * ((double)Zm[j].x - (double)Z[j].x);
+        }
+        const double kn = h.fk[2] * (double)M, q0 = kz * kz + ky * ky, qn = q0 + kn * kn;
+        hy_mode<OP>(h, q0, p0[0], p0[1], p0[2]);
+        hy_mode<OP>(h, qn, pn[0], pn[1], pn[2]);
+        // Y = Y0 + i YN at k; at -k the planes are conjugated: conj Y0 + i conj YN
+        out[i] = {(T)(p0[0][0] - pn[0][1]), (T)(p0[0][1] + pn[0][0])};
+        if (im != i) out[im] = {(T)(p0[0][0] + pn[0][1]), (T)(pn[0][0] - p0[0][1])};
+    }
 }
 
 // ------------------------------------------------------------------------------------------------

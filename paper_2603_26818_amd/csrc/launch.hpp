@@ -56,7 +56,25 @@ hipError_t launch_y_c2c(const Geom &g, cx<T> *data, int dir, const cx<T> *tw, hi
 template <typename T>
 hipError_t launch_last_fwd(const Geom &g, const cx<T> *src, cx<T> *dst, const cx<T> *tw, hipStream_t s);
 
+// last-axis complex FFT (dir = -1 forward, +1 inverse), out of place or in place, packed in and out.
+template <typename T>
+hipError_t launch_last_c2c(const Geom &g, const cx<T> *src, cx<T> *dst, int dir, const cx<T> *tw, hipStream_t s);
+
+// x_c2r with the hydrodynamic epilogue: out = w * x (+ out when add), w a real field
+template <typename T>
+hipError_t launch_x_c2r_mac(const Geom &g, const cx<T> *in, T *out, const T *w, bool add, const cx<T> *tw,
+                            hipStream_t s);
+
+// hydrodynamic spectral operations (kernels.hpp): derivative along a grid role (0 last axis,
+// 1 rows, 2 x) and the in-place updates HY_PSI / HY_MU / HY_VEL
+template <typename T>
+hipError_t launch_spec_deriv(const Geom &g, const cx<T> *in, cx<T> *out, int role, double fk, hipStream_t s);
+template <typename T>
+hipError_t launch_spec_update(const Geom &g, int op, cx<T> *out, const cx<T> *x0, const cx<T> *x1,
+                              const HydroArgs &h, hipStream_t s);
+
 enum LastMode { LAST_STEP = 0, LAST_R2C_NATURAL = 1, LAST_C2R_NATURAL = 2, LAST_ADJOINT = 3 };
+enum HydroOp { HYDRO_PSI = 0, HYDRO_MU = 1, HYDRO_VEL = 2 };  // the spec_update_kernel modes
 
 template <typename T>
 hipError_t launch_last(const Geom &g, int mode, const cx<T> *src, cx<T> *dst, cx<T> *dst2, cx<T> *state,

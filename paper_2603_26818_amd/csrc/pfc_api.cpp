@@ -555,6 +555,99 @@ size_t real_bytes(const pfc_plan *p) { return (size_t)(p->g.n0 * p->g.nrows * p-
 size_t half_bytes(const pfc_plan *p) { return (size_t)(p->g.n0 * p->g.nrows * (p->g.M + 1)) * cx_size(p); }
 size_t state_bytes(const pfc_plan *p) { return (size_t)(p->g.n0 * p->g.nrows * p->g.M) * cx_size(p); }
 
+// ---- hydrodynamic PFC
+size_t hydro_work_bytes(const pfc_plan *p) { return 2 * align256(state_bytes(p)) + 2 * align256(real_bytes(p)); }
+
+template <typename T>
+pfc_status do_hydro_state_init(pfc_plan *p, const void *psi, void *psi_state, const void *v, void *v_state,
+                               hipStream_t s)
+{
+    pfc_status st = do_state_init<T>(p, psi, psi_state, s);
+    for (int j = 0; j < p->g.ndim && !st; ++j)
+        st = do_state_init<T>(p, (const char *)v + j * real_bytes(p), (char *)v_state + j * state_bytes(p), s);
+    return st;
+}
+
+// One step after another as stated with pfc_hydro_step in pfc.h, composed of the transform passes
+// (x r2c, y, last axis, x c2r) and the pointwise spectral kernels.  Buffers: A, B packed spectra
+// and a, h real fields in `work`; the plan's own scratch is not used.
+template <typename T>
+pfc_status do_hydro_step(pfc_plan *p, const pfc_hydro_params *hp, void *psi_v, void *S_v, void *v_v, void *V_v,
+                         void *work, int64_t nsteps, hipStream_t s)
+{
+    const Geom &g = p->g;
+    const Bufs<T> b = bufs<T>(p);
+    const int d = g.ndim;
+    const size_t sb = state_bytes(p), rb = real_bytes(p);
+    char *w = (char *)work;
+    cx<T> *A = (cx<T> *)w, *B = (cx<T> *)(w + align256(sb));
+    T *a = (T *)(w + 2 * align256(sb)), *h = (T *)(w + 2 * align256(sb) + align256(rb));
+    T *psi = (T *)psi_v;
+    cx<T> *S = (cx<T> *)S_v;
+    auto vj = [&](int j) { return (T *)((char *)v_v + j * rb); };
+    auto Vj = [&](int j) { return (cx<T> *)((char *)V_v + j * sb); };
+    pfc::HydroArgs ha;
+    for (int i = 0; i < 3; ++i) ha.fk[i] = p->fk[i];
+    ha.r = p->d.r;
+    ha.dt = p->d.dt;
+    ha.q1sq = p->d.q1sq;
+    ha.R1 = p->d.R1;
+    ha.nl = (p->d.flags & PFC_FLAG_LINEAR_ONLY) ? 0.0 : 1.0;
+    ha.model = (int)p->d.model;
+    ha.c = p->d.dt / hp->rho0;
+    ha.gamma = hp->gamma;
+    ha.a0 = hp->a0;
+    // grid axis j -> (role of the spectral index, its wavenumber step)
+    auto role = [&](int j) { return d == 3 ? j : (j == 0 ? 0 : 2); };
+    auto fwd = [&](const T *real, bool cube, cx<T> *out) -> pfc_status {
+        pfc_status st = fwd_xy<T>(p, real, cube, out, s);
+        if (st) return st;
+        PFC_TRY(pfc::launch_last_c2c<T>(g, out, out, -1, b.tw, s), "last-axis forward launch");
+        return PFC_OK;
+    };
+    // inverse of spectrum `spec` through B into the real field `out`: plain, or out = w x (+ out)
+    auto inv = [&](const cx<T> *spec, T *out, const T *wf, bool add) -> pfc_status {
+        PFC_TRY(pfc::launch_last_c2c<T>(g, spec, B, +1, b.tw, s), "last-axis inverse launch");
+        if (d == 3) PFC_TRY(pfc::launch_y_c2c<T>(g, B, +1, b.tw, s), "y inverse launch");
+        if (wf)
+            PFC_TRY(pfc::launch_x_c2r_mac<T>(g, B, out, wf, add, b.tw, s), "x_c2r launch");
+        else
+            PFC_TRY(pfc::launch_x_c2r<T>(g, B, out, b.tw, s), "x_c2r launch");
+        return PFC_OK;
+    };
+    pfc_status st = PFC_OK;
+#define PFC_HY(call)        \
+    do {                    \
+        st = (call);        \
+        if (st) return st;  \
+    } while (0)
+    for (int64_t n = 0; n < nsteps; ++n) {
+        // density: A = FFT(psi^3), a = sum_j v_j IFFT(D_j S), B = FFT(a), S update, psi = IFFT(S)
+        PFC_HY(fwd(psi, true, A));
+        for (int j = 0; j < d; ++j) {
+            PFC_TRY(pfc::launch_spec_deriv<T>(g, S, B, role(j), p->fk[role(j)], s), "derivative launch");
+            PFC_HY(inv(B, a, vj(j), j > 0));
+        }
+        PFC_HY(fwd(a, false, B));
+        PFC_TRY(pfc::launch_spec_update<T>(g, pfc::HYDRO_PSI, S, A, B, ha, s), "density update launch");
+        PFC_HY(inv(S, psi, nullptr, false));
+        // velocity: A = mu = FFT(psi^3) + (r + L) S; per component h = psi IFFT(D_j mu), B = FFT(h)
+        PFC_HY(fwd(psi, true, A));
+        PFC_TRY(pfc::launch_spec_update<T>(g, pfc::HYDRO_MU, A, S, (const cx<T> *)nullptr, ha, s), "mu launch");
+        for (int j = 0; j < d; ++j) {
+            PFC_TRY(pfc::launch_spec_deriv<T>(g, A, B, role(j), p->fk[role(j)], s), "derivative launch");
+            PFC_HY(inv(B, h, psi, false));
+            PFC_HY(fwd(h, false, B));
+            PFC_TRY(pfc::launch_spec_update<T>(g, pfc::HYDRO_VEL, Vj(j), B, (const cx<T> *)nullptr, ha, s),
+                    "velocity update launch");
+            PFC_HY(inv(Vj(j), vj(j), nullptr, false));
+        }
+    }
+#undef PFC_HY
+    return PFC_OK;
+}
+
+
 void drop_graphs(pfc_batch *b)
 {
     for (auto &kv : b->graphs) {
@@ -1037,6 +1130,44 @@ pfc_status pfc_step_backward(pfc_plan *p, const void *psi_n, const void *psi_np1
     if (lambda_n != lambda_np1 && overlap(lambda_n, rb, lambda_np1, rb))
         return fail(PFC_ERR_INVALID_ARG, "lambda_n partially overlaps lambda_np1");
     PFC_DISPATCH(p, do_backward, p, psi_n, psi_np1, lambda_np1, lambda_n, dLdr_accum_dev, (hipStream_t)stream);
+}
+
+size_t pfc_hydro_work_bytes(const pfc_plan *p) { return p ? hydro_work_bytes(p) : 0; }
+
+pfc_status pfc_hydro_state_init(pfc_plan *p, const void *psi, void *psi_state, const void *v, void *v_state,
+                                void *stream)
+{
+    PFC_CHECK(check_ready(p));
+    PFC_CHECK(check_ptr(psi, "psi"));
+    PFC_CHECK(check_ptr(psi_state, "psi_state"));
+    PFC_CHECK(check_ptr(v, "v"));
+    PFC_CHECK(check_ptr(v_state, "v_state"));
+    PFC_DISPATCH(p, do_hydro_state_init, p, psi, psi_state, v, v_state, (hipStream_t)stream);
+}
+
+pfc_status pfc_hydro_step(pfc_plan *p, const pfc_hydro_params *hp, void *psi, void *psi_state, void *v,
+                          void *v_state, void *work, size_t work_bytes, int64_t nsteps, void *stream)
+{
+    PFC_CHECK(check_ready(p));
+    if (!hp) return fail(PFC_ERR_INVALID_ARG, "hydro parameters are NULL");
+    if (!(hp->rho0 > 0.0) || !std::isfinite(hp->rho0)) return fail(PFC_ERR_INVALID_ARG, "rho0 must be > 0 and finite");
+    if (!(hp->gamma >= 0.0) || !std::isfinite(hp->gamma)) return fail(PFC_ERR_INVALID_ARG, "gamma must be >= 0");
+    if (!(hp->a0 >= 0.0) || !std::isfinite(hp->a0)) return fail(PFC_ERR_INVALID_ARG, "a0 must be >= 0");
+    if (nsteps < 0) return fail(PFC_ERR_INVALID_ARG, "nsteps < 0");
+    PFC_CHECK(check_ptr(psi, "psi"));
+    PFC_CHECK(check_ptr(psi_state, "psi_state"));
+    PFC_CHECK(check_ptr(v, "v"));
+    PFC_CHECK(check_ptr(v_state, "v_state"));
+    if (!work || work_bytes < hydro_work_bytes(p))
+        return fail(PFC_ERR_WORKSPACE, "hydro work buffer has %zu bytes, needs %zu", work ? work_bytes : (size_t)0,
+                    hydro_work_bytes(p));
+    if (((uintptr_t)work & 255u) != 0) return fail(PFC_ERR_ALIGNMENT, "hydro work buffer must be 256-byte aligned");
+    const size_t nd = (size_t)p->g.ndim;
+    if (overlap(work, hydro_work_bytes(p), psi, real_bytes(p)) || overlap(work, hydro_work_bytes(p), v, nd * real_bytes(p)) ||
+        overlap(work, hydro_work_bytes(p), psi_state, state_bytes(p)) ||
+        overlap(work, hydro_work_bytes(p), v_state, nd * state_bytes(p)))
+        return fail(PFC_ERR_INVALID_ARG, "hydro work buffer overlaps a field");
+    PFC_DISPATCH(p, do_hydro_step, p, hp, psi, psi_state, v, v_state, work, nsteps, (hipStream_t)stream);
 }
 
 pfc_status pfc_energy(pfc_plan *p, const void *psi, const void *state, double *out_dev, void *stream)

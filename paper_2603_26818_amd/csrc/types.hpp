@@ -39,6 +39,18 @@ struct ModelParams {
     int model;
 };
 
+// Hydrodynamic PFC spectral updates (kernels.hpp).
+// Parameters, in FP64.  fk[0]: last-axis (index e), fk[1]: rows (3D y),
+// fk[2]: x wavenumber steps.
+struct HydroArgs {
+    double fk[3];
+    double r, dt, q1sq, R1, nl;
+    int model;
+    double c;      // dt / rho0
+    double gamma;  // viscosity
+    double a0;     // width of the Gaussian average
+};
+
 // ---- batched persistent form (one entry per instance, in device memory)
 template <typename T>
 struct BatchInst {
