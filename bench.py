@@ -114,6 +114,41 @@ def bench_batched(nsteps):
             "separate_launches_steps_per_s": round(1000.0 / ms_sep, 1)}
 
 
+def bench_hydro(nsteps, n=512, seed=9):
+    """Hydrodynamic PFC (density + 3 velocity components) at n^3 FP32, rho0 = gamma = a0 = 1,
+    r = -0.30, dt = 0.25: ms per step and algorithmic GB/s on the 528 B/point pass model (132 passes
+    of 4 B per point: 108 over packed spectra, 24 over real fields)."""
+    import torch
+
+    import paper_2603_26818_amd as pfc
+    import pfc_inputs
+
+    shape = (n, n, n)
+    plan = pfc.Plan(shape, dtype="f32", r=R, dt=0.25)
+    psi = pfc_inputs.pfc_initial_field_torch(seed, shape, R, torch.float32, "cuda:0")
+    v = torch.stack([pfc_inputs.uniform_torch(seed * 10 + j, shape, -0.05, 0.05, torch.float32, "cuda:0")
+                     for j in range(3)])
+    S, V = plan.hydro_state_init(psi, v)
+    work = torch.empty(int(plan._lib.pfc_hydro_work_bytes(plan._h)), dtype=torch.uint8, device="cuda:0")
+    plan.hydro_step(psi, S, v, V, 1, work=work)
+    stream = torch.cuda.current_stream()
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    plan.hydro_step(psi, S, v, V, nsteps, work=work)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / nsteps
+    finite = bool(torch.isfinite(psi).all().item()) and bool(torch.isfinite(v).all().item())
+    del psi, v, S, V, work, plan
+    torch.cuda.empty_cache()
+    alg = 528.0 * n**3
+    return {"workload": f"3D hydrodynamic PFC {n}^3 FP32 (psi + 3 velocity components), rho0=gamma=a0=1, r=-0.30, "
+                        f"dt=0.25, seed {seed}", "steps": nsteps, "ms_per_step": round(ms, 3),
+            "steps_per_s": round(1000.0 / ms, 2), "alg_gbps": round(alg / ms / 1e6, 1),
+            "frac": round(alg / ms / 1e6 / PEAK_HBM_GBPS, 4), "fields_finite": finite}
+
+
 def bench_big(nsteps, n=2048, seed=3):
     """3D one-mode PFC at n^3 FP32 (r = -0.30, dt = 0.5): steps/s and per-pass GB/s.  n = 2048: the
     full single-GPU size; n = 750: the paper's smaller 3D grid (mixed radix, 750 = 2 3 5^3)."""
@@ -277,6 +312,7 @@ def main():
     ap.add_argument("--batch-steps", type=int, default=500, help="steps of the batched form (0: skip)")
     ap.add_argument("--adjoint-steps", type=int, default=2000, help="steps of the adjoint form (0: skip)")
     ap.add_argument("--big-steps", type=int, default=50, help="timed steps at 2048^3 (0: skip)")
+    ap.add_argument("--hydro-steps", type=int, default=5, help="timed hydrodynamic steps at 512^3 (0: skip)")
     ap.add_argument("--paper-steps", type=int, default=20,
                     help="timed steps at 750^3 and 1400^3, the paper's 3D grids (0: skip)")
     ap.add_argument("--counters", type=int, default=0, metavar="STEPS",
@@ -391,6 +427,11 @@ def main():
             log(f"[bench] {n}^3 FP32 (mixed radix): {args.paper_steps} steps")
             paper[str(n)] = bench_big(args.paper_steps, n=n, seed=seed)
             log(f"[bench] {n}^3: {paper[str(n)]['steps_per_s']} steps/s ({paper[str(n)]['frac']:.3f} of peak)")
+    hydro = None
+    if args.hydro_steps > 0:
+        log(f"[bench] hydrodynamic PFC 512^3 FP32: {args.hydro_steps} steps")
+        hydro = bench_hydro(args.hydro_steps)
+        log(f"[bench] hydro: {hydro['ms_per_step']} ms/step ({hydro['frac']:.3f} of peak)")
     batched = None
     if args.batch_steps > 0:
         log(f"[bench] batched form: 48 instances, {args.batch_steps} steps")
@@ -427,6 +468,7 @@ def main():
                                "psi0=-0.30+U(-0.1,0.1) SplitMix64 seed 23", "grid": list(shape)},
         "roofline": roofline, "cpu_baseline": cpu, "fft": fft, "passes": passes, "big_2048": big,
         "paper_grids": paper,
+        "hydro": hydro,
         "batched": batched, "adjoint": adjoint,
         "step_alg_gbps": round(step_bytes / ms_per_step / 1e6, 1),
         "step_frac": round(step_bytes / ms_per_step / 1e6 / PEAK_HBM_GBPS, 4),
