@@ -310,10 +310,12 @@ hipError_t launch_last(const Geom &g, int mode, const cx<T> *src, cx<T> *dst, cx
                     if (g.nrows > 1 && (g.nrows * (g.M + 1)) % C == 0 && g.M >= C) {
                         using PL = SpreadIf<P0, TL::E>;
                         const int64_t nchunks = g.nrows * (g.M + 1) / C;
-                        hipLaunchKernelGGL((r2c_natural_chunk_kernel<T, PL, C, TL::G>), dim3((unsigned)nchunks),
-                                           dim3(C * PL::Tp), 0, s, src, dst, g.nrows, (int)g.M, tw + g.tw_last,
-                                           g.lt_shift);
-                        break;
+                        return with_nt(g.nt, [&](auto ntc) -> hipError_t {
+                            hipLaunchKernelGGL((r2c_natural_chunk_kernel<T, PL, C, TL::G, decltype(ntc)::value>),
+                                               dim3((unsigned)nchunks), dim3(C * PL::Tp), 0, s, src, dst, g.nrows,
+                                               (int)g.M, tw + g.tw_last, g.lt_shift);
+                            return hipGetLastError();
+                        });
                     }
                 }
                 hipLaunchKernelGGL((last_axis_kernel<T, P0, WM, LA_R2C_NATURAL, 1, true, ORD_XCD_ROW>), grid,
@@ -321,9 +323,12 @@ hipError_t launch_last(const Geom &g, int mode, const cx<T> *src, cx<T> *dst, cx
                 break;
             }
             case LAST_C2R_NATURAL:
-                hipLaunchKernelGGL((last_axis_kernel<T, P0, WM, LA_C2R_NATURAL, 1, true, ORD_XCD_ROW>), grid,
-                                   dim3(WM * P0::Tp), 0, s, a);
-                break;
+                return with_nt(g.nt && line_group<T>(a.W) == 1, [&](auto ntc) -> hipError_t {
+                    hipLaunchKernelGGL(
+                        (last_axis_kernel<T, P0, WM, LA_C2R_NATURAL, 1, true, ORD_XCD_ROW, decltype(ntc)::value>), grid,
+                        dim3(WM * P0::Tp), 0, s, a);
+                    return hipGetLastError();
+                });
             case LAST_ADJOINT:
                 hipLaunchKernelGGL((last_axis_kernel<T, P0, WM, LA_ADJOINT>), grid, dim3(WM * P0::Tp), 0, s, a);
                 break;

@@ -606,7 +606,7 @@ __device__ __forceinline__ void last_axis_block(const LastAxisArgs<T> &a, int64_
                 if (PL::jok(t + b * Tp, Rf))
 #pragma unroll
                 for (int r = 0; r < Rf; ++r)
-                    a.dst[(int64_t)(t + b * Tp + r * (L / Rf)) * estride + coloff] = v[b * Rf + r];
+                    st_grid<NT>(&a.dst[(int64_t)(t + b * Tp + r * (L / Rf)) * estride + coloff], v[b * Rf + r]);
         }
         return;
     } else {
@@ -963,7 +963,7 @@ __global__ __launch_bounds__(256) void spec_update_kernel(cx<T> *out, const cx<T
 // second round transforms: X0 = (Z(k) + conj Z(-k)) / 2, XM = -i (Z(k) - conj Z(-k)) / 2.  A chunk
 // holds at most two such slots; the second round runs only in chunks that have one.  The reads of
 // packed columns are not line-aligned; chunks that share input lines run on one XCD.
-template <typename T, class PL, int C, int G>
+template <typename T, class PL, int C, int G, bool NT = false>
 __global__ __launch_bounds__(C *PL::Tp) void r2c_natural_chunk_kernel(const cx<T> *__restrict__ src,
                                                                       cx<T> *__restrict__ dst, int64_t nrows, int M,
                                                                       const cx<T> *__restrict__ tw, int lt_shift)
@@ -995,7 +995,7 @@ __global__ __launch_bounds__(C *PL::Tp) void r2c_natural_chunk_kernel(const cx<T
         for (int b = 0; b < PL::nb(Rl); ++b)
             if (PL::jok(t + b * Tp, Rl))
 #pragma unroll
-            for (int r = 0; r < Rl; ++r) dst[(int64_t)(t + b * Tp + r * (L / Rl)) * plane + f] = v[b * Rl + r];
+            for (int r = 0; r < Rl; ++r) st_grid<NT>(&dst[(int64_t)(t + b * Tp + r * (L / Rl)) * plane + f], v[b * Rl + r]);
     }
     if (!__syncthreads_or(fold)) return;  // uniform: the chunk has no folded slot
     // round 2: mirror pencils of the folded slots
@@ -1036,7 +1036,7 @@ __global__ __launch_bounds__(C *PL::Tp) void r2c_natural_chunk_kernel(const cx<T
                     const cx<T> a = z[b * Rl + r], m = lds(neg_mod<L>(e));
                     const cx<T> out = (kx == 0) ? cx<T>{(a.x + m.x) * h, (a.y - m.y) * h}
                                                 : cx<T>{(a.y + m.y) * h, (m.x - a.x) * h};
-                    dst[(int64_t)e * plane + f] = out;
+                    st_grid<NT>(&dst[(int64_t)e * plane + f], out);
                 }
         }
     }
