@@ -39,7 +39,7 @@ extern "C" {
 typedef enum {
     PFC_OK = 0,
     PFC_ERR_INVALID_ARG = 1, /* bad value, NULL pointer, unstable dt, ...           */
-    PFC_ERR_UNSUPPORTED = 2, /* size not a power of two in [4, 2048], ndim not 2/3 */
+    PFC_ERR_UNSUPPORTED = 2, /* unsupported grid size (see pfc_plan_create), ndim not 2/3 */
     PFC_ERR_ALIGNMENT = 3,   /* device pointer not 16-byte aligned                 */
     PFC_ERR_WORKSPACE = 4,   /* workspace missing or too small                     */
     PFC_ERR_HIP = 5,         /* a HIP runtime call failed                          */
@@ -57,7 +57,7 @@ typedef struct pfc_plan pfc_plan;
 
 typedef struct {
     int ndim;        /* 2 or 3                                                    */
-    int64_t n[3];    /* grid, slowest axis first; n[ndim-1] is x; powers of two   */
+    int64_t n[3];    /* grid, slowest axis first; n[ndim-1] is x (sizes: below)   */
     double dx[3];    /* grid spacing per axis (> 0)                               */
     pfc_dtype dtype; /* arithmetic of fields, spectra and FFTs                    */
     pfc_model model; /* correlation operator L(q)                                 */
@@ -70,7 +70,11 @@ typedef struct {
 } pfc_plan_desc;
 
 /* Validate `d` and create a plan (host memory only; no device allocation, no kernel).
- * Rejects: ndim not in {2,3}, a size that is not a power of two in [4, 2048] (UNSUPPORTED), dx <= 0,
+ * Grid sizes: powers of two in [4, 2048]; or even sizes <= 2048 built from factors 2, 3, 5, 7 that
+ * have a compiled schedule: for y and the last axis n in {6, 10, 12, 14, 20, 30, 60, 150, 700, 750,
+ * 1400}, for x n/2 in {6, 10, 12, 14, 15, 20, 30, 60, 150, 375, 700, 750} (so the paper's 750^3 and
+ * 1400^3 grids run).
+ * Rejects: ndim not in {2,3}, any other size (UNSUPPORTED), dx <= 0,
  * dt <= 0, non-finite parameters, and any (r, dt) for which 1 + dt q (r + L(q)) <= 0 at some grid
  * wavevector (INVALID_ARG: the implicit denominator would vanish or change sign). */
 pfc_status pfc_plan_create(pfc_plan **out, const pfc_plan_desc *d);

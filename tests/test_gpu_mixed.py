@@ -120,3 +120,20 @@ def test_750_cube_two_steps_vs_oracle(pfc, oracle_750, dtype):
     e = relerr(to_np(psi), ref_psi)
     say(f"      psi rel L2 {e:.2e}")
     assert e < (1e-12 if dtype == "f64" else 1e-5)
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_mixed_adjoint_rollout_vs_oracle(pfc, dtype):
+    """Gradient of L = sum (psi(T) - target)^2 with respect to psi0 and r through 60 steps on a
+    30 x 20 grid, against the oracle's adjoint sweep."""
+    shape, nsteps, r0, rt = (30, 20), 60, -0.25, -0.30
+    say(f"[mixed adjoint] shape={shape} dtype={dtype} nsteps={nsteps}")
+    psi0 = rounded(P.pfc_initial_field(59, shape, r0), dtype)
+    target = oracle.rollout(oracle.Params(shape, r=rt, dt=0.5), psi0, nsteps)[-1]
+    L_ref, g_ref, dr_ref = oracle.loss_and_grad(oracle.Params(shape, r=r0, dt=0.5), psi0, target, nsteps)
+    plan = pfc.Plan(shape, dtype=dtype, r=r0, dt=0.5)
+    L, g, dr = pfc.loss_and_grad(plan, to_dev(psi0, dtype), r0, to_dev(target, dtype), nsteps, 20)
+    eg = relerr(to_np(g), g_ref)
+    say(f"      L {L:.10g} vs {L_ref:.10g}; grad rel L2 {eg:.2e}; dL/dr {dr:.8g} vs {dr_ref:.8g}")
+    tol = 1e-10 if dtype == "f64" else 1e-3
+    assert abs(L - L_ref) < tol * abs(L_ref) and eg < tol and abs(dr - dr_ref) < tol * abs(dr_ref)
