@@ -179,18 +179,35 @@ __device__ __forceinline__ void dft(cx<T> *v)
     if constexpr (!is_pow2c(R)) {
         constexpr int p = smallest_factor(R), q = R / p;
         if constexpr (q == 1) {
-            cx<T> in[R];
+            // prime R: pair x_r with x_{R-r}, a_r = x_r + x_{R-r}, b_r = x_r - x_{R-r} (r <= H);
+            // with c = cos(2 pi r s / R), sn = sin(2 pi r s / R):
+            //   X_s = x_0 + sum_r c a_r + DIR i sum_r sn b_r,  X_{R-s} = the same with -DIR i
+            // (real-times-complex products: a quarter of the multiplications of the direct sum)
+            constexpr int H = (R - 1) / 2;
+            cx<T> a[H + 1], b[H + 1];
+            cx<T> sum = v[0];
 #pragma unroll
-            for (int r = 0; r < R; ++r) in[r] = v[r];
-            static_for<0, R>([&](auto sc) {
+            for (int r = 1; r <= H; ++r) {
+                a[r] = v[r] + v[R - r];
+                b[r] = v[r] - v[R - r];
+                sum = sum + a[r];
+            }
+            const cx<T> x0 = v[0];
+            static_for<1, H + 1>([&](auto sc) {
                 constexpr int s2 = decltype(sc)::value;
-                cx<T> acc = in[0];
-                static_for<1, R>([&](auto rc) {
+                cx<T> A = x0, Bv = {T(0), T(0)};
+                static_for<1, H + 1>([&](auto rc) {
                     constexpr int r = decltype(rc)::value;
-                    acc = acc + rotg<T, R, r * s2, DIR>(in[r]);
+                    constexpr T c = (T)cs2pi(r * s2, R, 0), sn = (T)cs2pi(r * s2, R, 1);
+                    A = {A.x + c * a[r].x, A.y + c * a[r].y};
+                    Bv = {Bv.x + sn * b[r].x, Bv.y + sn * b[r].y};
                 });
-                v[s2] = acc;
+                // DIR i B = DIR (-B.y, B.x)
+                const cx<T> iB = {T(-DIR) * Bv.y, T(DIR) * Bv.x};
+                v[s2] = A + iB;
+                v[R - s2] = A - iB;
             });
+            v[0] = sum;
         } else {
             cx<T> e[p][q];
 #pragma unroll
