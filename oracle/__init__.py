@@ -47,8 +47,14 @@ def _load():
     lib.or_step_backward.argtypes = [pp, dp, dp, dp, dp, dp]
     lib.or_num_threads.argtypes = []
     lib.or_hydro_step.argtypes = [pp, ctypes.POINTER(_OrHydro), dp, dp, dp, dp, ctypes.c_int64]
+    ap = P(_OrApfc)
+    lib.or_apfc_nonlinear.argtypes = [ap, dp, dp]
+    lib.or_apfc_counts.argtypes = [ap, ctypes.c_int, P(ctypes.c_int)]
+    lib.or_apfc_state_init.argtypes = [ap, dp, dp]
+    lib.or_apfc_step.argtypes = [ap, dp, dp, ctypes.c_int64]
     for f in ("or_fft_c2c", "or_rfftn", "or_irfftn", "or_state_init", "or_step", "or_energy",
-              "or_step_backward", "or_num_threads", "or_hydro_step"):
+              "or_step_backward", "or_num_threads", "or_hydro_step", "or_apfc_nonlinear", "or_apfc_counts",
+              "or_apfc_state_init", "or_apfc_step"):
         getattr(lib, f).restype = ctypes.c_int
     _lib = lib
     return lib
@@ -233,3 +239,102 @@ def hydro_step(p: Params, h: Hydro, psi: np.ndarray, psi_state: np.ndarray, v: n
     _check(_load().or_hydro_step(ctypes.byref(p.c()), ctypes.byref(hc), _dp(psi), _dp(S.view(np.float64)), _dp(v),
                                  _dp(V.view(np.float64)), int(nsteps)), "hydro_step")
     return psi, S, v, V
+
+
+APFC_MAX = 32
+
+
+class _OrApfc(ctypes.Structure):
+    _fields_ = [
+        ("ndim", ctypes.c_int),
+        ("n", ctypes.c_int64 * 3),
+        ("dx", ctypes.c_double * 3),
+        ("nfields", ctypes.c_int),
+        ("kvec", (ctypes.c_double * 3) * APFC_MAX),
+        ("dB", ctypes.c_double),
+        ("Bx", ctypes.c_double),
+        ("t", ctypes.c_double),
+        ("v", ctypes.c_double),
+        ("dt", ctypes.c_double),
+    ]
+
+
+@dataclass
+class Apfc:
+    """Complex-amplitude PFC (equations in pfc_oracle.c): grid ``shape`` (C order), spacing ``dx``,
+    principal wave vectors ``kvec`` [N][ndim] (components along the grid axes, slowest first),
+    coefficients dB, Bx, t, v and time step dt."""
+
+    shape: tuple
+    kvec: np.ndarray
+    dx: float | tuple = np.pi / 2
+    dB: float = -0.15
+    Bx: float = 1.0
+    t: float = 0.0
+    v: float = 1.0
+    dt: float = 0.5
+
+    @property
+    def nfields(self) -> int:
+        return int(np.asarray(self.kvec).shape[0])
+
+    @property
+    def field_shape(self):
+        return (self.nfields,) + tuple(self.shape)
+
+    def c(self) -> _OrApfc:
+        a = _OrApfc()
+        nd = len(self.shape)
+        a.ndim = nd
+        dx = self.dx if isinstance(self.dx, (tuple, list)) else (self.dx,) * nd
+        for i in range(3):
+            a.n[i] = int(self.shape[i]) if i < nd else 1
+            a.dx[i] = float(dx[i]) if i < nd else 1.0
+        k = np.asarray(self.kvec, dtype=np.float64)
+        assert k.ndim == 2 and k.shape[1] == nd and 1 <= k.shape[0] <= APFC_MAX
+        a.nfields = k.shape[0]
+        for j in range(k.shape[0]):
+            for i in range(nd):
+                a.kvec[j][i] = float(k[j, i])
+        a.dB, a.Bx, a.t, a.v, a.dt = (float(self.dB), float(self.Bx), float(self.t), float(self.v),
+                                      float(self.dt))
+        return a
+
+
+def _cfields(a: Apfc, x) -> np.ndarray:
+    x = np.array(x, dtype=np.complex128, order="C", copy=True)
+    assert x.shape == a.field_shape, (x.shape, a.field_shape)
+    return x
+
+
+def apfc_nonlinear(a: Apfc, eta) -> np.ndarray:
+    """N_j (the resonant part of -t psi^2 + v psi^3 at k_j) at every point, [N][grid] complex."""
+    eta = _cfields(a, eta)
+    out = np.zeros_like(eta)
+    _check(_load().or_apfc_nonlinear(ctypes.byref(a.c()), _dp(eta.view(np.float64)), _dp(out.view(np.float64))),
+           "apfc_nonlinear")
+    return out
+
+
+def apfc_counts(a: Apfc, j: int):
+    """(resonant ordered pairs, resonant ordered triples) of field j."""
+    c = (ctypes.c_int * 2)()
+    _check(_load().or_apfc_counts(ctypes.byref(a.c()), int(j), c), "apfc_counts")
+    return int(c[0]), int(c[1])
+
+
+def apfc_state_init(a: Apfc, eta) -> np.ndarray:
+    eta = _cfields(a, eta)
+    out = np.zeros_like(eta)
+    _check(_load().or_apfc_state_init(ctypes.byref(a.c()), _dp(eta.view(np.float64)), _dp(out.view(np.float64))),
+           "apfc_state_init")
+    return out
+
+
+def apfc_step(a: Apfc, eta, eta_hat, nsteps: int):
+    """nsteps amplitude steps; returns new (eta, eta_hat); inputs are not modified."""
+    eta = _cfields(a, eta)
+    S = _cfields(a, eta_hat)
+    _check(_load().or_apfc_step(ctypes.byref(a.c()), _dp(eta.view(np.float64)), _dp(S.view(np.float64)),
+                                int(nsteps)), "apfc_step")
+    return eta, S

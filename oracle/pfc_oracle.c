@@ -18,7 +18,9 @@
  *         psiF <- (psiF + dt*lap*FFT(psi^3)) / (1 - dt*lin),   lap = -q,   lin = -q (eps + L(q)),
  *     followed by the inverse transform back to real space;
  *   - the discrete adjoint (transpose of the Jacobian) of that step, used for gradients;
- *   - the hydrodynamic PFC step of the multiphysics section (Eq. (5), (6), Listing 2).
+ *   - the hydrodynamic PFC step of the multiphysics section (Eq. (5), (6), Listing 2);
+ *   - the complex-amplitude form of the PFC model named at the end of that section (equations and
+ *     readings with its code below).
  *
  * Readings where the paper is silent (each is listed with its reason in the design notes):
  *   - fields are real, so the spectral state is the half spectrum [n0][n1][n2/2+1]; after every
@@ -615,6 +617,229 @@ int or_hydro_step(const or_params *p, const or_hydro *hp, double *psi, double *p
     free(NF);
     free(th);
     free(mu);
+    return e;
+}
+
+/* ---------------------------------------------------------------- amplitude equations */
+
+/* Complex-amplitude (coarse-grained) PFC, the extension named at the end of the multiphysics
+ * section: the density is written as psi = sum_j eta_j e^{i k_j.r} + c.c. over N principal
+ * reciprocal-lattice vectors k_j, with slowly varying complex amplitudes eta_j.  The paper names
+ * the formulation and leaves its equations to the cited overview of amplitude expansions; this
+ * oracle takes the standard form of that literature with the free energy of Eq. (3) generalised by
+ * the usual quadratic coefficient t:
+ *     f(psi) = psi (dB + Bx (1 + lap)^2) psi / 2 - t psi^3 / 3 + v psi^4 / 4
+ * (Eq. (3) is dB = r, Bx = 1, t = 0, v = 1), and for each amplitude
+ *     d_t eta_j = -|k_j|^2 [ (dB + Bx G_j^2) eta_j + N_j ],   G_j = lap + 2 i k_j . grad,
+ * where N_j is the resonant part of the nonlinearity -t psi^2 + v psi^3 at wave vector k_j:
+ *     N_j = -t sum_{k_a + k_b = k_j} eta_a eta_b + v sum_{k_a + k_b + k_c = k_j} eta_a eta_b eta_c,
+ * the sums running over ordered tuples of a, b, c in {+-1 .. +-N} with k_{-a} = -k_a and
+ * eta_{-a} = conj(eta_a).  In Fourier space G_j = -(|q|^2 + 2 k_j . q), and the semi-implicit step
+ * (the update of Listing 1 applied to each amplitude) is
+ *     eta_hat_j <- (eta_hat_j - dt |k_j|^2 FFT(N_j)) / (1 + dt |k_j|^2 (dB + Bx G_j^2)),
+ * followed by eta_j = IFFT(eta_hat_j).  Readings: the mean density is absorbed into dB, t, v; the
+ * mobility is the long-wave -|k_j|^2; wave vectors q use numpy's fftfreq order (the Nyquist index
+ * counts as -n/2, since G_j is odd in q); a tuple is resonant when its vector sum matches k_j to
+ * 1e-9 times the largest |k_j|. */
+#define OR_APFC_MAX 32
+typedef struct {
+    int ndim;
+    int64_t n[3];
+    double dx[3];
+    int nfields;                  /* N <= 32 */
+    double kvec[OR_APFC_MAX][3];  /* k_j, components along the grid axes (slowest first) */
+    double dB, Bx, t, v, dt;
+} or_apfc;
+
+typedef struct {
+    int nq, nc;   /* resonant ordered tuples for one field */
+    int *q, *c;   /* signed field indices (+-(a+1)), 2 or 3 per tuple */
+} apfc_terms;
+
+static int apfc_check(const or_apfc *p)
+{
+    if (!p || !check_dims(p->ndim, p->n) || p->nfields < 1 || p->nfields > OR_APFC_MAX) return 0;
+    for (int j = 0; j < p->nfields; ++j) {
+        double kk = 0.0;
+        for (int a = 0; a < p->ndim; ++a) kk += p->kvec[j][a] * p->kvec[j][a];
+        if (!(kk > 0.0)) return 0;
+    }
+    return 1;
+}
+
+/* component a of k_s for a signed index s = +-(j+1) */
+static double apfc_k(const or_apfc *p, int s, int a) { return s > 0 ? p->kvec[s - 1][a] : -p->kvec[-s - 1][a]; }
+
+static int apfc_match(const or_apfc *p, const int *s, int len, int j, double tol)
+{
+    for (int a = 0; a < p->ndim; ++a) {
+        double sum = 0.0;
+        for (int i = 0; i < len; ++i) sum += apfc_k(p, s[i], a);
+        if (fabs(sum - p->kvec[j][a]) > tol) return 0;
+    }
+    return 1;
+}
+
+/* All resonant ordered pairs and triples of every field (terms[j]). */
+static int apfc_enumerate(const or_apfc *p, apfc_terms *terms)
+{
+    const int N = p->nfields, S = 2 * N;
+    double kmax = 0.0;
+    for (int j = 0; j < N; ++j) {
+        double kk = 0.0;
+        for (int a = 0; a < p->ndim; ++a) kk += p->kvec[j][a] * p->kvec[j][a];
+        if (sqrt(kk) > kmax) kmax = sqrt(kk);
+    }
+    const double tol = 1e-9 * kmax;
+    int sig[2 * OR_APFC_MAX];
+    for (int i = 0; i < N; ++i) {
+        sig[2 * i] = i + 1;
+        sig[2 * i + 1] = -(i + 1);
+    }
+    for (int j = 0; j < N; ++j) {
+        apfc_terms *T = &terms[j];
+        T->nq = T->nc = 0;
+        T->q = (int *)malloc(sizeof(int) * 2 * (size_t)S * S);
+        T->c = (int *)malloc(sizeof(int) * 3 * (size_t)S * S * S);
+        if (!T->q || !T->c) return OR_ERR_MEM;
+        for (int x = 0; x < S; ++x)
+            for (int y = 0; y < S; ++y) {
+                int s[2] = {sig[x], sig[y]};
+                if (apfc_match(p, s, 2, j, tol)) {
+                    T->q[2 * T->nq] = s[0];
+                    T->q[2 * T->nq + 1] = s[1];
+                    ++T->nq;
+                }
+                for (int z = 0; z < S; ++z) {
+                    int s3[3] = {sig[x], sig[y], sig[z]};
+                    if (apfc_match(p, s3, 3, j, tol)) {
+                        for (int i = 0; i < 3; ++i) T->c[3 * T->nc + i] = s3[i];
+                        ++T->nc;
+                    }
+                }
+            }
+    }
+    return OR_OK;
+}
+
+static void apfc_free(apfc_terms *terms, int N)
+{
+    for (int j = 0; j < N; ++j) {
+        free(terms[j].q);
+        free(terms[j].c);
+    }
+}
+
+/* eta_s at point i of fields stored [N][P] */
+static cplx apfc_eta(const cplx *eta, int64_t P, int64_t i, int s)
+{
+    return s > 0 ? eta[(int64_t)(s - 1) * P + i] : conj(eta[(int64_t)(-s - 1) * P + i]);
+}
+
+static void apfc_nonlinear_terms(const or_apfc *p, const apfc_terms *terms, const cplx *eta, cplx *out)
+{
+    const int64_t P = total_size(p->ndim, p->n);
+#pragma omp parallel for schedule(static)
+    for (int64_t i = 0; i < P; ++i)
+        for (int j = 0; j < p->nfields; ++j) {
+            const apfc_terms *T = &terms[j];
+            cplx sq = 0.0, sc = 0.0;
+            for (int m = 0; m < T->nq; ++m) sq += apfc_eta(eta, P, i, T->q[2 * m]) * apfc_eta(eta, P, i, T->q[2 * m + 1]);
+            for (int m = 0; m < T->nc; ++m)
+                sc += apfc_eta(eta, P, i, T->c[3 * m]) * apfc_eta(eta, P, i, T->c[3 * m + 1]) *
+                      apfc_eta(eta, P, i, T->c[3 * m + 2]);
+            out[(int64_t)j * P + i] = -p->t * sq + p->v * sc;
+        }
+}
+
+/* Signed wavenumber of index m on an axis of length n (numpy fftfreq order: Nyquist negative). */
+static double apfc_wavenumber(int64_t m, int64_t n, double dx)
+{
+    int64_t s = (2 * m < n) ? m : m - n;
+    return 2.0 * PI * (double)s / ((double)n * dx);
+}
+
+/* N_j at every point of the fields eta [N][grid] (complex). */
+int or_apfc_nonlinear(const or_apfc *p, const double *eta, double *out)
+{
+    if (!apfc_check(p)) return OR_ERR_ARG;
+    apfc_terms terms[OR_APFC_MAX];
+    memset(terms, 0, sizeof terms);
+    int e = apfc_enumerate(p, terms);
+    if (!e) apfc_nonlinear_terms(p, terms, (const cplx *)eta, (cplx *)out);
+    apfc_free(terms, p->nfields);
+    return e;
+}
+
+/* Number of resonant ordered pairs and triples of field j (counts[0], counts[1]). */
+int or_apfc_counts(const or_apfc *p, int j, int *counts)
+{
+    if (!apfc_check(p) || j < 0 || j >= p->nfields) return OR_ERR_ARG;
+    apfc_terms terms[OR_APFC_MAX];
+    memset(terms, 0, sizeof terms);
+    int e = apfc_enumerate(p, terms);
+    if (!e) {
+        counts[0] = terms[j].nq;
+        counts[1] = terms[j].nc;
+    }
+    apfc_free(terms, p->nfields);
+    return e;
+}
+
+/* eta_hat_j = FFT(eta_j) for every field. */
+int or_apfc_state_init(const or_apfc *p, const double *eta, double *eta_hat)
+{
+    if (!apfc_check(p)) return OR_ERR_ARG;
+    const int64_t P = total_size(p->ndim, p->n);
+    memcpy(eta_hat, eta, sizeof(cplx) * (size_t)(P * p->nfields));
+    for (int j = 0; j < p->nfields; ++j) {
+        int e = fft_all_axes((cplx *)eta_hat + (int64_t)j * P, p->ndim, p->n, -1);
+        if (e) return e;
+    }
+    return OR_OK;
+}
+
+/* nsteps semi-implicit amplitude steps; eta (real space) and eta_hat (spectra) in place. */
+int or_apfc_step(const or_apfc *p, double *eta_d, double *eta_hat_d, int64_t nsteps)
+{
+    if (!apfc_check(p) || nsteps < 0) return OR_ERR_ARG;
+    const int ndim = p->ndim, N = p->nfields;
+    const int64_t P = total_size(ndim, p->n);
+    cplx *eta = (cplx *)eta_d, *S = (cplx *)eta_hat_d;
+    cplx *nl = (cplx *)malloc(sizeof(cplx) * (size_t)(P * N));
+    apfc_terms terms[OR_APFC_MAX];
+    memset(terms, 0, sizeof terms);
+    int e = nl ? apfc_enumerate(p, terms) : OR_ERR_MEM;
+    for (int64_t st = 0; st < nsteps && !e; ++st) {
+        apfc_nonlinear_terms(p, terms, eta, nl);
+        for (int j = 0; j < N && !e; ++j) e = fft_all_axes(nl + (int64_t)j * P, ndim, p->n, -1);
+        if (e) break;
+        for (int j = 0; j < N; ++j) {
+            double kk = 0.0;
+            for (int a = 0; a < ndim; ++a) kk += p->kvec[j][a] * p->kvec[j][a];
+#pragma omp parallel for schedule(static)
+            for (int64_t i = 0; i < P; ++i) {
+                int64_t m[3] = {0, 0, 0};
+                unflatten(i, ndim, p->n, m);
+                double q2 = 0.0, kq = 0.0;
+                for (int a = 0; a < ndim; ++a) {
+                    double qa = apfc_wavenumber(m[a], p->n[a], p->dx[a]);
+                    q2 += qa * qa;
+                    kq += p->kvec[j][a] * qa;
+                }
+                double G = -(q2 + 2.0 * kq);
+                int64_t o = (int64_t)j * P + i;
+                S[o] = (S[o] - p->dt * kk * nl[o]) / (1.0 + p->dt * kk * (p->dB + p->Bx * G * G));
+            }
+        }
+        memcpy(eta, S, sizeof(cplx) * (size_t)(P * N));
+        for (int j = 0; j < N && !e; ++j) e = fft_all_axes(eta + (int64_t)j * P, ndim, p->n, 1);
+        const double inv = 1.0 / (double)P;
+#pragma omp parallel for schedule(static)
+        for (int64_t i = 0; i < P * N; ++i) eta[i] *= inv;
+    }
+    apfc_free(terms, N);
+    free(nl);
     return e;
 }
 

@@ -142,3 +142,54 @@ def normal_torch(seed: int, shape, dtype, device, chunk: int = 1 << 25):
 def pfc_initial_field_torch(seed: int, shape, mean: float, dtype, device, amplitude: float = 0.1):
     """Same values as ``pfc_initial_field`` (rounded once to ``dtype``), drawn on ``device``."""
     return uniform_torch(seed, shape, -amplitude, amplitude, dtype, device, offset=mean)
+
+
+# ---------------------------------------------------------------------------- amplitude fields
+# Inputs of the complex-amplitude form: principal reciprocal-lattice vectors (components along the
+# grid axes, slowest axis first; unit length for the first shell) and seeded complex amplitudes.
+
+_S3 = math.sqrt(3.0) / 2.0
+_R2 = 1.0 / math.sqrt(2.0)
+_R3 = 1.0 / math.sqrt(3.0)
+LATTICES = {
+    # 2D (y, x): one shell of the triangular lattice (k1 + k2 + k3 = 0), and the square lattice
+    "triangular": [(-0.5, -_S3), (1.0, 0.0), (-0.5, _S3)],
+    "square": [(1.0, 0.0), (0.0, 1.0)],
+    # 2D two shells of the triangular lattice: |k| = 1 and |k| = sqrt(3)
+    "triangular2": [(-0.5, -_S3), (1.0, 0.0), (-0.5, _S3), (1.5, _S3), (-1.5, _S3), (0.0, -2.0 * _S3)],
+    # 3D (z, y, x): bcc, the six <110> vectors of unit length
+    "bcc": [(0.0, _R2, _R2), (0.0, _R2, -_R2), (_R2, 0.0, _R2), (_R2, 0.0, -_R2), (_R2, _R2, 0.0),
+            (_R2, -_R2, 0.0)],
+    # 3D fcc, two shells: four <111> of unit length and three <200> of length 2/sqrt(3)
+    "fcc2": [(_R3, _R3, _R3), (_R3, -_R3, -_R3), (-_R3, _R3, -_R3), (-_R3, -_R3, _R3),
+             (2 * _R3, 0.0, 0.0), (0.0, 2 * _R3, 0.0), (0.0, 0.0, 2 * _R3)],
+}
+
+
+def lattice_vectors(name: str) -> np.ndarray:
+    """[N][ndim] principal wave vectors of a named lattice."""
+    return np.array(LATTICES[name], dtype=np.float64)
+
+
+def amplitude_fields(seed: int, nfields: int, shape, mean: float, amplitude: float = 0.02) -> np.ndarray:
+    """[nfields, *shape] complex amplitudes: mean + U(-a, a) + i U(-a, a), field j drawn from the
+    sub-streams 2j (real part) and 2j + 1 (imaginary part) of ``seed``."""
+    out = np.empty((nfields,) + tuple(shape), np.complex128)
+    for j in range(nfields):
+        out[j].real = mean + uniform(derive_seed(seed, 2 * j), shape, -amplitude, amplitude)
+        out[j].imag = uniform(derive_seed(seed, 2 * j + 1), shape, -amplitude, amplitude)
+    return out
+
+
+def amplitude_fields_torch(seed: int, nfields: int, shape, mean: float, cdtype, device, amplitude: float = 0.02):
+    """Same values as ``amplitude_fields`` (each part rounded once), drawn on ``device``."""
+    import torch
+
+    rdt = torch.float32 if cdtype == torch.complex64 else torch.float64
+    out = torch.empty((nfields,) + tuple(shape), dtype=cdtype, device=device)
+    for j in range(nfields):
+        re = uniform_torch(derive_seed(seed, 2 * j), shape, -amplitude, amplitude, rdt, device, offset=mean)
+        im = uniform_torch(derive_seed(seed, 2 * j + 1), shape, -amplitude, amplitude, rdt, device)
+        out[j] = torch.complex(re, im)
+        del re, im
+    return out
