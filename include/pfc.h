@@ -246,6 +246,61 @@ int pfc_batch_grid(const pfc_batch *b);
 
 pfc_status pfc_batch_destroy(pfc_batch *b);
 
+/* ---- Complex-amplitude form (the amplitude extension named at the end of the multiphysics
+ * section; the paper gives no equations, so the standard amplitude expansion of the PFC energy is
+ * taken) -------------------------------------------------------------------------------------------
+ * The density is psi = sum_j eta_j e^{i k_j.r} + c.c. over N principal wave vectors k_j; the complex
+ * amplitudes eta_j (N fields on one 2D or 3D periodic grid) follow
+ *     d_t eta_j = -|k_j|^2 [ (dB + Bx G_j^2) eta_j + N_j ],   G_j = lap + 2 i k_j.grad,
+ * where N_j is the resonant part of -t psi^2 + v psi^3 at k_j: the sum of -t eta_a eta_b over ordered
+ * pairs with k_a + k_b = k_j and of v eta_a eta_b eta_c over ordered triples with k_a + k_b + k_c =
+ * k_j, indices over +-1 .. +-N with k_{-a} = -k_a and eta_{-a} = conj(eta_a) (a vector sum matches
+ * when it is within 1e-9 max|k| of k_j).  With dB = r, Bx = 1, t = 0, v = 1 this is the expansion of
+ * the energy of Eq. (3).  One step (Listing 1's update applied to every amplitude):
+ *     eta_hat_j <- (eta_hat_j - dt |k_j|^2 FFT(N_j)) / (1 + dt |k_j|^2 (dB + Bx G_j^2)),
+ *     eta_j = IFFT(eta_hat_j),       in Fourier space G_j = -(|q|^2 + 2 k_j.q),
+ * q on numpy's fftfreq grid (the Nyquist index counts as -n/2; G_j is odd in q).
+ * Layout: N complex grids back to back (field j at j * n0 n1 n2 elements), C order, interleaved
+ * (re, im) in the plan's dtype; spectra in natural FFT order, same layout.  Unnormalised forward
+ * transform, inverse with 1/(n0 n1 n2). */
+#define PFC_APFC_MAX_FIELDS 32
+typedef struct pfc_apfc pfc_apfc;
+typedef struct {
+    int ndim;                           /* 2 or 3 */
+    int64_t n[3];                       /* grid, slowest axis first; each a power of two in [4, 2048]
+                                           or one of 6, 10, 12, 14, 20, 30, 60, 150, 700, 750, 1400 */
+    double dx[3];                       /* grid spacing per axis, > 0 */
+    pfc_dtype dtype;
+    int nfields;                        /* N, 1 .. PFC_APFC_MAX_FIELDS */
+    double k[PFC_APFC_MAX_FIELDS][3];   /* k[j][a]: component of k_j along grid axis a (a < ndim) */
+    double dB, Bx, t, v;                /* energy coefficients; Bx >= 0 */
+    double dt;                          /* time step, > 0, with 1 + dt |k_j|^2 dB > 0 for every j */
+    int device;                         /* HIP device of every pointer passed to this object */
+} pfc_apfc_desc;
+
+/* Validate the descriptor, find the resonant products of every amplitude (host memory only). */
+pfc_status pfc_apfc_create(pfc_apfc **out, const pfc_apfc_desc *d);
+/* Bytes of the N fields (and of the N spectra): N n0 n1 n2 complex values. */
+size_t pfc_apfc_field_bytes(const pfc_apfc *p);
+/* Device workspace bytes: twiddles, the product table, one scratch copy of the fields. */
+size_t pfc_apfc_workspace_bytes(const pfc_apfc *p);
+/* Attach a caller-owned device workspace (256-byte aligned); uploads the tables (synchronous). */
+pfc_status pfc_apfc_set_workspace(pfc_apfc *p, void *dev_ptr, size_t bytes);
+/* Number of distinct products in N_j: pairs (t terms) and triples (v terms); products whose
+ * coefficient is zero are dropped. */
+pfc_status pfc_apfc_terms(const pfc_apfc *p, int j, int *npairs, int *ntriples);
+/* Complex FFT of every field over all axes, dir = -1 forward (unnormalised) or +1 inverse (times
+ * 1/(n0 n1 n2)); in may equal out. */
+pfc_status pfc_apfc_fft(pfc_apfc *p, const void *in, void *out, int dir, void *stream);
+/* out_j = N_j at every point (out must not overlap eta). */
+pfc_status pfc_apfc_nonlinear(pfc_apfc *p, const void *eta, void *out, void *stream);
+/* eta_hat = forward FFT of eta (the state of the step). */
+pfc_status pfc_apfc_state_init(pfc_apfc *p, const void *eta, void *eta_hat, void *stream);
+/* Advance nsteps >= 0 steps; eta (real-space amplitudes) and eta_hat (their spectra) are updated
+ * in place and must not overlap. */
+pfc_status pfc_apfc_step(pfc_apfc *p, void *eta, void *eta_hat, int64_t nsteps, void *stream);
+pfc_status pfc_apfc_destroy(pfc_apfc *p);
+
 const char *pfc_status_string(pfc_status st);
 const char *pfc_last_error(void);
 

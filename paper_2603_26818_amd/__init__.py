@@ -13,12 +13,18 @@ from ._binding import (  # noqa: F401
     PFC_FLAG_LINEAR_ONLY,
     PFC_ONE_MODE,
     PFC_TWO_MODE,
+    Apfc,
     Batch,
     HydroParams,
     PfcError,
     Plan,
     library_path,
     load_library,
+    pfc_apfc_create,
+    pfc_apfc_fft,
+    pfc_apfc_nonlinear,
+    pfc_apfc_state_init,
+    pfc_apfc_step,
     pfc_energy,
     pfc_fft_c2r,
     pfc_fft_r2c,

@@ -50,6 +50,26 @@ class PlanDesc(ctypes.Structure):
     ]
 
 
+APFC_MAX_FIELDS = 32
+
+
+class ApfcDesc(ctypes.Structure):
+    _fields_ = [
+        ("ndim", ctypes.c_int),
+        ("n", ctypes.c_int64 * 3),
+        ("dx", ctypes.c_double * 3),
+        ("dtype", ctypes.c_int),
+        ("nfields", ctypes.c_int),
+        ("k", (ctypes.c_double * 3) * APFC_MAX_FIELDS),
+        ("dB", ctypes.c_double),
+        ("Bx", ctypes.c_double),
+        ("t", ctypes.c_double),
+        ("v", ctypes.c_double),
+        ("dt", ctypes.c_double),
+        ("device", ctypes.c_int),
+    ]
+
+
 _SIGS = {
     "pfc_plan_create": (ctypes.c_int, [ctypes.POINTER(ctypes.c_void_p), ctypes.POINTER(PlanDesc)]),
     "pfc_plan_workspace_bytes": (ctypes.c_size_t, [ctypes.c_void_p]),
@@ -89,6 +109,17 @@ _SIGS = {
     "pfc_batch_get_tuning": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_int), ctypes.c_int]),
     "pfc_batch_set_tuning": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_int), ctypes.c_int]),
     "pfc_batch_destroy": (ctypes.c_int, [ctypes.c_void_p]),
+    "pfc_apfc_create": (ctypes.c_int, [ctypes.POINTER(ctypes.c_void_p), ctypes.POINTER(ApfcDesc)]),
+    "pfc_apfc_field_bytes": (ctypes.c_size_t, [ctypes.c_void_p]),
+    "pfc_apfc_workspace_bytes": (ctypes.c_size_t, [ctypes.c_void_p]),
+    "pfc_apfc_set_workspace": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t]),
+    "pfc_apfc_terms": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.POINTER(ctypes.c_int),
+                                      ctypes.POINTER(ctypes.c_int)]),
+    "pfc_apfc_fft": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p]),
+    "pfc_apfc_nonlinear": (ctypes.c_int, [ctypes.c_void_p] * 4),
+    "pfc_apfc_state_init": (ctypes.c_int, [ctypes.c_void_p] * 4),
+    "pfc_apfc_step": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p]),
+    "pfc_apfc_destroy": (ctypes.c_int, [ctypes.c_void_p]),
     "pfc_status_string": (ctypes.c_char_p, [ctypes.c_int]),
     "pfc_last_error": (ctypes.c_char_p, []),
 }
@@ -571,3 +602,119 @@ def pfc_hydro_state_init(plan: Plan, psi, v, psi_state=None, v_state=None):
 
 def pfc_hydro_step(plan: Plan, psi, psi_state, v, v_state, nsteps=1, rho0=1.0, gamma=1.0, a0=1.0, work=None):
     return plan.hydro_step(psi, psi_state, v, v_state, nsteps, rho0, gamma, a0, work)
+
+
+class Apfc:
+    """A pfc_apfc object (complex-amplitude form) with its workspace (a torch uint8 tensor).
+    Fields and spectra are complex tensors of shape (N, *shape)."""
+
+    def __init__(self, shape, kvec, dtype="f32", dx=math.pi / 2, dB=-0.15, Bx=1.0, t=0.0, v=1.0, dt=0.5, device=0):
+        torch = _torch()
+        lib = load_library()
+        shape = tuple(int(s) for s in shape)
+        kvec = [[float(c) for c in row] for row in kvec]
+        d = ApfcDesc()
+        d.ndim = len(shape)
+        dxs = tuple(dx) if isinstance(dx, (tuple, list)) else (dx,) * len(shape)
+        for a in range(3):
+            d.n[a] = shape[a] if a < len(shape) else 1
+            d.dx[a] = float(dxs[a]) if a < len(shape) else 1.0
+        self.f64 = dtype in ("f64", "float64", PFC_F64)
+        d.dtype = PFC_F64 if self.f64 else PFC_F32
+        if not 1 <= len(kvec) <= APFC_MAX_FIELDS:
+            raise ValueError(f"need 1..{APFC_MAX_FIELDS} wave vectors")
+        d.nfields = len(kvec)
+        for j, row in enumerate(kvec):
+            if len(row) != len(shape):
+                raise ValueError("each wave vector needs one component per grid axis")
+            for a, c in enumerate(row):
+                d.k[j][a] = c
+        d.dB, d.Bx, d.t, d.v, d.dt = float(dB), float(Bx), float(t), float(v), float(dt)
+        d.device = int(device)
+        h = ctypes.c_void_p()
+        _check(lib.pfc_apfc_create(ctypes.byref(h), ctypes.byref(d)), "pfc_apfc_create")
+        self._h, self._lib = h, lib
+        self.shape = shape
+        self.nfields = len(kvec)
+        self.field_shape = (self.nfields,) + shape
+        self.device = torch.device("cuda", int(device))
+        self.complex_dtype = torch.complex128 if self.f64 else torch.complex64
+        nbytes = lib.pfc_apfc_workspace_bytes(h)
+        self.workspace = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+        if self.workspace.data_ptr() % 256:
+            raise PfcError(3, "Apfc", "workspace tensor is not 256-byte aligned")
+        _check(lib.pfc_apfc_set_workspace(h, ctypes.c_void_p(self.workspace.data_ptr()), nbytes),
+               "pfc_apfc_set_workspace")
+
+    def _fields(self, x, name):
+        torch = _torch()
+        if not isinstance(x, torch.Tensor):
+            raise TypeError(f"{name} must be a torch.Tensor")
+        if x.device != self.device or x.dtype != self.complex_dtype:
+            raise TypeError(f"{name} must be {self.complex_dtype} on {self.device}")
+        if tuple(x.shape) != self.field_shape or not x.is_contiguous():
+            raise ValueError(f"{name} must be a contiguous tensor of shape {self.field_shape}")
+        return ctypes.c_void_p(x.data_ptr())
+
+    def empty(self):
+        return _torch().empty(self.field_shape, dtype=self.complex_dtype, device=self.device)
+
+    def terms(self, j):
+        np_, nt_ = ctypes.c_int(), ctypes.c_int()
+        _check(self._lib.pfc_apfc_terms(self._h, int(j), ctypes.byref(np_), ctypes.byref(nt_)), "pfc_apfc_terms")
+        return np_.value, nt_.value
+
+    def fft(self, x, dir=-1, out=None):
+        out = self.empty() if out is None else out
+        _check(self._lib.pfc_apfc_fft(self._h, self._fields(x, "in"), self._fields(out, "out"), int(dir),
+                                      _stream_ptr(self.device)), "pfc_apfc_fft")
+        return out
+
+    def nonlinear(self, eta, out=None):
+        out = self.empty() if out is None else out
+        _check(self._lib.pfc_apfc_nonlinear(self._h, self._fields(eta, "eta"), self._fields(out, "out"),
+                                            _stream_ptr(self.device)), "pfc_apfc_nonlinear")
+        return out
+
+    def state_init(self, eta, eta_hat=None):
+        eta_hat = self.empty() if eta_hat is None else eta_hat
+        _check(self._lib.pfc_apfc_state_init(self._h, self._fields(eta, "eta"), self._fields(eta_hat, "eta_hat"),
+                                             _stream_ptr(self.device)), "pfc_apfc_state_init")
+        return eta_hat
+
+    def step(self, eta, eta_hat, nsteps=1):
+        _check(self._lib.pfc_apfc_step(self._h, self._fields(eta, "eta"), self._fields(eta_hat, "eta_hat"),
+                                       int(nsteps), _stream_ptr(self.device)), "pfc_apfc_step")
+        return eta, eta_hat
+
+    def destroy(self):
+        h = getattr(self, "_h", None)
+        if h is not None and h.value:
+            self._lib.pfc_apfc_destroy(h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.destroy()
+        except Exception:
+            pass
+
+
+def pfc_apfc_create(shape, kvec, **kw) -> Apfc:
+    return Apfc(shape, kvec, **kw)
+
+
+def pfc_apfc_state_init(obj: Apfc, eta, eta_hat=None):
+    return obj.state_init(eta, eta_hat)
+
+
+def pfc_apfc_step(obj: Apfc, eta, eta_hat, nsteps=1):
+    return obj.step(eta, eta_hat, nsteps)
+
+
+def pfc_apfc_fft(obj: Apfc, x, dir=-1, out=None):
+    return obj.fft(x, dir, out)
+
+
+def pfc_apfc_nonlinear(obj: Apfc, eta, out=None):
+    return obj.nonlinear(eta, out)

@@ -1,0 +1,75 @@
+// apfc.hip -- launchers of the complex-amplitude kernels (apfc.hpp), FP32 and FP64.
+#include "apfc.hpp"
+#include "apfc_launch.hpp"
+#include "dispatch_impl.hpp"
+
+namespace pfc {
+
+template <typename T>
+hipError_t launch_apfc_nonlin(const cx<T> *eta, cx<T> *out, int64_t P, int nf, const ApfcTerm *terms, const int *off,
+                              hipStream_t s)
+{
+    if (nf < 1 || nf > kApfcMaxFields) return hipErrorInvalidValue;
+    const size_t lds = (size_t)nf * kApfcThreads * sizeof(cx<T>);
+    hipLaunchKernelGGL(apfc_nonlin_kernel<T>, dim3((unsigned)cdiv(P, kApfcThreads)), dim3(kApfcThreads), lds, s, eta,
+                       out, P, nf, terms, off);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_apfc_rows(int64_t L, const cx<T> *in, cx<T> *out, int64_t nrows, int dir, double scale, bool nt,
+                            const cx<T> *tw, int lt_shift, hipStream_t s)
+{
+    return by_length(L, [&](auto Lc) -> hipError_t {
+        constexpr int LL = decltype(Lc)::value;
+        if constexpr (LL < 4) {
+            return hipErrorInvalidValue;
+        } else {
+            using PL = typename DefaultPlan<LL>::type;
+            constexpr int ROWS = XRows<PL>::value;
+            const dim3 grid((unsigned)cdiv(nrows, ROWS)), block(ROWS * PL::Tp);
+            return with_nt(nt, [&](auto ntc) -> hipError_t {
+                constexpr bool NT = decltype(ntc)::value;
+                if (dir < 0)
+                    hipLaunchKernelGGL((apfc_row_kernel<T, PL, ROWS, -1, NT>), grid, block, 0, s, in, out, nrows, tw,
+                                       lt_shift, (T)scale);
+                else
+                    hipLaunchKernelGGL((apfc_row_kernel<T, PL, ROWS, +1, NT>), grid, block, 0, s, in, out, nrows, tw,
+                                       lt_shift, (T)scale);
+                return hipGetLastError();
+            });
+        }
+    });
+}
+
+template <typename T>
+hipError_t launch_apfc_last_step(int64_t L, int nf, ApfcStepArgs<T> a, hipStream_t s)
+{
+    return by_length(L, [&](auto Lc) -> hipError_t {
+        constexpr int LL = decltype(Lc)::value;
+        if constexpr (LL < 4) {
+            return hipErrorInvalidValue;
+        } else {
+            using TL = PencilTile<T, LL>;
+            using PL = SpreadIf<typename AxisPlan<LL>::type, TL::E>;
+            constexpr int WM = TL::W;
+            constexpr bool PF = is_pow2c(LL) && PL::Rmax <= 16;  // state prefetch while registers allow
+            a.W = (int)(a.ncols < WM ? a.ncols : WM);
+            a.tiles = cdiv(a.ncols, a.W);
+            const dim3 grid((unsigned)(a.tiles * nf)), block(WM * PL::Tp);
+            hipLaunchKernelGGL((apfc_last_step_kernel<T, PL, WM, PF, TL::G>), grid, block, 0, s, a);
+            return hipGetLastError();
+        }
+    });
+}
+
+#define PFC_APFC_INSTANTIATE(T)                                                                                   \
+    template hipError_t launch_apfc_nonlin<T>(const cx<T> *, cx<T> *, int64_t, int, const ApfcTerm *, const int *, \
+                                              hipStream_t);                                                        \
+    template hipError_t launch_apfc_rows<T>(int64_t, const cx<T> *, cx<T> *, int64_t, int, double, bool,          \
+                                            const cx<T> *, int, hipStream_t);                                      \
+    template hipError_t launch_apfc_last_step<T>(int64_t, int, ApfcStepArgs<T>, hipStream_t);
+PFC_APFC_INSTANTIATE(float)
+PFC_APFC_INSTANTIATE(double)
+
+}  // namespace pfc

@@ -16,6 +16,7 @@
 #include <vector>
 
 #include "fft_core.hpp"
+#include "apfc_launch.hpp"
 #include "launch.hpp"
 #include "types.hpp"
 
@@ -1385,5 +1386,419 @@ const char *pfc_status_string(pfc_status st)
 }
 
 const char *pfc_last_error(void) { return g_last_error.c_str(); }
+
+}  // extern "C"
+
+// ------------------------------------------------------------------------------------------------
+// Complex-amplitude form (contract in include/pfc.h; kernels in apfc.hpp).
+
+struct pfc_apfc {
+    pfc_apfc_desc d;
+    int64_t n0, n1, nx, P;  // 2D: n1 = 1
+    double fk[3];           // 2 pi / (n dx) along (axis 0, axis 1, x)
+    int lt_shift = 0;
+    bool nt = false;
+    int64_t tw_x = 0, tw_y = 0, tw_last = 0;
+    size_t tw_entries = 0;
+    std::vector<pfc::ApfcTerm> terms;
+    std::vector<int> off;   // terms of field j: [off[j], off[j+1])
+    std::vector<int> npairs, ntriples;
+    size_t tw_off = 0, terms_off = 0, off_off = 0, scratch_off = 0, ws_need = 0;
+    char *ws = nullptr;
+};
+
+namespace {
+
+size_t apfc_cx(const pfc_apfc *p) { return p->d.dtype == PFC_F64 ? 16 : 8; }
+size_t apfc_field_bytes(const pfc_apfc *p) { return (size_t)p->P * (size_t)p->d.nfields * apfc_cx(p); }
+
+bool apfc_length_ok(int64_t n) { return (is_pow2(n) && n >= 4 && n <= 2048) || (pfc::mixed_length(n) && n % 2 == 0); }
+
+// Resonant products of every amplitude.  Signed index s = +-(f+1); k_{-a} = -k_a.  Ordered tuples
+// whose vector sum is within tol of k_j are counted per unordered product, and the count becomes
+// the product's multiplicity.
+void apfc_products(pfc_apfc *p)
+{
+    const pfc_apfc_desc &d = p->d;
+    const int N = d.nfields, nd = d.ndim;
+    double kmax = 0.0;
+    for (int j = 0; j < N; ++j) {
+        double kk = 0.0;
+        for (int a = 0; a < nd; ++a) kk += d.k[j][a] * d.k[j][a];
+        kmax = std::max(kmax, std::sqrt(kk));
+    }
+    const double tol = 1e-9 * kmax;
+    std::vector<int> sig;
+    for (int f = 1; f <= N; ++f) {
+        sig.push_back(f);
+        sig.push_back(-f);
+    }
+    auto comp = [&](int s, int a) { return s > 0 ? d.k[s - 1][a] : -d.k[-s - 1][a]; };
+    p->terms.clear();
+    p->off.assign(1, 0);
+    p->npairs.clear();
+    p->ntriples.clear();
+    for (int j = 0; j < N; ++j) {
+        auto hits = [&](const int *s, int len) {
+            for (int a = 0; a < nd; ++a) {
+                double sum = 0.0;
+                for (int i = 0; i < len; ++i) sum += comp(s[i], a);
+                if (std::fabs(sum - d.k[j][a]) > tol) return false;
+            }
+            return true;
+        };
+        std::map<std::vector<int>, int> pairs, triples;
+        for (int x : sig)
+            for (int y : sig) {
+                const int s2[2] = {x, y};
+                if (hits(s2, 2)) {
+                    std::vector<int> key(s2, s2 + 2);
+                    std::sort(key.begin(), key.end());
+                    ++pairs[key];
+                }
+                for (int z : sig) {
+                    const int s3[3] = {x, y, z};
+                    if (hits(s3, 3)) {
+                        std::vector<int> key(s3, s3 + 3);
+                        std::sort(key.begin(), key.end());
+                        ++triples[key];
+                    }
+                }
+            }
+        int np = 0, nt = 0;
+        if (d.t != 0.0)
+            for (auto &kv : pairs) {
+                pfc::ApfcTerm m{};
+                m.a = (int16_t)kv.first[0];
+                m.b = (int16_t)kv.first[1];
+                m.c = 0;
+                m.coef = -d.t * kv.second;
+                m.coef32 = (float)m.coef;
+                p->terms.push_back(m);
+                ++np;
+            }
+        if (d.v != 0.0)
+            for (auto &kv : triples) {
+                pfc::ApfcTerm m{};
+                m.a = (int16_t)kv.first[0];
+                m.b = (int16_t)kv.first[1];
+                m.c = (int16_t)kv.first[2];
+                m.coef = d.v * kv.second;
+                m.coef32 = (float)m.coef;
+                p->terms.push_back(m);
+                ++nt;
+            }
+        p->npairs.push_back(np);
+        p->ntriples.push_back(nt);
+        p->off.push_back((int)p->terms.size());
+    }
+}
+
+pfc_status apfc_validate(const pfc_apfc_desc *d)
+{
+    if (d->ndim != 2 && d->ndim != 3) return fail(PFC_ERR_INVALID_ARG, "ndim must be 2 or 3");
+    if (d->dtype != PFC_F32 && d->dtype != PFC_F64) return fail(PFC_ERR_INVALID_ARG, "bad dtype");
+    for (int a = 0; a < d->ndim; ++a) {
+        if (!apfc_length_ok(d->n[a]))
+            return fail(PFC_ERR_UNSUPPORTED, "axis %d: length %lld has no compiled schedule", a, (long long)d->n[a]);
+        if (!(d->dx[a] > 0.0) || !std::isfinite(d->dx[a])) return fail(PFC_ERR_INVALID_ARG, "dx[%d] must be > 0", a);
+    }
+    if (d->nfields < 1 || d->nfields > PFC_APFC_MAX_FIELDS)
+        return fail(PFC_ERR_INVALID_ARG, "nfields must be in [1, %d]", PFC_APFC_MAX_FIELDS);
+    if (!(d->dt > 0.0) || !std::isfinite(d->dt)) return fail(PFC_ERR_INVALID_ARG, "dt must be > 0");
+    if (!(d->Bx >= 0.0) || !std::isfinite(d->Bx)) return fail(PFC_ERR_INVALID_ARG, "Bx must be >= 0");
+    if (!std::isfinite(d->dB) || !std::isfinite(d->t) || !std::isfinite(d->v))
+        return fail(PFC_ERR_INVALID_ARG, "dB, t, v must be finite");
+    for (int j = 0; j < d->nfields; ++j) {
+        double kk = 0.0;
+        for (int a = 0; a < d->ndim; ++a) {
+            if (!std::isfinite(d->k[j][a])) return fail(PFC_ERR_INVALID_ARG, "k[%d] is not finite", j);
+            kk += d->k[j][a] * d->k[j][a];
+        }
+        if (!(kk > 0.0)) return fail(PFC_ERR_INVALID_ARG, "k[%d] is zero", j);
+        // the denominator 1 + dt |k|^2 (dB + Bx G^2) is smallest at G = 0 (Bx >= 0)
+        if (!(1.0 + d->dt * kk * d->dB > 0.0))
+            return fail(PFC_ERR_INVALID_ARG, "1 + dt |k_%d|^2 dB <= 0: dt too large for this dB", j);
+    }
+    return PFC_OK;
+}
+
+pfc_status apfc_ready(const pfc_apfc *p)
+{
+    if (!p) return fail(PFC_ERR_INVALID_ARG, "object is NULL");
+    if (!p->ws) return fail(PFC_ERR_WORKSPACE, "no workspace attached (pfc_apfc_set_workspace)");
+    return PFC_OK;
+}
+
+// the y pass and the FFT-only last-axis pass reuse the PFC pencil launchers through a geometry
+// that treats the fields as extra planes
+pfc::Geom apfc_y_geom(const pfc_apfc *p)
+{
+    pfc::Geom g{};
+    g.ndim = 3;
+    g.n0 = (int64_t)p->d.nfields * p->n0;
+    g.n1 = p->n1;
+    g.nx = p->nx;
+    g.M = p->nx;
+    g.nrows = p->n1;
+    g.xrows = g.n0 * g.nrows;
+    g.lt_shift = p->lt_shift;
+    g.nt = p->nt;
+    g.tw_y = p->tw_y;
+    return g;
+}
+pfc::Geom apfc_last_geom(const pfc_apfc *p)
+{
+    pfc::Geom g{};
+    g.ndim = p->d.ndim;
+    g.n0 = p->n0;
+    g.n1 = p->n1;
+    g.nx = p->nx;
+    g.M = p->nx;
+    g.nrows = p->n1;
+    g.xrows = g.n0 * g.nrows;
+    g.lt_shift = p->lt_shift;
+    g.tw_last = p->tw_last;
+    return g;
+}
+
+template <typename T>
+const cx<T> *apfc_tw(const pfc_apfc *p)
+{
+    return reinterpret_cast<const cx<T> *>(p->ws + p->tw_off);
+}
+
+template <typename T>
+pfc_status do_apfc_fft(pfc_apfc *p, const void *in_v, void *out_v, int dir, hipStream_t s)
+{
+    const cx<T> *in = (const cx<T> *)in_v;
+    cx<T> *out = (cx<T> *)out_v;
+    const cx<T> *tw = apfc_tw<T>(p);
+    const int N = p->d.nfields;
+    const int64_t rows = (int64_t)N * p->n0 * p->n1;
+    const pfc::Geom gy = apfc_y_geom(p), gl = apfc_last_geom(p);
+    if (dir < 0) {
+        PFC_TRY(pfc::launch_apfc_rows<T>(p->nx, in, out, rows, -1, 1.0, p->nt, tw + p->tw_x, p->lt_shift, s),
+                "x forward launch");
+        if (p->d.ndim == 3) PFC_TRY(pfc::launch_y_c2c<T>(gy, out, -1, tw, s), "y forward launch");
+        for (int f = 0; f < N; ++f)
+            PFC_TRY(pfc::launch_last_c2c<T>(gl, out + f * p->P, out + f * p->P, -1, tw, s), "last-axis forward launch");
+    } else {
+        for (int f = 0; f < N; ++f)
+            PFC_TRY(pfc::launch_last_c2c<T>(gl, in + f * p->P, out + f * p->P, +1, tw, s), "last-axis inverse launch");
+        if (p->d.ndim == 3) PFC_TRY(pfc::launch_y_c2c<T>(gy, out, +1, tw, s), "y inverse launch");
+        PFC_TRY(pfc::launch_apfc_rows<T>(p->nx, out, out, rows, +1, 1.0 / (double)p->P, p->nt, tw + p->tw_x,
+                                         p->lt_shift, s),
+                "x inverse launch");
+    }
+    return PFC_OK;
+}
+
+template <typename T>
+pfc_status do_apfc_nonlinear(pfc_apfc *p, const void *eta, void *out, hipStream_t s)
+{
+    const pfc::ApfcTerm *terms = reinterpret_cast<const pfc::ApfcTerm *>(p->ws + p->terms_off);
+    const int *off = reinterpret_cast<const int *>(p->ws + p->off_off);
+    PFC_TRY(pfc::launch_apfc_nonlin<T>((const cx<T> *)eta, (cx<T> *)out, p->P, p->d.nfields, terms, off, s),
+            "nonlinearity launch");
+    return PFC_OK;
+}
+
+template <typename T>
+pfc_status do_apfc_step(pfc_apfc *p, void *eta_v, void *eta_hat_v, int64_t nsteps, hipStream_t s)
+{
+    cx<T> *eta = (cx<T> *)eta_v, *S = (cx<T> *)eta_hat_v;
+    cx<T> *scr = reinterpret_cast<cx<T> *>(p->ws + p->scratch_off);
+    const cx<T> *tw = apfc_tw<T>(p);
+    const pfc_apfc_desc &d = p->d;
+    const int N = d.nfields;
+    const int64_t rows = (int64_t)N * p->n0 * p->n1;
+    const pfc::Geom gy = apfc_y_geom(p);
+    pfc::ApfcStepArgs<T> a{};
+    a.src = scr;
+    a.dst = scr;
+    a.state = S;
+    a.ncols = p->n1 * p->nx;
+    a.nx = p->nx;
+    a.n1 = p->n1;
+    a.fstride = p->P;
+    for (int i = 0; i < 3; ++i) a.fk[i] = (T)p->fk[i];
+    a.dt = (T)d.dt;
+    a.dB = (T)d.dB;
+    a.Bx = (T)d.Bx;
+    for (int f = 0; f < N; ++f) {
+        // components along (axis 0, axis 1, x); axis 1 is absent in 2D
+        const double k0 = d.k[f][0], k1 = d.ndim == 3 ? d.k[f][1] : 0.0, kx = d.k[f][d.ndim - 1];
+        a.kv[f][0] = (T)k0;
+        a.kv[f][1] = (T)k1;
+        a.kv[f][2] = (T)kx;
+        a.kk[f] = (T)(k0 * k0 + k1 * k1 + kx * kx);
+    }
+    a.tw = tw + p->tw_last;
+    a.lt_shift = p->lt_shift;
+    for (int64_t st = 0; st < nsteps; ++st) {
+        pfc_status e = do_apfc_nonlinear<T>(p, eta, scr, s);
+        if (e) return e;
+        PFC_TRY(pfc::launch_apfc_rows<T>(p->nx, scr, scr, rows, -1, 1.0, p->nt, tw + p->tw_x, p->lt_shift, s),
+                "x forward launch");
+        if (d.ndim == 3) PFC_TRY(pfc::launch_y_c2c<T>(gy, scr, -1, tw, s), "y forward launch");
+        PFC_TRY(pfc::launch_apfc_last_step<T>(p->n0, N, a, s), "last-axis step launch");
+        if (d.ndim == 3) PFC_TRY(pfc::launch_y_c2c<T>(gy, scr, +1, tw, s), "y inverse launch");
+        PFC_TRY(pfc::launch_apfc_rows<T>(p->nx, scr, eta, rows, +1, 1.0 / (double)p->P, p->nt, tw + p->tw_x,
+                                         p->lt_shift, s),
+                "x inverse launch");
+    }
+    return PFC_OK;
+}
+
+pfc_status apfc_fields(const pfc_apfc *p, const void *a, const char *na, const void *b, const char *nb)
+{
+    for (auto pr : {std::make_pair(a, na), std::make_pair(b, nb)}) {
+        if (!pr.first) return fail(PFC_ERR_INVALID_ARG, "%s is NULL", pr.second);
+        if (!aligned16(pr.first)) return fail(PFC_ERR_ALIGNMENT, "%s is not 16-byte aligned", pr.second);
+        if (overlap(pr.first, apfc_field_bytes(p), p->ws, p->ws_need))
+            return fail(PFC_ERR_INVALID_ARG, "%s overlaps the workspace", pr.second);
+    }
+    return PFC_OK;
+}
+
+}  // namespace
+
+#define PFC_APFC_DISPATCH(p, fn, ...)                                              \
+    do {                                                                           \
+        DeviceGuard dg_((p)->d.device);                                            \
+        if (dg_.err != hipSuccess) return hip_fail(dg_.err, "hipSetDevice");       \
+        return (p)->d.dtype == PFC_F64 ? fn<double>(__VA_ARGS__) : fn<float>(__VA_ARGS__); \
+    } while (0)
+
+extern "C" {
+
+pfc_status pfc_apfc_create(pfc_apfc **out, const pfc_apfc_desc *d)
+{
+    if (!out) return fail(PFC_ERR_INVALID_ARG, "out is NULL");
+    *out = nullptr;
+    if (!d) return fail(PFC_ERR_INVALID_ARG, "descriptor is NULL");
+    PFC_CHECK(apfc_validate(d));
+    pfc_apfc *p = new (std::nothrow) pfc_apfc;
+    if (!p) return fail(PFC_ERR_INTERNAL, "out of host memory");
+    p->d = *d;
+    p->n0 = d->n[0];
+    p->n1 = d->ndim == 3 ? d->n[1] : 1;
+    p->nx = d->n[d->ndim - 1];
+    p->P = p->n0 * p->n1 * p->nx;
+    p->fk[0] = 2.0 * M_PI / ((double)d->n[0] * d->dx[0]);
+    p->fk[1] = d->ndim == 3 ? 2.0 * M_PI / ((double)d->n[1] * d->dx[1]) : 0.0;
+    p->fk[2] = 2.0 * M_PI / ((double)p->nx * d->dx[d->ndim - 1]);
+    int64_t Lt = std::max(p->n0, std::max(p->n1, p->nx));
+    while ((int64_t(1) << p->lt_shift) < Lt) ++p->lt_shift;
+    size_t tw_entries = twiddle_count(int64_t(1) << p->lt_shift);
+    std::vector<std::pair<int64_t, int64_t>> mixed;
+    auto table_of = [&](int64_t L) -> int64_t {
+        if (!pfc::mixed_length(L)) return 0;
+        for (auto &m : mixed)
+            if (m.first == L) return m.second;
+        mixed.emplace_back(L, (int64_t)tw_entries);
+        tw_entries += mix_table_entries(L);
+        return mixed.back().second;
+    };
+    p->tw_x = table_of(p->nx);
+    p->tw_y = d->ndim == 3 ? table_of(p->n1) : 0;
+    p->tw_last = table_of(p->n0);
+    p->tw_entries = tw_entries;
+    p->nt = apfc_field_bytes(p) >= kNonTemporalBytes;
+    apfc_products(p);
+    const size_t cs = apfc_cx(p);
+    p->tw_off = 0;
+    p->terms_off = align256(tw_entries * cs);
+    p->off_off = p->terms_off + align256(std::max<size_t>(1, p->terms.size()) * sizeof(pfc::ApfcTerm));
+    p->scratch_off = p->off_off + align256(p->off.size() * sizeof(int));
+    p->ws_need = p->scratch_off + align256(apfc_field_bytes(p));
+    *out = p;
+    return PFC_OK;
+}
+
+size_t pfc_apfc_field_bytes(const pfc_apfc *p) { return p ? apfc_field_bytes(p) : 0; }
+size_t pfc_apfc_workspace_bytes(const pfc_apfc *p) { return p ? p->ws_need : 0; }
+
+pfc_status pfc_apfc_set_workspace(pfc_apfc *p, void *dev_ptr, size_t bytes)
+{
+    if (!p) return fail(PFC_ERR_INVALID_ARG, "object is NULL");
+    if (!dev_ptr) return fail(PFC_ERR_INVALID_ARG, "workspace is NULL");
+    if (((uintptr_t)dev_ptr & 255u) != 0) return fail(PFC_ERR_ALIGNMENT, "workspace must be 256-byte aligned");
+    if (bytes < p->ws_need) return fail(PFC_ERR_WORKSPACE, "workspace has %zu bytes, needs %zu", bytes, p->ws_need);
+    std::vector<char> host(p->scratch_off, 0);
+    auto build = [&](auto tc) {
+        using T = decltype(tc);
+        std::vector<cx<T>> tw = twiddle_table<T>(int64_t(1) << p->lt_shift);
+        tw.resize(p->tw_entries);
+        const int64_t lens[3] = {p->nx, p->d.ndim == 3 ? p->n1 : 0, p->n0};
+        const int64_t offs[3] = {p->tw_x, p->tw_y, p->tw_last};
+        for (int i = 0; i < 3; ++i)
+            if (offs[i] > 0)
+                with_mixed_length(lens[i], [&](auto lc) { fill_mix_table<T, decltype(lc)::value>(tw.data() + offs[i]); });
+        std::memcpy(host.data() + p->tw_off, tw.data(), tw.size() * sizeof(cx<T>));
+    };
+    if (p->d.dtype == PFC_F64)
+        build(double{});
+    else
+        build(float{});
+    if (!p->terms.empty())
+        std::memcpy(host.data() + p->terms_off, p->terms.data(), p->terms.size() * sizeof(pfc::ApfcTerm));
+    std::memcpy(host.data() + p->off_off, p->off.data(), p->off.size() * sizeof(int));
+    DeviceGuard dg(p->d.device);
+    if (dg.err != hipSuccess) return hip_fail(dg.err, "hipSetDevice");
+    hipError_t e = hipMemcpy(dev_ptr, host.data(), host.size(), hipMemcpyHostToDevice);
+    if (e != hipSuccess) return hip_fail(e, "table upload");
+    p->ws = (char *)dev_ptr;
+    return PFC_OK;
+}
+
+pfc_status pfc_apfc_terms(const pfc_apfc *p, int j, int *npairs, int *ntriples)
+{
+    if (!p) return fail(PFC_ERR_INVALID_ARG, "object is NULL");
+    if (j < 0 || j >= p->d.nfields) return fail(PFC_ERR_INVALID_ARG, "field %d out of range", j);
+    if (npairs) *npairs = p->npairs[j];
+    if (ntriples) *ntriples = p->ntriples[j];
+    return PFC_OK;
+}
+
+pfc_status pfc_apfc_fft(pfc_apfc *p, const void *in, void *out, int dir, void *stream)
+{
+    PFC_CHECK(apfc_ready(p));
+    if (dir != -1 && dir != 1) return fail(PFC_ERR_INVALID_ARG, "dir must be -1 or +1");
+    PFC_CHECK(apfc_fields(p, in, "in", out, "out"));
+    if (in != out && overlap(in, apfc_field_bytes(p), out, apfc_field_bytes(p)))
+        return fail(PFC_ERR_INVALID_ARG, "in and out overlap without being equal");
+    PFC_APFC_DISPATCH(p, do_apfc_fft, p, in, out, dir, (hipStream_t)stream);
+}
+
+pfc_status pfc_apfc_nonlinear(pfc_apfc *p, const void *eta, void *out, void *stream)
+{
+    PFC_CHECK(apfc_ready(p));
+    PFC_CHECK(apfc_fields(p, eta, "eta", out, "out"));
+    if (overlap(eta, apfc_field_bytes(p), out, apfc_field_bytes(p))) return fail(PFC_ERR_INVALID_ARG, "eta and out overlap");
+    PFC_APFC_DISPATCH(p, do_apfc_nonlinear, p, eta, out, (hipStream_t)stream);
+}
+
+pfc_status pfc_apfc_state_init(pfc_apfc *p, const void *eta, void *eta_hat, void *stream)
+{
+    return pfc_apfc_fft(p, eta, eta_hat, -1, stream);
+}
+
+pfc_status pfc_apfc_step(pfc_apfc *p, void *eta, void *eta_hat, int64_t nsteps, void *stream)
+{
+    PFC_CHECK(apfc_ready(p));
+    if (nsteps < 0) return fail(PFC_ERR_INVALID_ARG, "nsteps < 0");
+    PFC_CHECK(apfc_fields(p, eta, "eta", eta_hat, "eta_hat"));
+    if (overlap(eta, apfc_field_bytes(p), eta_hat, apfc_field_bytes(p)))
+        return fail(PFC_ERR_INVALID_ARG, "eta and eta_hat overlap");
+    PFC_APFC_DISPATCH(p, do_apfc_step, p, eta, eta_hat, nsteps, (hipStream_t)stream);
+}
+
+pfc_status pfc_apfc_destroy(pfc_apfc *p)
+{
+    delete p;
+    return PFC_OK;
+}
 
 }  // extern "C"

@@ -136,3 +136,106 @@ def test_tuning_set_get_validation():
     st, h = _create(b, lib, _desc(b, (8, 4, 8), 0))  # lengths with a single candidate
     assert lib.pfc_plan_set_tuning(h, (ctypes.c_int * 5)(0, 0, 1, 0, 0), 5) == 1
     lib.pfc_plan_destroy(h)
+
+
+# ---------------------------------------------------------------- complex-amplitude form
+def _apfc_desc(b, shape=(64, 64), kvec=None, dtype=0, dB=-0.15, Bx=1.0, t=0.3, v=1.0, dt=0.5, dx=math.pi / 2):
+    import pfc_inputs as P
+
+    kvec = P.lattice_vectors("triangular") if kvec is None else kvec
+    d = b.ApfcDesc()
+    d.ndim = len(shape)
+    for a in range(3):
+        d.n[a] = shape[a] if a < len(shape) else 1
+        d.dx[a] = dx if a < len(shape) else 1.0
+    d.dtype = dtype
+    d.nfields = len(kvec)
+    for j, row in enumerate(kvec):
+        for a, c in enumerate(row):
+            d.k[j][a] = float(c)
+    d.dB, d.Bx, d.t, d.v, d.dt, d.device = dB, Bx, t, v, dt, 0
+    return d
+
+
+def _apfc_create(lib, d):
+    h = ctypes.c_void_p()
+    return lib.pfc_apfc_create(ctypes.byref(h), ctypes.byref(d)), h
+
+
+def test_apfc_struct_layout_matches_c():
+    b, _ = _lib()
+    assert b.ApfcDesc.n.offset == 8 and b.ApfcDesc.dx.offset == 32 and b.ApfcDesc.dtype.offset == 56
+    assert b.ApfcDesc.nfields.offset == 60 and b.ApfcDesc.k.offset == 64 and b.ApfcDesc.dB.offset == 832
+    assert b.ApfcDesc.dt.offset == 864 and b.ApfcDesc.device.offset == 872 and ctypes.sizeof(b.ApfcDesc) == 880
+
+
+@pytest.mark.parametrize("lattice,shape,dtype", [("triangular", (64, 64), 0), ("bcc", (256, 256, 256), 0),
+                                                 ("fcc2", (30, 20, 12), 1), ("square", (750, 20), 1),
+                                                 ("bcc", (2048, 4, 8), 0)])
+def test_apfc_create_and_sizes(lattice, shape, dtype):
+    import pfc_inputs as P
+
+    b, lib = _lib()
+    k = P.lattice_vectors(lattice)
+    st, h = _apfc_create(lib, _apfc_desc(b, shape, k, dtype))
+    assert st == 0, lib.pfc_last_error()
+    n = len(k) * math.prod(shape) * (16 if dtype else 8)
+    assert lib.pfc_apfc_field_bytes(h) == n
+    assert lib.pfc_apfc_workspace_bytes(h) >= n
+    lib.pfc_apfc_destroy(h)
+
+
+def test_apfc_distinct_products():
+    """Distinct products of the resonant sums: one triangular shell has the pair conj(eta_a eta_b)
+    and the triples eta_j |eta_i|^2 (i = 1..3); the square lattice has no resonant pair."""
+    import pfc_inputs as P
+
+    b, lib = _lib()
+    for lattice, t, expect in [("triangular", 0.3, (1, 3)), ("triangular", 0.0, (0, 3)), ("square", 0.3, (0, 2))]:
+        st, h = _apfc_create(lib, _apfc_desc(b, (16, 16), P.lattice_vectors(lattice), t=t))
+        assert st == 0
+        for j in range(len(P.lattice_vectors(lattice))):
+            np_, nt_ = ctypes.c_int(), ctypes.c_int()
+            assert lib.pfc_apfc_terms(h, j, ctypes.byref(np_), ctypes.byref(nt_)) == 0
+            assert (np_.value, nt_.value) == expect, (lattice, t, j)
+        assert lib.pfc_apfc_terms(h, 7, ctypes.byref(np_), ctypes.byref(nt_)) == 1
+        lib.pfc_apfc_destroy(h)
+
+
+def test_apfc_rejects_bad_descriptors():
+    import pfc_inputs as P
+
+    b, lib = _lib()
+    k3 = P.lattice_vectors("bcc")
+    bad = [
+        (dict(shape=(18, 64)), 2),             # no schedule for 18
+        (dict(shape=(64,)), 1),                # 1D
+        (dict(shape=(16, 16, 16)), 1),         # 2D vectors on a 3D grid: k has zero components only if given
+        (dict(Bx=-1.0), 1),
+        (dict(dt=0.0), 1),
+        (dict(dB=-10.0, dt=1.0), 1),           # 1 + dt |k|^2 dB <= 0
+        (dict(dx=0.0), 1),
+    ]
+    for kw, code in bad:
+        d = _apfc_desc(b, **kw)
+        if kw.get("shape") == (16, 16, 16):
+            d.nfields = 1
+            for a in range(3):
+                d.k[0][a] = 0.0
+        st, _ = _apfc_create(lib, d)
+        assert st == code, (kw, st, lib.pfc_last_error())
+    d = _apfc_desc(b, (8, 8, 8), k3)
+    d.nfields = 0
+    assert _apfc_create(lib, d)[0] == 1
+    d.nfields = 33
+    assert _apfc_create(lib, d)[0] == 1
+
+
+def test_apfc_calls_without_workspace_fail_cleanly():
+    b, lib = _lib()
+    st, h = _apfc_create(lib, _apfc_desc(b))
+    assert st == 0
+    buf = ctypes.create_string_buffer(64)
+    assert lib.pfc_apfc_step(h, buf, buf, 1, None) == 4  # PFC_ERR_WORKSPACE
+    assert lib.pfc_apfc_fft(h, buf, buf, -1, None) == 4
+    lib.pfc_apfc_destroy(h)
