@@ -149,6 +149,39 @@ def bench_hydro(nsteps, n=512, seed=9):
             "frac": round(alg / ms / 1e6 / PEAK_HBM_GBPS, 4), "fields_finite": finite}
 
 
+def bench_amplitude(nsteps, n=256, seed=7):
+    """Complex-amplitude form: 6 bcc amplitudes on n^3, FP32 (dB = -0.15, Bx = 1, t = 0.3, v = 1,
+    dt = 0.5, dx = pi/2), amplitudes 0.1 + U(-0.05, 0.05) (1 + i).  Algorithmic bytes per step:
+    14 reads or writes of the 6 complex fields (nonlinearity, x forward, y forward, the fused last
+    axis twice each way, y inverse, x inverse)."""
+    import torch
+
+    import paper_2603_26818_amd as pfc
+    import pfc_inputs
+
+    shape, k = (n, n, n), pfc_inputs.lattice_vectors("bcc")
+    obj = pfc.Apfc(shape, k, dtype="f32", dB=-0.15, Bx=1.0, t=0.3, v=1.0, dt=0.5)
+    eta = pfc_inputs.amplitude_fields_torch(seed, len(k), shape, 0.1, torch.complex64, "cuda:0", 0.05)
+    S = obj.state_init(eta)
+    obj.step(eta, S, 2)
+    stream = torch.cuda.current_stream()
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    obj.step(eta, S, nsteps)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / nsteps
+    finite = bool(torch.isfinite(torch.view_as_real(eta)).all().item())
+    del eta, S, obj
+    torch.cuda.empty_cache()
+    alg = 14.0 * len(k) * n**3 * 8
+    return {"workload": f"complex-amplitude PFC, 6 bcc amplitudes on {n}^3, FP32, dB=-0.15 Bx=1 t=0.3 v=1, "
+                        f"dt=0.5, seed {seed}", "steps": nsteps, "ms_per_step": round(ms, 3),
+            "steps_per_s": round(1000.0 / ms, 2), "alg_gbps": round(alg / ms / 1e6, 1),
+            "frac": round(alg / ms / 1e6 / PEAK_HBM_GBPS, 4), "fields_finite": finite}
+
+
 def bench_big(nsteps, n=2048, seed=3):
     """3D one-mode PFC at n^3 FP32 (r = -0.30, dt = 0.5): steps/s and per-pass GB/s.  n = 2048: the
     full single-GPU size; n = 750: the paper's smaller 3D grid (mixed radix, 750 = 2 3 5^3)."""
@@ -313,6 +346,7 @@ def main():
     ap.add_argument("--adjoint-steps", type=int, default=2000, help="steps of the adjoint form (0: skip)")
     ap.add_argument("--big-steps", type=int, default=50, help="timed steps at 2048^3 (0: skip)")
     ap.add_argument("--hydro-steps", type=int, default=5, help="timed hydrodynamic steps at 512^3 (0: skip)")
+    ap.add_argument("--amp-steps", type=int, default=20, help="timed complex-amplitude steps at 256^3 (0: skip)")
     ap.add_argument("--paper-steps", type=int, default=20,
                     help="timed steps at 750^3 and 1400^3, the paper's 3D grids (0: skip)")
     ap.add_argument("--counters", type=int, default=0, metavar="STEPS",
@@ -432,6 +466,11 @@ def main():
         log(f"[bench] hydrodynamic PFC 512^3 FP32: {args.hydro_steps} steps")
         hydro = bench_hydro(args.hydro_steps)
         log(f"[bench] hydro: {hydro['ms_per_step']} ms/step ({hydro['frac']:.3f} of peak)")
+    amplitude = None
+    if args.amp_steps > 0:
+        log(f"[bench] complex-amplitude form, 6 bcc amplitudes on 256^3 FP32: {args.amp_steps} steps")
+        amplitude = bench_amplitude(args.amp_steps)
+        log(f"[bench] amplitude: {amplitude['ms_per_step']} ms/step ({amplitude['frac']:.3f} of peak)")
     batched = None
     if args.batch_steps > 0:
         log(f"[bench] batched form: 48 instances, {args.batch_steps} steps")
@@ -469,6 +508,7 @@ def main():
         "roofline": roofline, "cpu_baseline": cpu, "fft": fft, "passes": passes, "big_2048": big,
         "paper_grids": paper,
         "hydro": hydro,
+        "amplitude": amplitude,
         "batched": batched, "adjoint": adjoint,
         "step_alg_gbps": round(step_bytes / ms_per_step / 1e6, 1),
         "step_frac": round(step_bytes / ms_per_step / 1e6 / PEAK_HBM_GBPS, 4),

@@ -286,7 +286,9 @@ size_t pfc_apfc_field_bytes(const pfc_apfc *p);
 size_t pfc_apfc_workspace_bytes(const pfc_apfc *p);
 /* Attach a caller-owned device workspace (256-byte aligned); uploads the tables (synchronous). */
 pfc_status pfc_apfc_set_workspace(pfc_apfc *p, void *dev_ptr, size_t bytes);
-/* Number of distinct products in N_j: pairs (t terms) and triples (v terms); products whose
+/* Number of distinct products that N_j sums one by one: pairs (t terms) and triples (v terms).
+ * The triples that permute (j, i, -i), resonant on every lattice, are summed in closed form as
+ * 3v (A^2 - |eta_j|^2) eta_j, A^2 = 2 sum_i |eta_i|^2, and are not counted; products whose
  * coefficient is zero are dropped. */
 pfc_status pfc_apfc_terms(const pfc_apfc *p, int j, int *npairs, int *ntriples);
 /* Complex FFT of every field over all axes, dir = -1 forward (unnormalised) or +1 inverse (times

@@ -7,12 +7,12 @@ namespace pfc {
 
 template <typename T>
 hipError_t launch_apfc_nonlin(const cx<T> *eta, cx<T> *out, int64_t P, int nf, const ApfcTerm *terms, const int *off,
-                              hipStream_t s)
+                              double c3, hipStream_t s)
 {
     if (nf < 1 || nf > kApfcMaxFields) return hipErrorInvalidValue;
     const size_t lds = (size_t)nf * kApfcThreads * sizeof(cx<T>);
     hipLaunchKernelGGL(apfc_nonlin_kernel<T>, dim3((unsigned)cdiv(P, kApfcThreads)), dim3(kApfcThreads), lds, s, eta,
-                       out, P, nf, terms, off);
+                       out, P, nf, terms, off, (T)c3);
     return hipGetLastError();
 }
 
@@ -65,7 +65,7 @@ hipError_t launch_apfc_last_step(int64_t L, int nf, ApfcStepArgs<T> a, hipStream
 
 #define PFC_APFC_INSTANTIATE(T)                                                                                   \
     template hipError_t launch_apfc_nonlin<T>(const cx<T> *, cx<T> *, int64_t, int, const ApfcTerm *, const int *, \
-                                              hipStream_t);                                                        \
+                                              double, hipStream_t);                                                \
     template hipError_t launch_apfc_rows<T>(int64_t, const cx<T> *, cx<T> *, int64_t, int, double, bool,          \
                                             const cx<T> *, int, hipStream_t);                                      \
     template hipError_t launch_apfc_last_step<T>(int64_t, int, ApfcStepArgs<T>, hipStream_t);

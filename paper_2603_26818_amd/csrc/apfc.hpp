@@ -34,23 +34,43 @@ __device__ __forceinline__ cx<T> apfc_pick(const cx<T> *mine, int s, int stride)
 }
 
 // out_j = N_j at every point, for all fields.  One point per thread: the thread's N amplitudes sit
-// in LDS (a runtime-indexed register array would live in scratch memory), then every field's terms
-// terms[off[j] .. off[j+1]) are summed.  Dynamic LDS: nf * kApfcThreads * sizeof(cx<T>) bytes.
+// in LDS (a runtime-indexed register array would live in scratch memory).  The ordered triples that
+// are a permutation of (j, i, -i) are resonant on every lattice (6 orders for i != j, 3 for i = j);
+// their sum is c3 (A^2 - |eta_j|^2) eta_j with A^2 = 2 sum_i |eta_i|^2 and c3 = 3v.  The remaining
+// products terms[off[j] .. off[j+1]) are summed one by one.  Dynamic LDS: nf * kApfcThreads *
+// sizeof(cx<T>) bytes.
 constexpr int kApfcThreads = 128;
 template <typename T>
 __global__ __launch_bounds__(kApfcThreads) void apfc_nonlin_kernel(const cx<T> *__restrict__ eta,
                                                                    cx<T> *__restrict__ out, int64_t P, int nf,
                                                                    const ApfcTerm *__restrict__ terms,
-                                                                   const int *__restrict__ off)
+                                                                   const int *__restrict__ off, T c3)
 {
     extern __shared__ __align__(16) unsigned char apfc_lds[];
     cx<T> *mine = reinterpret_cast<cx<T> *>(apfc_lds) + threadIdx.x;
     const int64_t i = (int64_t)blockIdx.x * kApfcThreads + threadIdx.x;
     const bool valid = i < P;
-    for (int f = 0; f < nf; ++f) mine[f * kApfcThreads] = valid ? eta[(int64_t)f * P + i] : cx<T>{T(0), T(0)};
+    T A2 = T(0);
+    // loads in groups of 8, all in flight before the first one is used
+    for (int f0 = 0; f0 < nf; f0 += 8) {
+        cx<T> z[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u)
+            z[u] = (valid && f0 + u < nf) ? eta[(int64_t)(f0 + u) * P + i] : cx<T>{T(0), T(0)};
+#pragma unroll
+        for (int u = 0; u < 8; ++u)
+            if (f0 + u < nf) {
+                mine[(f0 + u) * kApfcThreads] = z[u];
+                A2 += z[u].x * z[u].x + z[u].y * z[u].y;
+            }
+    }
+    A2 *= T(2);
     // each thread reads back only its own slots: no barrier needed
     for (int j = 0; j < nf; ++j) {
-        cx<T> acc = {T(0), T(0)};
+        // the triples eta_j eta_i conj(eta_i), resonant on every lattice, summed in closed form
+        const cx<T> zj = mine[j * kApfcThreads];
+        const T g = c3 * (A2 - (zj.x * zj.x + zj.y * zj.y));
+        cx<T> acc = {g * zj.x, g * zj.y};
         const int m1 = off[j + 1];
         for (int m = off[j]; m < m1; ++m) {
             const ApfcTerm tm = terms[m];

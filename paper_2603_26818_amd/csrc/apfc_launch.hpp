@@ -37,11 +37,12 @@ struct ApfcStepArgs {
     int lt_shift;
 };
 
-// out_f = N_f at all P points of every field (nf fields of P points back to back); terms[off[j] ..
-// off[j+1]) are field j's products (device pointers).
+// out_f = N_f at all P points of every field (nf fields of P points back to back): c3 (A^2 -
+// |eta_f|^2) eta_f for the triples (f, i, -i), plus the products terms[off[f] .. off[f+1]) (device
+// pointers).
 template <typename T>
 hipError_t launch_apfc_nonlin(const cx<T> *eta, cx<T> *out, int64_t P, int nf, const ApfcTerm *terms, const int *off,
-                              hipStream_t s);
+                              double c3, hipStream_t s);
 
 // FFT (dir -1 forward, +1 inverse) of nrows contiguous rows of length L, times scale.
 template <typename T>

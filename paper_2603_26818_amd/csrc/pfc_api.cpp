@@ -1465,6 +1465,13 @@ void apfc_products(pfc_apfc *p)
                     }
                 }
             }
+        // the permutations of (j, i, -i) are evaluated in closed form by the kernel (3 orders for
+        // i = j, 6 otherwise: every one of them is resonant, so none is left over)
+        for (int i = 1; i <= N; ++i) {
+            std::vector<int> key = {j + 1, i, -i};
+            std::sort(key.begin(), key.end());
+            triples.erase(key);
+        }
         int np = 0, nt = 0;
         if (d.t != 0.0)
             for (auto &kv : pairs) {
@@ -1599,7 +1606,8 @@ pfc_status do_apfc_nonlinear(pfc_apfc *p, const void *eta, void *out, hipStream_
 {
     const pfc::ApfcTerm *terms = reinterpret_cast<const pfc::ApfcTerm *>(p->ws + p->terms_off);
     const int *off = reinterpret_cast<const int *>(p->ws + p->off_off);
-    PFC_TRY(pfc::launch_apfc_nonlin<T>((const cx<T> *)eta, (cx<T> *)out, p->P, p->d.nfields, terms, off, s),
+    PFC_TRY(pfc::launch_apfc_nonlin<T>((const cx<T> *)eta, (cx<T> *)out, p->P, p->d.nfields, terms, off,
+                                       3.0 * p->d.v, s),
             "nonlinearity launch");
     return PFC_OK;
 }

@@ -186,13 +186,16 @@ def test_apfc_create_and_sizes(lattice, shape, dtype):
 
 
 def test_apfc_distinct_products():
-    """Distinct products of the resonant sums: one triangular shell has the pair conj(eta_a eta_b)
-    and the triples eta_j |eta_i|^2 (i = 1..3); the square lattice has no resonant pair."""
+    """Distinct products summed one by one (the triples eta_j |eta_i|^2 go into the closed form):
+    one triangular shell has the single pair conj(eta_a eta_b) and no other triple; the square
+    lattice has neither; bcc has two pairs and two triples of three different amplitudes."""
     import pfc_inputs as P
 
     b, lib = _lib()
-    for lattice, t, expect in [("triangular", 0.3, (1, 3)), ("triangular", 0.0, (0, 3)), ("square", 0.3, (0, 2))]:
-        st, h = _apfc_create(lib, _apfc_desc(b, (16, 16), P.lattice_vectors(lattice), t=t))
+    for lattice, t, expect in [("triangular", 0.3, (1, 0)), ("triangular", 0.0, (0, 0)), ("square", 0.3, (0, 0)),
+                               ("bcc", 0.3, (2, 2))]:
+        k = P.lattice_vectors(lattice)
+        st, h = _apfc_create(lib, _apfc_desc(b, (16,) * k.shape[1], k, t=t))
         assert st == 0
         for j in range(len(P.lattice_vectors(lattice))):
             np_, nt_ = ctypes.c_int(), ctypes.c_int()
