@@ -251,15 +251,16 @@ pfc_status pfc_batch_destroy(pfc_batch *b);
  * taken) -------------------------------------------------------------------------------------------
  * The density is psi = sum_j eta_j e^{i k_j.r} + c.c. over N principal wave vectors k_j; the complex
  * amplitudes eta_j (N fields on one 2D or 3D periodic grid) follow
- *     d_t eta_j = -|k_j|^2 [ (dB + Bx G_j^2) eta_j + N_j ],   G_j = lap + 2 i k_j.grad,
+ *     d_t eta_j = -|k_j|^2 [ (dB + Bx (1 - |k_j|^2 + G_j)^2) eta_j + N_j ],   G_j = lap + 2 i k_j.grad,
  * where N_j is the resonant part of -t psi^2 + v psi^3 at k_j: the sum of -t eta_a eta_b over ordered
  * pairs with k_a + k_b = k_j and of v eta_a eta_b eta_c over ordered triples with k_a + k_b + k_c =
  * k_j, indices over +-1 .. +-N with k_{-a} = -k_a and eta_{-a} = conj(eta_a) (a vector sum matches
  * when it is within 1e-9 max|k| of k_j).  With dB = r, Bx = 1, t = 0, v = 1 this is the expansion of
  * the energy of Eq. (3).  One step (Listing 1's update applied to every amplitude):
- *     eta_hat_j <- (eta_hat_j - dt |k_j|^2 FFT(N_j)) / (1 + dt |k_j|^2 (dB + Bx G_j^2)),
- *     eta_j = IFFT(eta_hat_j),       in Fourier space G_j = -(|q|^2 + 2 k_j.q),
- * q on numpy's fftfreq grid (the Nyquist index counts as -n/2; G_j is odd in q).
+ *     eta_hat_j <- (eta_hat_j - dt |k_j|^2 FFT(N_j)) / (1 + dt |k_j|^2 (dB + Bx (1 - |q + k_j|^2)^2)),
+ *     eta_j = IFFT(eta_hat_j),
+ * ((1 - |k_j|^2 + G_j) is (1 + lap) acting on eta_j e^{i k_j.r}; it is G_j on a unit shell), q on
+ * numpy's fftfreq grid (the Nyquist index counts as -n/2: the operator is not even in q).
  * Layout: N complex grids back to back (field j at j * n0 n1 n2 elements), C order, interleaved
  * (re, im) in the plan's dtype; spectra in natural FFT order, same layout.  Unnormalised forward
  * transform, inverse with 1/(n0 n1 n2). */

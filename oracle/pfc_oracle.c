@@ -630,13 +630,14 @@ int or_hydro_step(const or_params *p, const or_hydro *hp, double *psi, double *p
  * the usual quadratic coefficient t:
  *     f(psi) = psi (dB + Bx (1 + lap)^2) psi / 2 - t psi^3 / 3 + v psi^4 / 4
  * (Eq. (3) is dB = r, Bx = 1, t = 0, v = 1), and for each amplitude
- *     d_t eta_j = -|k_j|^2 [ (dB + Bx G_j^2) eta_j + N_j ],   G_j = lap + 2 i k_j . grad,
+ *     d_t eta_j = -|k_j|^2 [ (dB + Bx (1 - |k_j|^2 + G_j)^2) eta_j + N_j ],   G_j = lap + 2 i k_j . grad,
+ * where (1 - |k_j|^2 + G_j) is what (1 + lap) becomes on eta_j e^{i k_j.r} (it is G_j when |k_j| = 1),
  * where N_j is the resonant part of the nonlinearity -t psi^2 + v psi^3 at wave vector k_j:
  *     N_j = -t sum_{k_a + k_b = k_j} eta_a eta_b + v sum_{k_a + k_b + k_c = k_j} eta_a eta_b eta_c,
  * the sums running over ordered tuples of a, b, c in {+-1 .. +-N} with k_{-a} = -k_a and
- * eta_{-a} = conj(eta_a).  In Fourier space G_j = -(|q|^2 + 2 k_j . q), and the semi-implicit step
- * (the update of Listing 1 applied to each amplitude) is
- *     eta_hat_j <- (eta_hat_j - dt |k_j|^2 FFT(N_j)) / (1 + dt |k_j|^2 (dB + Bx G_j^2)),
+ * eta_{-a} = conj(eta_a).  In Fourier space 1 - |k_j|^2 + G_j = 1 - |q + k_j|^2, and the
+ * semi-implicit step (the update of Listing 1 applied to each amplitude) is
+ *     eta_hat_j <- (eta_hat_j - dt |k_j|^2 FFT(N_j)) / (1 + dt |k_j|^2 (dB + Bx (1 - |q + k_j|^2)^2)),
  * followed by eta_j = IFFT(eta_hat_j).  Readings: the mean density is absorbed into dB, t, v; the
  * mobility is the long-wave -|k_j|^2; wave vectors q use numpy's fftfreq order (the Nyquist index
  * counts as -n/2, since G_j is odd in q); a tuple is resonant when its vector sum matches k_j to
@@ -827,7 +828,7 @@ int or_apfc_step(const or_apfc *p, double *eta_d, double *eta_hat_d, int64_t nst
                     q2 += qa * qa;
                     kq += p->kvec[j][a] * qa;
                 }
-                double G = -(q2 + 2.0 * kq);
+                double G = 1.0 - kk - q2 - 2.0 * kq; /* 1 - |q + k_j|^2 */
                 int64_t o = (int64_t)j * P + i;
                 S[o] = (S[o] - p->dt * kk * nl[o]) / (1.0 + p->dt * kk * (p->dB + p->Bx * G * G));
             }

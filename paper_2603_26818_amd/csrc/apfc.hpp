@@ -2,9 +2,10 @@
 // named at the end of the paper's multiphysics section).  The density is expanded as
 // psi = sum_j eta_j e^{i k_j.r} + c.c. over N principal reciprocal-lattice vectors k_j; each
 // complex amplitude follows
-//     d_t eta_j = -|k_j|^2 [ (dB + Bx G_j^2) eta_j + N_j ],   G_j = lap + 2 i k_j.grad,
-// N_j the resonant part of -t psi^2 + v psi^3 at k_j, stepped like Listing 1's update:
-//     eta_hat_j <- (eta_hat_j - dt |k_j|^2 FFT(N_j)) / (1 + dt |k_j|^2 (dB + Bx G_j^2)).
+//     d_t eta_j = -|k_j|^2 [ (dB + Bx (1 - |k_j|^2 + G_j)^2) eta_j + N_j ],   G_j = lap + 2 i k_j.grad,
+// N_j the resonant part of -t psi^2 + v psi^3 at k_j, stepped like Listing 1's update; in Fourier
+// space 1 - |k_j|^2 + G_j = 1 - |q + k_j|^2:
+//     eta_hat_j <- (eta_hat_j - dt |k_j|^2 FFT(N_j)) / (1 + dt |k_j|^2 (dB + Bx (1 - |q + k_j|^2)^2)).
 // Fields are N complex grids back to back, C order (axis 0 slowest, x contiguous); spectra in
 // natural FFT order.  Kernels here: the pointwise nonlinearity, complex FFTs of contiguous rows
 // (x pass), and the fused last-axis pass (forward FFT, update of every amplitude, inverse FFT).
@@ -162,7 +163,7 @@ __global__ __launch_bounds__(WMAX *PL::Tp) void apfc_last_step_kernel(ApfcStepAr
     const int64_t k1i = valid ? col / a.nx : 0, kxi = valid ? col - k1i * a.nx : 0;
     const T q1 = a.fk[1] * (T)fft_freq(k1i, a.n1), qx = a.fk[2] * (T)fft_freq(kxi, a.nx);
     const T k0 = a.kv[f][0], kq12 = a.kv[f][1] * q1 + a.kv[f][2] * qx, q12 = q1 * q1 + qx * qx;
-    const T dq = a.dt * a.kk[f];
+    const T dq = a.dt * a.kk[f], c1 = T(1) - a.kk[f];
 #pragma unroll
     for (int b = 0; b < PL::nb(Rl); ++b)
         if (PL::jok(t + b * Tp, Rl))
@@ -170,7 +171,7 @@ __global__ __launch_bounds__(WMAX *PL::Tp) void apfc_last_step_kernel(ApfcStepAr
         for (int r = 0; r < Rl; ++r) {
             const int e = t + b * Tp + r * (L / Rl);
             const T q0 = a.fk[0] * (T)fft_freq(e, L);
-            const T Gj = -(q0 * q0 + q12 + T(2) * (k0 * q0 + kq12));
+            const T Gj = c1 - (q0 * q0 + q12 + T(2) * (k0 * q0 + kq12));  // 1 - |q + k_f|^2
             const T inv = T(1) / (T(1) + dq * (a.dB + a.Bx * Gj * Gj));
             cx<T> S;
             if constexpr (PF)

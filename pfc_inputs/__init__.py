@@ -166,8 +166,27 @@ LATTICES = {
 }
 
 
+def triangular_reciprocal(count: int) -> np.ndarray:
+    """The ``count`` shortest reciprocal vectors i (1, 0) + j (-1/2, sqrt(3)/2) (components (y, x))
+    of the triangular lattice, one of each +- pair, ordered by length, then by angle in [0, pi)."""
+    out = []
+    for i in range(-12, 13):
+        for j in range(-12, 13):
+            y, x = i - 0.5 * j, _S3 * j
+            r2 = y * y + x * x
+            ang = math.atan2(x, y)
+            if r2 < 1e-12 or not (0.0 <= ang < math.pi - 1e-9):
+                continue
+            out.append((round(r2, 9), round(ang, 9), y, x))
+    out.sort()
+    return np.array([(y, x) for _, _, y, x in out[:count]], dtype=np.float64)
+
+
 def lattice_vectors(name: str) -> np.ndarray:
-    """[N][ndim] principal wave vectors of a named lattice."""
+    """[N][ndim] principal wave vectors of a named lattice ("triangular<N>": the N shortest
+    reciprocal vectors of the triangular lattice)."""
+    if name.startswith("triangular") and name[10:].isdigit() and int(name[10:]) > 2:
+        return triangular_reciprocal(int(name[10:]))
     return np.array(LATTICES[name], dtype=np.float64)
 
 

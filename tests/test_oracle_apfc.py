@@ -42,6 +42,8 @@ def unit_cell(name):
     s3 = np.sqrt(3.0) / 2
     if name in ("triangular", "triangular2"):
         box, n = (4 * np.pi, 2 * np.pi / s3), (24, 24)
+    elif name.startswith("triangular"):  # up to |k| = 4: indices |2i - j| <= 8 along y, |j| <= 5 along x
+        box, n = (4 * np.pi, 2 * np.pi / s3), (64, 32)
     elif name == "square":
         box, n = (2 * np.pi, 2 * np.pi), (8, 8)
     elif name == "bcc":
@@ -57,7 +59,7 @@ def unit_cell(name):
     return np.meshgrid(*axes, indexing="ij")
 
 
-@pytest.mark.parametrize("name", ["triangular", "square", "triangular2", "bcc", "fcc2"])
+@pytest.mark.parametrize("name", ["triangular", "square", "triangular2", "bcc", "fcc2", "triangular30"])
 def test_nonlinearity_equals_projection_of_the_density_nonlinearity(name):
     """For constant amplitudes, N_j is the Fourier coefficient at k_j of -t psi^2 + v psi^3 with
     psi = sum_j eta_j e^{i k_j.r} + c.c.: computed here by sampling psi on a periodic cell of the
@@ -100,7 +102,8 @@ def test_uniform_crystal_reaches_the_equilibrium_amplitude():
 
 def test_linear_modes_closed_form():
     """t = v = 0: every Fourier mode q of amplitude j is multiplied per step by
-    1 / (1 + dt |k_j|^2 (dB + Bx (|q|^2 + 2 k_j.q)^2)), with q on numpy's fftfreq grid."""
+    1 / (1 + dt |k_j|^2 (dB + Bx (1 - |q + k_j|^2)^2)), with q on numpy's fftfreq grid (the one-mode
+    operator (1 + lap)^2 acting on eta_j e^{i k_j.r}; two shells, so |k_j| = 1 and sqrt(3) occur)."""
     shape, dx = (8, 12), (np.pi / 2, np.pi / 3)
     k = P.lattice_vectors("triangular2")
     a = oracle.Apfc(shape, k, dx=dx, dB=-0.1, Bx=0.9, t=0.0, v=0.0, dt=0.4)
@@ -108,7 +111,7 @@ def test_linear_modes_closed_form():
     eta, S = oracle.apfc_step(a, eta0, oracle.apfc_state_init(a, eta0), 5)
     qy, qx = np.meshgrid(*[2 * np.pi * np.fft.fftfreq(n, d) for n, d in zip(shape, dx)], indexing="ij")
     for j in range(6):
-        G = qy**2 + qx**2 + 2 * (k[j, 0] * qy + k[j, 1] * qx)
+        G = 1 - ((qy + k[j, 0]) ** 2 + (qx + k[j, 1]) ** 2)
         kk = k[j] @ k[j]
         ref = np.fft.fftn(eta0[j]) / (1 + 0.4 * kk * (-0.1 + 0.9 * G**2)) ** 5
         assert relerr(S[j], ref) < 1e-13
