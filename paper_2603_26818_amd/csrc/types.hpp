@@ -69,12 +69,17 @@ struct BatchInst {
     ModelParams<T> mp;
 };
 
+// Grid-barrier state of the batched kernel.  The arrival counter and the generation the waiters
+// poll sit on separate 128-byte lines: on one line, the polling and the arrivals contend for it
+// (measured on MI355X, 512 workgroups: 35 us per barrier on one line, 13 us on two).
 struct BatchCtl {
     unsigned count;
+    unsigned pad0[31];
     unsigned gen;
     int err;
-    int pad;
+    int pad1[30];
 };
+static_assert(sizeof(BatchCtl) == 256, "the instance table follows at byte 256");
 
 template <typename T>
 struct BatchArgs {
