@@ -83,6 +83,7 @@ def bench_batched(nsteps):
                                                torch.float32, "cuda:0") for i, d in enumerate(insts)]
     b = pfc.Batch(insts).bind(psis)
     b.state_init()
+    variants, tuned_ms = b.autotune(steps=5)  # radix schedules (and item shapes) per pass and length
     b.step(nsteps)  # captures the graph for this nsteps and warms up
     b.check()
     stream = torch.cuda.current_stream()
@@ -109,7 +110,8 @@ def bench_batched(nsteps):
     return {"workload": "48 2D runs {128^2,256^2,512^2,1024^2}x12, one-/two-mode, FP32, dt=0.25", "steps": nsteps,
             "ms": round(ms, 3), "batch_steps_per_s": round(1000.0 * nsteps / ms, 1),
             "points_per_step": pts, "alg_gbps": round(32.0 * pts * nsteps / ms / 1e6, 1),
-            "grid_workgroups": b.grid,
+            "grid_workgroups": b.grid, "autotuned_variants_by_size": {
+                f"{d['shape'][0]}^2": v for d, v in zip(insts, variants)},
             "separate_launches_ms_per_step": round(ms_sep, 4),
             "separate_launches_steps_per_s": round(1000.0 / ms_sep, 1)}
 

@@ -3,7 +3,10 @@
 // One launch runs `nsteps` steps of every instance.  A step is three passes (x r2c with cube,
 // y forward + update + y inverse, x c2r); each pass is a list of work items (a group of rows or a
 // tile of columns of one instance), and the persistent workgroups take items round-robin.  A grid
-// barrier separates passes.  Every workgroup has NT threads; each size runs a schedule whose
+// barrier separates passes.  Between two steps the x c2r of one step and the x r2c of the next
+// touch the same rows only, so they run as one fused pass (an item: the c2r blocks of a row group,
+// then the r2c blocks of the same rows, which read the fresh psi back from the L2): two barriers
+// per step instead of three.  Every workgroup has NT threads; each size runs a schedule whose
 // thread count per item is exactly NT, so one kernel serves all sizes.
 //
 // The grid barrier waits a bounded number of polls.  If the wait runs out (the workgroups are not
@@ -75,7 +78,7 @@ __device__ __forceinline__ int find_inst(const BatchArgs<T> &a, int k)
     int i = 0;
     while (i + 1 < a.ninst) {
         const BatchInst<T> &n = a.inst[i + 1];
-        const int b = PASS == 0 ? n.x_begin : PASS == 1 ? n.y_begin : n.c_begin;
+        const int b = PASS == 0 ? n.x_begin : PASS == 1 ? n.y_begin : PASS == 2 ? n.c_begin : n.f_begin;
         if (k < b) break;
         ++i;
     }
@@ -176,20 +179,39 @@ __device__ __forceinline__ void batch_pass(int pass, const BatchInst<T> *in, int
 // LDS needed by the largest schedule: NT * Rmax complex values (Rmax <= 16).
 constexpr int kBatchLdsElems = kBatchThreads * 16;
 
+// Fused item between two steps: x c2r of rows [item f_rows, (item + 1) f_rows), then x r2c of the
+// same rows (f_rows is a multiple of both passes' rows per item).  The r2c reads the psi rows this
+// workgroup has just stored; __syncthreads makes them visible to all of its threads.
+template <typename T>
+__device__ __forceinline__ void batch_fused(const BatchInst<T> *in, int item, const cx<T> *tw, int lt)
+{
+    const int nc = in->f_rows / in->c_rows, nx = in->f_rows / in->x_rows;
+    for (int s = 0; s < nc; ++s) batch_pass<T>(2, in, item * nc + s, tw, lt);
+    __syncthreads();
+    for (int s = 0; s < nx; ++s) batch_pass<T>(0, in, item * nx + s, tw, lt);
+}
+
 // 2 workgroups of kBatchThreads per CU (4 waves per SIMD).
 template <typename T>
 __global__ __launch_bounds__(kBatchThreads, 4) void batch_kernel(BatchArgs<T> a)
 {
     const unsigned G = gridDim.x;
     for (int64_t step = 0; step < a.nsteps; ++step) {
-        for (int pass = 0; pass < 3; ++pass) {
-            const int total = pass == 0 ? a.x_total : pass == 1 ? a.y_total : a.c_total;
+        // pass 0: x r2c (first step only; later steps get it from the fused pass), 1: y, then
+        // 2: x c2r after the last step, 3: fused x c2r + next step's x r2c otherwise
+        for (int pass = (step == 0 ? 0 : 1); pass < 3; ++pass) {
+            const int kind = (pass == 2 && step + 1 < a.nsteps) ? 3 : pass;
+            const int total = kind == 0 ? a.x_total : kind == 1 ? a.y_total : kind == 2 ? a.c_total : a.f_total;
             for (int k = blockIdx.x; k < total; k += G) {
-                const int i = pass == 0 ? find_inst<T, 0>(a, k) : pass == 1 ? find_inst<T, 1>(a, k)
-                                                                             : find_inst<T, 2>(a, k);
+                const int i = kind == 0 ? find_inst<T, 0>(a, k) : kind == 1 ? find_inst<T, 1>(a, k)
+                              : kind == 2 ? find_inst<T, 2>(a, k) : find_inst<T, 3>(a, k);
                 const BatchInst<T> *in = &a.inst[i];
-                const int item = k - (pass == 0 ? in->x_begin : pass == 1 ? in->y_begin : in->c_begin);
-                batch_pass<T>(pass, in, item, a.tw, a.lt_shift);
+                const int item = k - (kind == 0 ? in->x_begin : kind == 1 ? in->y_begin
+                                      : kind == 2 ? in->c_begin : in->f_begin);
+                if (kind == 3)
+                    batch_fused<T>(in, item, a.tw, a.lt_shift);
+                else
+                    batch_pass<T>(kind, in, item, a.tw, a.lt_shift);
             }
             if (!grid_sync(a.ctl, G, a.max_polls)) return;
         }

@@ -43,12 +43,12 @@ struct pfc_batch {
     std::vector<pfc_plan_desc> descs;  // caller's order
     std::vector<int> order;            // device table order (largest first) -> caller's index
     struct Inst {
-        int n0, nx, M, x_rows, c_rows, W, tiles, x_items, c_items;
+        int n0, nx, M, x_rows, c_rows, W, tiles, x_items, c_items, f_rows, f_items;
         int vx = 0, vy = 0, vc = 0;  // candidate schedules (autotuner)
     };
     std::vector<Inst> inst;  // caller's order
     int lt_shift = 0;
-    int x_total = 0, y_total = 0, c_total = 0;
+    int x_total = 0, y_total = 0, c_total = 0, f_total = 0;
     size_t ctl_off = 0, inst_off = 0, tw_off = 0, partial_off = 0, ws_need = 0;
     std::vector<size_t> scratch_off;  // caller's order
     char *ws = nullptr;
@@ -671,6 +671,10 @@ pfc_status batch_layout(pfc_batch *b)
         g.tiles = g.M / g.W;
         g.x_items = (g.n0 + g.x_rows - 1) / g.x_rows;
         g.c_items = (g.n0 + g.c_rows - 1) / g.c_rows;
+        g.f_rows = std::max(g.x_rows, g.c_rows);  // both powers of two: a multiple of each
+        if (g.f_rows % g.x_rows || g.f_rows % g.c_rows)
+            return fail(PFC_ERR_INTERNAL, "instance %d: rows per item %d and %d do not nest", i, g.x_rows, g.c_rows);
+        g.f_items = (g.n0 + g.f_rows - 1) / g.f_rows;
     }
     return PFC_OK;
 }
@@ -680,7 +684,7 @@ template <typename T>
 pfc_status batch_upload_table(pfc_batch *b)
 {
     std::vector<pfc::BatchInst<T>> table(b->count);
-    int xb = 0, yb = 0, cb = 0;
+    int xb = 0, yb = 0, cb = 0, fb = 0;
     for (int j = 0; j < b->count; ++j) {
         const int i = b->order[j];
         const pfc_batch::Inst &g = b->inst[i];
@@ -695,15 +699,21 @@ pfc_status batch_upload_table(pfc_batch *b)
         t.tiles = g.tiles;
         t.x_items = g.x_items;
         t.c_items = g.c_items;
+        t.x_rows = g.x_rows;
+        t.c_rows = g.c_rows;
+        t.f_rows = g.f_rows;
+        t.f_items = g.f_items;
         t.x_begin = xb;
         t.y_begin = yb;
         t.c_begin = cb;
+        t.f_begin = fb;
         t.vx = g.vx;
         t.vy = g.vy;
         t.vc = g.vc;
         xb += g.x_items;
         yb += g.tiles;
         cb += g.c_items;
+        fb += g.f_items;
         t.sc = (T)(1.0 / ((double)g.n0 * (double)g.M));
         t.mp.r = (T)d.r;
         t.mp.dt = (T)d.dt;
@@ -718,6 +728,7 @@ pfc_status batch_upload_table(pfc_batch *b)
     b->x_total = xb;
     b->y_total = yb;
     b->c_total = cb;
+    b->f_total = fb;
     PFC_TRY(hipMemcpy(b->ws + b->inst_off, table.data(), table.size() * sizeof(table[0]), hipMemcpyHostToDevice),
             "instance table upload");
     drop_graphs(b);  // the captured launches hold the item totals
@@ -750,6 +761,7 @@ pfc::BatchArgs<T> batch_args(const pfc_batch *b, int64_t nsteps)
     a.x_total = b->x_total;
     a.y_total = b->y_total;
     a.c_total = b->c_total;
+    a.f_total = b->f_total;
     a.tw = (const cx<T> *)(b->ws + b->tw_off);
     a.lt_shift = b->lt_shift;
     a.ctl = (pfc::BatchCtl *)(b->ws + b->ctl_off);

@@ -63,7 +63,9 @@ struct BatchInst {
     int tiles;       // y items (M / W)
     int x_items;     // x r2c items
     int c_items;     // x c2r items
-    int x_begin, y_begin, c_begin;  // first global item of this instance in each pass
+    int x_rows, c_rows;  // rows per x r2c / x c2r item
+    int f_rows, f_items;  // fused x c2r + x r2c items (between two steps): rows per item, items
+    int x_begin, y_begin, c_begin, f_begin;  // first global item of this instance in each pass
     int vx, vy, vc;                 // candidate schedule of the x forward, y and x inverse passes
     T sc;            // 1 / (n0 M)
     ModelParams<T> mp;
@@ -85,7 +87,7 @@ template <typename T>
 struct BatchArgs {
     const BatchInst<T> *inst;  // sorted largest first
     int ninst;
-    int x_total, y_total, c_total;
+    int x_total, y_total, c_total, f_total;
     const cx<T> *tw;
     int lt_shift;
     BatchCtl *ctl;

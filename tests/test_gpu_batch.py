@@ -53,11 +53,13 @@ def test_batch_matches_single_plans_every_replay(pfc, dtype):
     torch.cuda.synchronize()
     for k in range(len(insts)):
         assert torch.equal(b.state[k], ref_state[k]), f"state_init differs for instance {k}"
-    for rep in range(3):
-        b.step(7)  # graph replay
+    # launches of 7 steps (graph replays; every step after the first runs the fused x c2r + x r2c
+    # pass), then of 1 and 2 steps (no fused pass, and one)
+    for rep, n in enumerate((7, 7, 7, 1, 2)):
+        b.step(n)
         b.check()
         for p, x, s in zip(plans, ref_psi, ref_state):
-            p.step(x, s, 7)
+            p.step(x, s, n)
         torch.cuda.synchronize()
         for k in range(len(insts)):
             same = torch.equal(b.psi[k], ref_psi[k]) and torch.equal(b.state[k], ref_state[k])
