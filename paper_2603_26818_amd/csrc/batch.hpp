@@ -122,6 +122,15 @@ __device__ __noinline__ void batch_y_step(const BatchInst<T> *in, int item, cons
     last_axis_block<T, PL, WM, LA_STEP, TL::PF, ORD_TILE, false, TL::G>(la, item, batch_lds<T>());
 }
 
+// x c2r of a row group fused with the cube and x r2c of the next step (the single-plan step's
+// fused kernel body, with this kernel's thread count): rows [item f_rows, (item + 1) f_rows)
+template <typename T, class PLI, class PLF>
+__device__ __noinline__ void batch_x_fused(const BatchInst<T> *in, int item, const cx<T> *tw, int lt_shift)
+{
+    x_c2r_r2c_block<T, PLI, PLF, kBatchThreads>(in->scratch, in->scratch, in->n0, tw, lt_shift, in->sc, item,
+                                                batch_lds<T>());
+}
+
 template <typename T, class PL>
 __device__ __noinline__ void batch_x_inv(const BatchInst<T> *in, int item, const cx<T> *tw, int lt_shift)
 {
@@ -179,17 +188,26 @@ __device__ __forceinline__ void batch_pass(int pass, const BatchInst<T> *in, int
 // LDS needed by the largest schedule: NT * Rmax complex values (Rmax <= 16).
 constexpr int kBatchLdsElems = kBatchThreads * 16;
 
-// Fused item between two steps: x c2r of rows [item f_rows, (item + 1) f_rows), then x r2c of the
-// same rows (f_rows is a multiple of both passes' rows per item).  The r2c reads the psi rows this
-// workgroup has just stored; __syncthreads makes them visible to all of its threads.
+// Fused item between two steps: x c2r of rows [item f_rows, (item + 1) f_rows), the field kept in
+// LDS, cube and x r2c of the same rows (f_rows is XFused<..>::R of the two schedules).
+#define PFC_FCASE(LEN)                                                                                     \
+    case LEN:                                                                                              \
+        with_plan<typename XInvCands<LEN>::type>(in->vc, [&](auto pi) {                                    \
+            return with_plan<typename XFwdCands<LEN>::type>(in->vx, [&](auto pf) {                         \
+                batch_x_fused<T, decltype(pi), decltype(pf)>(in, item, tw, lt);                            \
+                return 0;                                                                                  \
+            });                                                                                            \
+        });                                                                                                \
+        break;
 template <typename T>
 __device__ __forceinline__ void batch_fused(const BatchInst<T> *in, int item, const cx<T> *tw, int lt)
 {
-    const int nc = in->f_rows / in->c_rows, nx = in->f_rows / in->x_rows;
-    for (int s = 0; s < nc; ++s) batch_pass<T>(2, in, item * nc + s, tw, lt);
-    __syncthreads();
-    for (int s = 0; s < nx; ++s) batch_pass<T>(0, in, item * nx + s, tw, lt);
+    switch (in->M) {
+        PFC_FCASE(16) PFC_FCASE(32) PFC_FCASE(64) PFC_FCASE(128) PFC_FCASE(256) PFC_FCASE(512)
+    default: break;
+    }
 }
+#undef PFC_FCASE
 
 // 2 workgroups of kBatchThreads per CU (4 waves per SIMD).
 template <typename T>

@@ -130,24 +130,31 @@ template <bool PAD>
 __device__ __forceinline__ int xidx(int e) { return PAD ? xpad(e) : e; }
 
 // One block of ROWS rows (block index `bid`); `sh` holds ROWS * XPitch<M, PAD> LDS slots.
-// Uses threads 0 .. ROWS*Tp-1, which must be all threads of the workgroup.
-template <typename T, class PL, int ROWS, bool CUBE, bool PAD = false, bool NT = false>
+// Uses threads 0 .. ROWS*Tp-1, which must be all threads of the workgroup.  FROM_LDS: the rows'
+// reals are not read from `in` but from `sh` (row p at sh[p M], as packed pairs), where the caller
+// has left them.
+template <typename T, class PL, int ROWS, bool CUBE, bool PAD = false, bool NT = false, bool FROM_LDS = false>
 __device__ __forceinline__ void x_r2c_block(const T *__restrict__ in, cx<T> *__restrict__ out, int64_t nrows,
                                             const cx<T> *__restrict__ tw, int lt_shift, int64_t bid, cx<T> *sh)
 {
+    static_assert(!FROM_LDS || !PAD, "staged rows are unpadded");
     constexpr int M = PL::L, Tp = PL::Tp, R0 = PL::first, Rl = PL::last, Rmax = PL::Rmax;
     constexpr int LD = XPitch<M, PAD>::value;  // row pitch in LDS
     const int tid = threadIdx.x, p = tid / Tp, t = tid - p * Tp;
     const int64_t row = bid * ROWS + p;
     const bool valid = row < nrows;
-    const cx<T> *src = reinterpret_cast<const cx<T> *>(in) + (valid ? row : 0) * M;
+    const cx<T> *src = FROM_LDS ? sh + p * M : reinterpret_cast<const cx<T> *>(in) + (valid ? row : 0) * M;
     cx<T> v[Rmax];
 #pragma unroll
     for (int b = 0; b < PL::nb(R0); ++b)
         if (PL::jok(t + b * Tp, R0))
 #pragma unroll
         for (int r = 0; r < R0; ++r) {
-            cx<T> z = valid ? ld_grid<NT>(&src[t + b * Tp + r * (M / R0)]) : cx<T>{T(0), T(0)};
+            cx<T> z;
+            if constexpr (FROM_LDS)
+                z = src[t + b * Tp + r * (M / R0)];
+            else
+                z = valid ? ld_grid<NT>(&src[t + b * Tp + r * (M / R0)]) : cx<T>{T(0), T(0)};
             if constexpr (CUBE) z = {z.x * z.x * z.x, z.y * z.y * z.y};
             v[b * R0 + r] = z;
         }
@@ -270,10 +277,14 @@ __device__ __forceinline__ void x_c2r_row(cx<T> *v, const cx<T> *src, bool valid
         }
 }
 
-template <typename T, class PL, int ROWS, int EPI, bool PAD = false, bool PG = false, bool NT = false>
+// TO_LDS (EPI_PLAIN): the scaled reals of row p are left in sh[p M] (as packed pairs) instead of
+// being stored to `out`.
+template <typename T, class PL, int ROWS, int EPI, bool PAD = false, bool PG = false, bool NT = false,
+          bool TO_LDS = false>
 __device__ __forceinline__ void x_c2r_block(const cx<T> *in, T *out, int64_t nrows, const cx<T> *__restrict__ tw,
                                             int lt_shift, T sc, const AdjEpi<T> &ea, int64_t bid, cx<T> *sh)
 {
+    static_assert(!TO_LDS || (EPI == EPI_PLAIN && !PAD), "staging only for the plain epilogue, unpadded");
     constexpr int M = PL::L, Tp = PL::Tp, Rl = PL::last, Rmax = PL::Rmax;
     constexpr int LD = XPitch<M, PAD>::value;
     const int tid = threadIdx.x, p = tid / Tp, t = tid - p * Tp;
@@ -300,6 +311,13 @@ __device__ __forceinline__ void x_c2r_block(const cx<T> *in, T *out, int64_t nro
                         dst[m] = o;
                     }
         }
+    } else if constexpr (EPI == EPI_PLAIN && TO_LDS) {
+        __syncthreads();  // every thread of the row is past its last exchange read
+#pragma unroll
+        for (int b = 0; b < PL::nb(Rl); ++b)
+            if (PL::jok(t + b * Tp, Rl))
+#pragma unroll
+            for (int r = 0; r < Rl; ++r) sh[p * M + t + b * Tp + r * (M / Rl)] = scale(v[b * Rl + r], sc);
     } else if constexpr (EPI == EPI_PLAIN) {
         if (valid) {
 #pragma unroll
@@ -347,6 +365,45 @@ __global__ __launch_bounds__(ROWS *PL::Tp) void x_c2r_kernel(const cx<T> *in, T 
 // ------------------------------------------------------------------------------------------------
 // Pencils per workgroup of the strided passes: 128-byte rows (16 FP32 / 8 FP64 complex) as long as
 // the workgroup's LDS tile stays within 128 KB.
+// x pass between two steps of a batched run: the inverse x transform of one step (x c2r) and the
+// forward x transform with the cube of the next (x r2c), over the same rows, with the field between
+// them kept in LDS: a workgroup takes R rows, runs the c2r schedule PLI on them in groups of RI rows
+// (each group leaving its reals in its rows' LDS slots), then the r2c schedule PLF in groups of RF
+// rows reading those slots.  The field of the intermediate step is never stored.  Arithmetic
+// identical to x_c2r_kernel followed by x_r2c_kernel with the cube.  (As a separate kernel of the
+// single-plan step it measured no faster than the two passes it replaces: 0.40 ms against 0.41 ms at
+// 512^3, slower at 2048^3; with half the memory traffic, the two row FFTs then bound it.)
+template <class PLI, class PLF, int NTH = 256>
+struct XFused {
+    static constexpr int RI = NTH / PLI::Tp < 1 ? 1 : NTH / PLI::Tp;
+    static constexpr int RF = NTH / PLF::Tp < 1 ? 1 : NTH / PLF::Tp;
+    static constexpr int R = RI > RF ? RI : RF;
+    static constexpr int threads = RI * PLI::Tp;
+    // both schedules fill the same workgroup, and a group of either kind tiles the R rows
+    static constexpr bool ok = RI * PLI::Tp == RF * PLF::Tp && R % RI == 0 && R % RF == 0;
+};
+// One block of R rows (block index `bid`); `sh` holds R M LDS slots; NTH threads.
+template <typename T, class PLI, class PLF, int NTH, bool NT = false>
+__device__ __forceinline__ void x_c2r_r2c_block(const cx<T> *in, cx<T> *out, int64_t nrows,
+                                                const cx<T> *__restrict__ tw, int lt_shift, T sc, int64_t bid,
+                                                cx<T> *sh)
+{
+    using F = XFused<PLI, PLF, NTH>;
+    static_assert(F::ok && PLI::L == PLF::L, "schedules must share the workgroup");
+    constexpr int M = PLI::L;
+    const AdjEpi<T> ea{};
+#pragma unroll
+    for (int s = 0; s < F::R / F::RI; ++s)
+        x_c2r_block<T, PLI, F::RI, EPI_PLAIN, false, false, NT, true>(in, nullptr, nrows, tw, lt_shift, sc, ea,
+                                                                      bid * (F::R / F::RI) + s, sh + s * F::RI * M);
+    __syncthreads();  // all staged rows written
+#pragma unroll
+    for (int s = 0; s < F::R / F::RF; ++s)
+        x_r2c_block<T, PLF, F::RF, true, false, NT, true>(nullptr, out, nrows, tw, lt_shift, bid * (F::R / F::RF) + s,
+                                                          sh + s * F::RF * M);
+}
+
+
 template <typename T, int L>
 struct WMax {
     static constexpr int pref = 128 / (int)sizeof(cx<T>);
