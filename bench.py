@@ -151,17 +151,21 @@ def bench_hydro(nsteps, n=512, seed=9):
             "frac": round(alg / ms / 1e6 / PEAK_HBM_GBPS, 4), "fields_finite": finite}
 
 
-def bench_amplitude(nsteps, n=256, seed=7):
-    """Complex-amplitude form: 6 bcc amplitudes on n^3, FP32 (dB = -0.15, Bx = 1, t = 0.3, v = 1,
-    dt = 0.5, dx = pi/2), amplitudes 0.1 + U(-0.05, 0.05) (1 + i).  Algorithmic bytes per step:
-    14 reads or writes of the 6 complex fields (nonlinearity, x forward, y forward, the fused last
-    axis twice each way, y inverse, x inverse)."""
+def bench_amplitude(nsteps, shape=(256, 256, 256), lattice="bcc", seed=7):
+    """Complex-amplitude form: the amplitudes of a lattice (6 bcc amplitudes on 256^3, or 3
+    triangular ones on 2048^2), FP32 (dB = -0.15, Bx = 1, t = 0.3, v = 1, dt = 0.5, dx = pi/2),
+    amplitudes 0.1 + U(-0.05, 0.05) (1 + i).  Algorithmic bytes per step: 14 (3D) or 10 (2D) reads or
+    writes of the complex fields (nonlinearity, x forward, y forward in 3D, the fused last axis
+    twice each way, y inverse in 3D, x inverse)."""
     import torch
 
     import paper_2603_26818_amd as pfc
     import pfc_inputs
 
-    shape, k = (n, n, n), pfc_inputs.lattice_vectors("bcc")
+    shape, k = tuple(shape), pfc_inputs.lattice_vectors(lattice)
+    npts = 1
+    for v in shape:
+        npts *= v
     obj = pfc.Apfc(shape, k, dtype="f32", dB=-0.15, Bx=1.0, t=0.3, v=1.0, dt=0.5)
     eta = pfc_inputs.amplitude_fields_torch(seed, len(k), shape, 0.1, torch.complex64, "cuda:0", 0.05)
     S = obj.state_init(eta)
@@ -177,9 +181,10 @@ def bench_amplitude(nsteps, n=256, seed=7):
     finite = bool(torch.isfinite(torch.view_as_real(eta)).all().item())
     del eta, S, obj
     torch.cuda.empty_cache()
-    alg = 14.0 * len(k) * n**3 * 8
-    return {"workload": f"complex-amplitude PFC, 6 bcc amplitudes on {n}^3, FP32, dB=-0.15 Bx=1 t=0.3 v=1, "
-                        f"dt=0.5, seed {seed}", "steps": nsteps, "ms_per_step": round(ms, 3),
+    alg = (14.0 if len(shape) == 3 else 10.0) * len(k) * npts * 8
+    dims = "x".join(str(v) for v in shape)
+    return {"workload": f"complex-amplitude PFC, {len(k)} {lattice} amplitudes on {dims}, FP32, dB=-0.15 Bx=1 "
+                        f"t=0.3 v=1, dt=0.5, seed {seed}", "steps": nsteps, "ms_per_step": round(ms, 3),
             "steps_per_s": round(1000.0 / ms, 2), "alg_gbps": round(alg / ms / 1e6, 1),
             "frac": round(alg / ms / 1e6 / PEAK_HBM_GBPS, 4), "fields_finite": finite}
 
@@ -473,6 +478,10 @@ def main():
         log(f"[bench] complex-amplitude form, 6 bcc amplitudes on 256^3 FP32: {args.amp_steps} steps")
         amplitude = bench_amplitude(args.amp_steps)
         log(f"[bench] amplitude: {amplitude['ms_per_step']} ms/step ({amplitude['frac']:.3f} of peak)")
+        log(f"[bench] complex-amplitude form, 3 triangular amplitudes on 2048^2 FP32: {args.amp_steps} steps")
+        amplitude["2d_triangular_2048sq"] = bench_amplitude(args.amp_steps, (2048, 2048), "triangular", 8)
+        log(f"[bench] amplitude 2D: {amplitude['2d_triangular_2048sq']['ms_per_step']} ms/step "
+            f"({amplitude['2d_triangular_2048sq']['frac']:.3f} of peak)")
     batched = None
     if args.batch_steps > 0:
         log(f"[bench] batched form: 48 instances, {args.batch_steps} steps")

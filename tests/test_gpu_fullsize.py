@@ -114,3 +114,30 @@ def test_256_cube_1000_steps_energy_and_fp32(pfc):
         f"max|psi| {float(x64.abs().max()):.3f}); FP32 vs FP64 at step {steps}: rel L2 {e:.2e}")
     assert checked >= 10
     assert e < 1e-3
+
+
+def test_512_cube_bench_workload_vs_oracle(pfc):
+    """The benchmark's headline workload itself: 512^3 FP32, r = -0.30, dt = 0.5, dx = pi/4, psi0
+    seed 23, drawn on the device as the benchmark draws it, the plan launched as the benchmark
+    launches it; 3 steps and one r2c against the FP64 oracle on the same (FP32-rounded) field."""
+    import torch
+
+    shape, r = (512, 512, 512), -0.30
+    say("[fullsize] 512^3 FP32 bench workload: 3 steps and one r2c vs the oracle")
+    psi = P.pfc_initial_field_torch(23, shape, r, torch.float32, "cuda:0")
+    psi0 = to_np(psi)
+    plan = pfc.Plan(shape, dtype="f32", r=r, dt=0.5)
+    half = to_np(plan.fft_r2c(psi))
+    ref_half = oracle.rfftn(psi0)
+    e_fft = relerr(half, ref_half)
+    del half
+    state = plan.state_init(psi)
+    plan.step(psi, state, 3)
+    got = to_np(psi)
+    del psi, state, plan
+    torch.cuda.empty_cache()
+    p = oracle.Params(shape, r=r, dt=0.5)
+    ref, _ = oracle.step(p, psi0, oracle.state_init(p, psi0), 3)
+    e = relerr(got, ref)
+    say(f"      r2c rel L2 {e_fft:.2e}   psi after 3 steps rel L2 {e:.2e}")
+    assert e_fft < 5e-6 and e < 1e-5
