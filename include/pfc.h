@@ -285,7 +285,9 @@ pfc_status pfc_apfc_create(pfc_apfc **out, const pfc_apfc_desc *d);
 size_t pfc_apfc_field_bytes(const pfc_apfc *p);
 /* Device workspace bytes: twiddles, the product table, one scratch copy of the fields. */
 size_t pfc_apfc_workspace_bytes(const pfc_apfc *p);
-/* Attach a caller-owned device workspace (256-byte aligned); uploads the tables (synchronous). */
+/* Attach a caller-owned device workspace (256-byte aligned); uploads the tables (synchronous).  The
+ * workspace must stay valid while the object is used; calls on one object share its scratch, so
+ * they must not run concurrently on different streams. */
 pfc_status pfc_apfc_set_workspace(pfc_apfc *p, void *dev_ptr, size_t bytes);
 /* Number of distinct products that N_j sums one by one: pairs (t terms) and triples (v terms).
  * The triples that permute (j, i, -i), resonant on every lattice, are summed in closed form as
