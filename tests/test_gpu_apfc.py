@@ -88,6 +88,7 @@ STEP_CASES = [
     ("bcc", (16, 32, 64), "f32", 30, 87),
     ("fcc2", (30, 20, 12), "f64", 30, 88),
     ("bcc", (2048, 4, 8), "f32", 5, 89),
+    ("bcc", (2048, 32, 64), "f32", 2, 95),  # 768 pencil tiles: the full-width 2048-point tile
     ("bcc", (1024, 6, 10), "f32", 5, 90),
     ("bcc", (1400, 4, 6), "f32", 5, 91),
     ("bcc", (1400, 4, 6), "f64", 5, 91),
