@@ -53,7 +53,10 @@ def test_apfc_fft_vs_oracle(pfc, shape, dtype):
     k = P.lattice_vectors("triangular") if len(shape) == 2 else P.lattice_vectors("bcc")[:nf]
     x = crounded(P.amplitude_fields(81, nf, shape, 0.0, 1.0), dtype)
     obj = pfc.Apfc(shape, k, dtype=dtype)
-    X = chost(obj.fft(cdev(x, dtype), -1))
+    xd = cdev(x, dtype)
+    X = chost(obj.fft(xd, -1))
+    Xin = chost(obj.fft(xd, -1, out=xd))  # in place: the same bits as out of place
+    assert np.array_equal(X, Xin)
     ref = np.stack([oracle.fft_c2c(x[j], -1) for j in range(nf)])
     e_fwd = relerr(X, ref)
     y = chost(obj.fft(cdev(ref, dtype), +1))
