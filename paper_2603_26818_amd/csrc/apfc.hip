@@ -10,9 +10,15 @@ hipError_t launch_apfc_nonlin(const cx<T> *eta, cx<T> *out, int64_t P, int nf, c
                               double c3, hipStream_t s)
 {
     if (nf < 1 || nf > kApfcMaxFields) return hipErrorInvalidValue;
-    const size_t lds = (size_t)nf * kApfcThreads * sizeof(cx<T>);
-    hipLaunchKernelGGL(apfc_nonlin_kernel<T>, dim3((unsigned)cdiv(P, kApfcThreads)), dim3(kApfcThreads), lds, s, eta,
-                       out, P, nf, terms, off, (T)c3);
+    // two points per thread while their LDS slots fit in 64 KB (all but FP64 with over 16 fields)
+    const size_t lds2 = (size_t)nf * 2 * kApfcThreads * sizeof(cx<T>);
+    if (lds2 <= 65536) {
+        hipLaunchKernelGGL((apfc_nonlin_kernel<T, 2>), dim3((unsigned)cdiv(P, 2 * kApfcThreads)), dim3(kApfcThreads),
+                           lds2, s, eta, out, P, nf, terms, off, (T)c3);
+    } else {
+        hipLaunchKernelGGL((apfc_nonlin_kernel<T, 1>), dim3((unsigned)cdiv(P, kApfcThreads)), dim3(kApfcThreads),
+                           lds2 / 2, s, eta, out, P, nf, terms, off, (T)c3);
+    }
     return hipGetLastError();
 }
 

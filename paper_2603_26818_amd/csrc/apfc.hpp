@@ -38,49 +38,70 @@ __device__ __forceinline__ cx<T> apfc_pick(const cx<T> *mine, int s, int stride)
 // in LDS (a runtime-indexed register array would live in scratch memory).  The ordered triples that
 // are a permutation of (j, i, -i) are resonant on every lattice (6 orders for i != j, 3 for i = j);
 // their sum is c3 (A^2 - |eta_j|^2) eta_j with A^2 = 2 sum_i |eta_i|^2 and c3 = 3v.  The remaining
-// products terms[off[j] .. off[j+1]) are summed one by one.  Dynamic LDS: nf * kApfcThreads *
-// sizeof(cx<T>) bytes.
+// products terms[off[j] .. off[j+1]) are summed one by one.
 constexpr int kApfcThreads = 128;
-template <typename T>
+// PPT points per thread (PPT consecutive groups of kApfcThreads points per workgroup): each term of
+// the table is then read once for PPT points.  Dynamic LDS: nf * PPT * kApfcThreads * sizeof(cx<T>).
+template <typename T, int PPT>
 __global__ __launch_bounds__(kApfcThreads) void apfc_nonlin_kernel(const cx<T> *__restrict__ eta,
                                                                    cx<T> *__restrict__ out, int64_t P, int nf,
                                                                    const ApfcTerm *__restrict__ terms,
                                                                    const int *__restrict__ off, T c3)
 {
+    constexpr int S = PPT * kApfcThreads;  // LDS stride between fields
     extern __shared__ __align__(16) unsigned char apfc_lds[];
-    cx<T> *mine = reinterpret_cast<cx<T> *>(apfc_lds) + threadIdx.x;
-    const int64_t i = (int64_t)blockIdx.x * kApfcThreads + threadIdx.x;
-    const bool valid = i < P;
-    T A2 = T(0);
-    // loads in groups of 8, all in flight before the first one is used
-    for (int f0 = 0; f0 < nf; f0 += 8) {
-        cx<T> z[8];
+    cx<T> *mine[PPT];
+    int64_t idx[PPT];
+    bool valid[PPT];
+    T A2[PPT];
 #pragma unroll
-        for (int u = 0; u < 8; ++u)
-            z[u] = (valid && f0 + u < nf) ? eta[(int64_t)(f0 + u) * P + i] : cx<T>{T(0), T(0)};
-#pragma unroll
-        for (int u = 0; u < 8; ++u)
-            if (f0 + u < nf) {
-                mine[(f0 + u) * kApfcThreads] = z[u];
-                A2 += z[u].x * z[u].x + z[u].y * z[u].y;
-            }
+    for (int q = 0; q < PPT; ++q) {
+        mine[q] = reinterpret_cast<cx<T> *>(apfc_lds) + q * kApfcThreads + threadIdx.x;
+        idx[q] = (int64_t)blockIdx.x * S + q * kApfcThreads + threadIdx.x;
+        valid[q] = idx[q] < P;
+        A2[q] = T(0);
     }
-    A2 *= T(2);
+    // loads in groups of 8 fields, all in flight before the first one is used
+    for (int f0 = 0; f0 < nf; f0 += 8) {
+        cx<T> z[PPT][8];
+#pragma unroll
+        for (int q = 0; q < PPT; ++q)
+#pragma unroll
+            for (int u = 0; u < 8; ++u)
+                z[q][u] = (valid[q] && f0 + u < nf) ? eta[(int64_t)(f0 + u) * P + idx[q]] : cx<T>{T(0), T(0)};
+#pragma unroll
+        for (int q = 0; q < PPT; ++q)
+#pragma unroll
+            for (int u = 0; u < 8; ++u)
+                if (f0 + u < nf) {
+                    mine[q][(f0 + u) * S] = z[q][u];
+                    A2[q] += z[q][u].x * z[q][u].x + z[q][u].y * z[q][u].y;
+                }
+    }
     // each thread reads back only its own slots: no barrier needed
     for (int j = 0; j < nf; ++j) {
         // the triples eta_j eta_i conj(eta_i), resonant on every lattice, summed in closed form
-        const cx<T> zj = mine[j * kApfcThreads];
-        const T g = c3 * (A2 - (zj.x * zj.x + zj.y * zj.y));
-        cx<T> acc = {g * zj.x, g * zj.y};
+        cx<T> acc[PPT];
+#pragma unroll
+        for (int q = 0; q < PPT; ++q) {
+            const cx<T> zj = mine[q][j * S];
+            const T g = c3 * (T(2) * A2[q] - (zj.x * zj.x + zj.y * zj.y));
+            acc[q] = {g * zj.x, g * zj.y};
+        }
         const int m1 = off[j + 1];
         for (int m = off[j]; m < m1; ++m) {
             const ApfcTerm tm = terms[m];
-            cx<T> p = cmul(apfc_pick(mine, tm.a, kApfcThreads), apfc_pick(mine, tm.b, kApfcThreads));
-            if (tm.c != 0) p = cmul(p, apfc_pick(mine, tm.c, kApfcThreads));
             const T c = apfc_coef<T>(tm);
-            acc = {acc.x + c * p.x, acc.y + c * p.y};
+#pragma unroll
+            for (int q = 0; q < PPT; ++q) {
+                cx<T> p = cmul(apfc_pick(mine[q], tm.a, S), apfc_pick(mine[q], tm.b, S));
+                if (tm.c != 0) p = cmul(p, apfc_pick(mine[q], tm.c, S));
+                acc[q] = {acc[q].x + c * p.x, acc[q].y + c * p.y};
+            }
         }
-        if (valid) out[(int64_t)j * P + i] = acc;
+#pragma unroll
+        for (int q = 0; q < PPT; ++q)
+            if (valid[q]) out[(int64_t)j * P + idx[q]] = acc[q];
     }
 }
 
