@@ -118,8 +118,9 @@ def bench_batched(nsteps):
 
 def bench_hydro(nsteps, n=512, seed=9):
     """Hydrodynamic PFC (density + 3 velocity components) at n^3 FP32, rho0 = gamma = a0 = 1,
-    r = -0.30, dt = 0.25: ms per step and algorithmic GB/s on the 528 B/point pass model (132 passes
-    of 4 B per point: 108 over packed spectra, 24 over real fields)."""
+    r = -0.30, dt = 0.25: ms per step and algorithmic GB/s on the 480 B/point pass model (120 reads
+    or writes of 4 B per point, a packed spectrum or a real field: 16 transforms, the 6 derivatives
+    applied inside the last-axis inverse passes, 5 pointwise updates)."""
     import torch
 
     import paper_2603_26818_amd as pfc
@@ -144,7 +145,7 @@ def bench_hydro(nsteps, n=512, seed=9):
     finite = bool(torch.isfinite(psi).all().item()) and bool(torch.isfinite(v).all().item())
     del psi, v, S, V, work, plan
     torch.cuda.empty_cache()
-    alg = 528.0 * n**3
+    alg = 480.0 * n**3
     return {"workload": f"3D hydrodynamic PFC {n}^3 FP32 (psi + 3 velocity components), rho0=gamma=a0=1, r=-0.30, "
                         f"dt=0.25, seed {seed}", "steps": nsteps, "ms_per_step": round(ms, 3),
             "steps_per_s": round(1000.0 / ms, 2), "alg_gbps": round(alg / ms / 1e6, 1),

@@ -163,16 +163,6 @@ hipError_t launch_x_c2r_mac(const Geom &g, const cx<T> *in, T *out, const T *w, 
 }
 
 template <typename T>
-hipError_t launch_spec_deriv(const Geom &g, const cx<T> *in, cx<T> *out, int role, double fk, hipStream_t s)
-{
-    const int64_t n = g.n0 * g.nrows * g.M;
-    const int64_t blocks = cdiv(n, 256) < 16384 ? cdiv(n, 256) : 16384;
-    hipLaunchKernelGGL((spec_deriv_kernel<T>), dim3((unsigned)blocks), dim3(256), 0, s, in, out, g.n0, g.nrows, g.M, role,
-                       fk);
-    return hipGetLastError();
-}
-
-template <typename T>
 hipError_t launch_spec_update(const Geom &g, int op, cx<T> *out, const cx<T> *x0, const cx<T> *x1,
                               const HydroArgs &h, hipStream_t s)
 {
@@ -252,6 +242,28 @@ hipError_t launch_last_c2c(const Geom &g, const cx<T> *src, cx<T> *dst, int dir,
             else
                 hipLaunchKernelGGL((axis_c2c_kernel<T, PL, WM, +1>), grid, block, 0, s, src, dst, W, ncols, ncols,
                                    (int64_t)0, tiles, tw + g.tw_last, g.lt_shift, 1);
+            return hipGetLastError();
+        }
+    });
+}
+
+template <typename T>
+hipError_t launch_last_c2c_deriv(const Geom &g, const cx<T> *src, cx<T> *dst, int role, double fk, const cx<T> *tw,
+                                 hipStream_t s)
+{
+    return by_length(g.n0, [&](auto Lc) -> hipError_t {
+        constexpr int L = decltype(Lc)::value;
+        if constexpr (L < 4) {
+            return hipErrorInvalidValue;
+        } else {
+            using PL = typename AxisPlan<L>::type;
+            constexpr int WM = WMax<T, L>::value;
+            const int64_t ncols = g.nrows * g.M;
+            const int W = (int)(ncols < WM ? ncols : WM);
+            const int64_t tiles = cdiv(ncols, W);
+            const DerivArgs da{role, fk, g.nrows, g.M};
+            hipLaunchKernelGGL((axis_c2c_deriv_kernel<T, PL, WM>), dim3((unsigned)tiles), dim3(WM * PL::Tp), 0, s, src,
+                               dst, W, ncols, ncols, tw + g.tw_last, g.lt_shift, da);
             return hipGetLastError();
         }
     });
@@ -383,9 +395,10 @@ hipError_t launch_export(const Geom &g, const cx<T> *state, cx<T> *out, hipStrea
     template hipError_t launch_y_c2c<T>(const Geom &, cx<T> *, int, const cx<T> *, hipStream_t, int);                 \
     template hipError_t launch_last_fwd<T>(const Geom &, const cx<T> *, cx<T> *, const cx<T> *, hipStream_t);         \
     template hipError_t launch_last_c2c<T>(const Geom &, const cx<T> *, cx<T> *, int, const cx<T> *, hipStream_t);    \
+    template hipError_t launch_last_c2c_deriv<T>(const Geom &, const cx<T> *, cx<T> *, int, double, const cx<T> *,    \
+                                                 hipStream_t);                                                        \
     template hipError_t launch_x_c2r_mac<T>(const Geom &, const cx<T> *, T *, const T *, bool, const cx<T> *,         \
                                             hipStream_t);                                                             \
-    template hipError_t launch_spec_deriv<T>(const Geom &, const cx<T> *, cx<T> *, int, double, hipStream_t);        \
     template hipError_t launch_spec_update<T>(const Geom &, int, cx<T> *, const cx<T> *, const cx<T> *,               \
                                               const HydroArgs &, hipStream_t);                                        \
     template hipError_t launch_last<T>(const Geom &, int, const cx<T> *, cx<T> *, cx<T> *, cx<T> *,                   \

@@ -461,16 +461,28 @@ __device__ __forceinline__ int64_t xcd_tile_order(int64_t b, int64_t n, int G)
     return (grp * 8 + (w & 7)) * G + (w >> 3);
 }
 
+// Spectral first derivative applied on load by the strided FFT (DERIV): multiplies element e of
+// pencil column col = row * M + kx by i k, k along `role` (0: this axis, index e of length L; 1: the
+// rows; 2: x), with k = 0 at a Nyquist index (a first derivative of a real field has no real Nyquist
+// component), computed in FP64 and rounded once.  On the folded column kx = 0 of the packed layout
+// the multiplier is the same for both planes (0 for x), so it applies to X0 + i XN as stored.
+struct DerivArgs {
+    int role;
+    double fk;
+    int64_t nrows, M;
+};
+
 // ------------------------------------------------------------------------------------------------
 // Strided complex FFT along one axis, out of place or in place (src == dst).
 // Pencil (batch, col) has element e at  batch*bstride + e*estride + col,  col < ncols contiguous.
 // A workgroup handles W adjacent columns (W <= WMAX); its threads are laid out column-fastest so
 // each load/store instruction moves W * sizeof(cx) contiguous bytes per element row.  `bid` is the
 // logical tile index (see xcd_tile_order).
-template <typename T, class PL, int WMAX, int DIR, bool NT = false, int G = 1>
+template <typename T, class PL, int WMAX, int DIR, bool NT = false, int G = 1, bool DERIV = false>
 __device__ __forceinline__ void axis_c2c_block(const cx<T> *src, cx<T> *dst, int W, int64_t ncols, int64_t estride,
                                                int64_t bstride, int64_t tiles_per_batch,
-                                               const cx<T> *__restrict__ tw, int lt_shift, int64_t bid, cx<T> *sh)
+                                               const cx<T> *__restrict__ tw, int lt_shift, int64_t bid, cx<T> *sh,
+                                               const DerivArgs &da = DerivArgs{})
 {
     constexpr int L = PL::L, Tp = PL::Tp, R0 = PL::first, Rl = PL::last, Rmax = PL::Rmax;
     const int tid = threadIdx.x, p = tid % WMAX, t = tid / WMAX;
@@ -486,6 +498,25 @@ __device__ __forceinline__ void axis_c2c_block(const cx<T> *src, cx<T> *dst, int
         for (int r = 0; r < R0; ++r)
             v[b * R0 + r] = valid ? ld_grid<NT>(&src[base + (int64_t)(t + b * Tp + r * (L / R0)) * estride])
                                   : cx<T>{T(0), T(0)};
+    if constexpr (DERIV) {
+        const int64_t crow = valid ? col / da.M : 0, ckx = valid ? col - crow * da.M : 0;
+#pragma unroll
+        for (int b = 0; b < PL::nb(R0); ++b)
+            if (PL::jok(t + b * Tp, R0))
+#pragma unroll
+            for (int r = 0; r < R0; ++r) {
+                const int e = t + b * Tp + r * (L / R0);
+                double k;
+                if (da.role == 0)
+                    k = (2 * e == L) ? 0.0 : da.fk * signed_index(e, L);
+                else if (da.role == 1)
+                    k = (2 * crow == da.nrows) ? 0.0 : da.fk * signed_index(crow, da.nrows);
+                else
+                    k = da.fk * (double)ckx;
+                const cx<T> z = v[b * R0 + r];
+                v[b * R0 + r] = {(T)(-k * (double)z.y), (T)(k * (double)z.x)};
+            }
+    }
     constexpr int GW = WMAX / G;  // pencils per LDS group (see fft_stages)
     auto lds = [&](int e) -> cx<T> & { return sh[e * GW + p % GW]; };
     fft_stages<T, PL, DIR, TW_STAGE, G>(v, t, lds, tw, lt_shift, p / GW);
@@ -509,6 +540,18 @@ __global__ __launch_bounds__(WMAX *PL::Tp, OCC) void axis_c2c_kernel(const cx<T>
     __shared__ cx<T> sh[PL::L * WMAX / G];
     axis_c2c_block<T, PL, WMAX, DIR, NT, G>(src, dst, W, ncols, estride, bstride, tiles_per_batch, tw, lt_shift,
                                          xcd_tile_order(blockIdx.x, gridDim.x, xg), sh);
+}
+
+// Inverse strided FFT of the spectral derivative i k_role of `src` (DerivArgs), out of place.
+template <typename T, class PL, int WMAX>
+__global__ __launch_bounds__(WMAX *PL::Tp) void axis_c2c_deriv_kernel(const cx<T> *src, cx<T> *dst, int W,
+                                                                   int64_t ncols, int64_t estride,
+                                                                   const cx<T> *__restrict__ tw, int lt_shift,
+                                                                   DerivArgs da)
+{
+    __shared__ cx<T> sh[PL::L * WMAX];
+    axis_c2c_block<T, PL, WMAX, +1, false, 1, true>(src, dst, W, ncols, estride, 0, (ncols + W - 1) / W, tw,
+                                                    lt_shift, blockIdx.x, sh, da);
 }
 
 // ------------------------------------------------------------------------------------------------
@@ -922,28 +965,6 @@ __device__ __forceinline__ double hy_corr(const HydroArgs &h, double q)
     if (h.model == 0) return a;
     const double b = h.q1sq - q;
     return a * (b * b + h.R1);
-}
-
-// out = D in, D = i k the first derivative along `role` (0: last axis, 1: rows, 2: x), with k = 0
-// at the Nyquist index (a first derivative of a real field has no real Nyquist component).  On the
-// folded column the multiplier is the same for both planes (0 for x), so it applies to X0 + i XN.
-template <typename T>
-__global__ __launch_bounds__(256) void spec_deriv_kernel(const cx<T> *__restrict__ in, cx<T> *__restrict__ out,
-                                                         int64_t L, int64_t nrows, int64_t M, int role, double fk)
-{
-    const int64_t n = L * nrows * M;
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
-        const int64_t kx = i % M, rest = i / M, row = rest % nrows, e = rest / nrows;
-        double k;
-        if (role == 0)
-            k = (2 * e == L) ? 0.0 : fk * signed_index(e, L);
-        else if (role == 1)
-            k = (2 * row == nrows) ? 0.0 : fk * signed_index(row, nrows);
-        else
-            k = fk * (double)kx;  // kx < M: never the Nyquist index; 0 on the folded column
-        const cx<T> z = in[i];
-        out[i] = {(T)(-k * (double)z.y), (T)(k * (double)z.x)};
-    }
 }
 
 enum { HY_PSI = 0, HY_MU = 1, HY_VEL = 2 };

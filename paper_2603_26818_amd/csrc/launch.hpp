@@ -60,15 +60,18 @@ hipError_t launch_last_fwd(const Geom &g, const cx<T> *src, cx<T> *dst, const cx
 template <typename T>
 hipError_t launch_last_c2c(const Geom &g, const cx<T> *src, cx<T> *dst, int dir, const cx<T> *tw, hipStream_t s);
 
+// last-axis inverse FFT of the spectral derivative i k of src along a grid role (0 last axis,
+// 1 rows, 2 x; wavenumber step fk; k = 0 at a Nyquist index), out of place
+template <typename T>
+hipError_t launch_last_c2c_deriv(const Geom &g, const cx<T> *src, cx<T> *dst, int role, double fk, const cx<T> *tw,
+                                 hipStream_t s);
+
 // x_c2r with the hydrodynamic epilogue: out = w * x (+ out when add), w a real field
 template <typename T>
 hipError_t launch_x_c2r_mac(const Geom &g, const cx<T> *in, T *out, const T *w, bool add, const cx<T> *tw,
                             hipStream_t s);
 
-// hydrodynamic spectral operations (kernels.hpp): derivative along a grid role (0 last axis,
-// 1 rows, 2 x) and the in-place updates HY_PSI / HY_MU / HY_VEL
-template <typename T>
-hipError_t launch_spec_deriv(const Geom &g, const cx<T> *in, cx<T> *out, int role, double fk, hipStream_t s);
+// hydrodynamic spectral updates (kernels.hpp), in place: HY_PSI / HY_MU / HY_VEL
 template <typename T>
 hipError_t launch_spec_update(const Geom &g, int op, cx<T> *out, const cx<T> *x0, const cx<T> *x1,
                               const HydroArgs &h, hipStream_t s);

@@ -616,6 +616,17 @@ pfc_status do_hydro_step(pfc_plan *p, const pfc_hydro_params *hp, void *psi_v, v
             PFC_TRY(pfc::launch_x_c2r<T>(g, B, out, b.tw, s), "x_c2r launch");
         return PFC_OK;
     };
+    // the same for the spectral derivative i k_j of `spec`, applied as the last-axis pass loads it
+    auto inv_deriv = [&](const cx<T> *spec, int j, T *out, const T *wf, bool add) -> pfc_status {
+        PFC_TRY(pfc::launch_last_c2c_deriv<T>(g, spec, B, role(j), p->fk[role(j)], b.tw, s),
+                "last-axis derivative inverse launch");
+        if (d == 3) PFC_TRY(pfc::launch_y_c2c<T>(g, B, +1, b.tw, s), "y inverse launch");
+        if (wf)
+            PFC_TRY(pfc::launch_x_c2r_mac<T>(g, B, out, wf, add, b.tw, s), "x_c2r launch");
+        else
+            PFC_TRY(pfc::launch_x_c2r<T>(g, B, out, b.tw, s), "x_c2r launch");
+        return PFC_OK;
+    };
     pfc_status st = PFC_OK;
 #define PFC_HY(call)        \
     do {                    \
@@ -625,10 +636,7 @@ pfc_status do_hydro_step(pfc_plan *p, const pfc_hydro_params *hp, void *psi_v, v
     for (int64_t n = 0; n < nsteps; ++n) {
         // density: A = FFT(psi^3), a = sum_j v_j IFFT(D_j S), B = FFT(a), S update, psi = IFFT(S)
         PFC_HY(fwd(psi, true, A));
-        for (int j = 0; j < d; ++j) {
-            PFC_TRY(pfc::launch_spec_deriv<T>(g, S, B, role(j), p->fk[role(j)], s), "derivative launch");
-            PFC_HY(inv(B, a, vj(j), j > 0));
-        }
+        for (int j = 0; j < d; ++j) PFC_HY(inv_deriv(S, j, a, vj(j), j > 0));
         PFC_HY(fwd(a, false, B));
         PFC_TRY(pfc::launch_spec_update<T>(g, pfc::HYDRO_PSI, S, A, B, ha, s), "density update launch");
         PFC_HY(inv(S, psi, nullptr, false));
@@ -636,8 +644,7 @@ pfc_status do_hydro_step(pfc_plan *p, const pfc_hydro_params *hp, void *psi_v, v
         PFC_HY(fwd(psi, true, A));
         PFC_TRY(pfc::launch_spec_update<T>(g, pfc::HYDRO_MU, A, S, (const cx<T> *)nullptr, ha, s), "mu launch");
         for (int j = 0; j < d; ++j) {
-            PFC_TRY(pfc::launch_spec_deriv<T>(g, A, B, role(j), p->fk[role(j)], s), "derivative launch");
-            PFC_HY(inv(B, h, psi, false));
+            PFC_HY(inv_deriv(A, j, h, psi, false));
             PFC_HY(fwd(h, false, B));
             PFC_TRY(pfc::launch_spec_update<T>(g, pfc::HYDRO_VEL, Vj(j), B, (const cx<T> *)nullptr, ha, s),
                     "velocity update launch");
