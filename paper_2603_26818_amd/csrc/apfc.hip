@@ -5,6 +5,8 @@
 
 namespace pfc {
 
+constexpr int64_t kApfcCUs = 256;  // compute units of the MI355X
+
 template <typename T>
 hipError_t launch_apfc_nonlin(const cx<T> *eta, cx<T> *out, int64_t P, int nf, const ApfcTerm *terms, const int *off,
                               double c3, hipStream_t s)
@@ -58,13 +60,24 @@ hipError_t launch_apfc_last_step(int64_t L, int nf, ApfcStepArgs<T> a, hipStream
         } else {
             using TL = PencilTile<T, LL>;
             using PL = SpreadIf<typename AxisPlan<LL>::type, TL::E>;
-            constexpr int WM = TL::W;
             constexpr bool PF = is_pow2c(LL) && PL::Rmax <= 16;  // state prefetch while registers allow
-            a.W = (int)(a.ncols < WM ? a.ncols : WM);
-            a.tiles = cdiv(a.ncols, a.W);
-            const dim3 grid((unsigned)(a.tiles * nf)), block(WM * PL::Tp);
-            hipLaunchKernelGGL((apfc_last_step_kernel<T, PL, WM, PF, TL::G>), grid, block, 0, s, a);
-            return hipGetLastError();
+            auto run = [&](auto wc, auto gc) -> hipError_t {
+                constexpr int WM = decltype(wc)::value, G = decltype(gc)::value;
+                a.W = (int)(a.ncols < WM ? a.ncols : WM);
+                a.tiles = cdiv(a.ncols, a.W);
+                const dim3 grid((unsigned)(a.tiles * nf)), block(WM * PL::Tp);
+                hipLaunchKernelGGL((apfc_last_step_kernel<T, PL, WM, PF, G>), grid, block, 0, s, a);
+                return hipGetLastError();
+            };
+            // The grouped long tiles fill a CU each: with few pencil columns (2D grids) their count
+            // leaves the last round of workgroups partly empty.  Half-width tiles in one LDS group
+            // (still one per CU) double the count, and the rounds fill up.
+            if constexpr (TL::G == 2 && TL::W == 16) {
+                const int64_t full = cdiv(a.ncols, TL::W) * nf;
+                if (full < 4 * kApfcCUs && (full % kApfcCUs) != 0)
+                    return run(std::integral_constant<int, TL::W / 2>{}, std::integral_constant<int, 1>{});
+            }
+            return run(std::integral_constant<int, TL::W>{}, std::integral_constant<int, TL::G>{});
         }
     });
 }
