@@ -305,7 +305,7 @@ hipError_t launch_last(const Geom &g, int mode, const cx<T> *src, cx<T> *dst, cx
                     b.tiles_per_row = (int)cdiv(g.M, b.W);
                     const int64_t nb = (g.nrows == 1) ? b.tiles_per_row : g.nrows * b.tiles_per_row;
                     return with_nt(g.nt && line_group<T>(b.W) == 1, [&](auto ntc) -> hipError_t {
-                        hipLaunchKernelGGL((last_axis_kernel<T, PL, TL::W, LA_STEP, 1, TL::PF, ORD_TILE,
+                        hipLaunchKernelGGL((last_axis_kernel<T, PL, TL::W, LA_STEP, 1, TL::PF, ORD_XCD_ROW,
                                                              decltype(ntc)::value, TL::G>),
                                            dim3((unsigned)nb), dim3(TL::W * PL::Tp), 0, s, b);
                         return hipGetLastError();
