@@ -531,11 +531,14 @@ __device__ __forceinline__ void axis_c2c_block(const cx<T> *src, cx<T> *dst, int
 }
 
 // Workgroup order: xg >= 1 as xcd_tile_order; xg == 0: workgroup b (on XCD b mod 8) takes the
-// batches congruent to b mod 8, their tiles in order, so each XCD works through whole planes
-// (needs a grid of tiles_per_batch * batches with batches % 8 == 0).  Measured for the 512-point y
-// pass at 512^3 FP32: 188-192 against 206-219 us; slower for the grouped 2048-point tiles.
-__device__ __forceinline__ int64_t plane_xcd_order(int64_t b, int64_t tiles_per_batch)
+// batches congruent to b mod 8, their tiles in order, so each XCD works through whole planes (the
+// batches past the last multiple of 8 keep the tile order).  Measured for the y pass at 512^3 FP32:
+// 188-192 against 206-219 us; at 750^3 (rows not line-aligned, so neighbouring tiles share lines,
+// which now meet in one L2) 1.26 against 1.87 ms; slower for the grouped 2048-point tiles.
+__device__ __forceinline__ int64_t plane_xcd_order(int64_t b, int64_t tiles_per_batch, int64_t nblocks)
 {
+    const int64_t batches = nblocks / tiles_per_batch;
+    if (b >= (batches - batches % 8) * tiles_per_batch) return b;
     const int64_t k = b >> 3;
     return ((k / tiles_per_batch) * 8 + (b & 7)) * tiles_per_batch + k % tiles_per_batch;
 }
@@ -548,7 +551,7 @@ __global__ __launch_bounds__(WMAX *PL::Tp, OCC) void axis_c2c_kernel(const cx<T>
 {
     static_assert(WMAX % G == 0, "groups of whole pencils");
     __shared__ cx<T> sh[PL::L * WMAX / G];
-    const int64_t bid = xg == 0 ? plane_xcd_order(blockIdx.x, tiles_per_batch)
+    const int64_t bid = xg == 0 ? plane_xcd_order(blockIdx.x, tiles_per_batch, gridDim.x)
                                 : xcd_tile_order(blockIdx.x, gridDim.x, xg);
     axis_c2c_block<T, PL, WMAX, DIR, NT, G>(src, dst, W, ncols, estride, bstride, tiles_per_batch, tw, lt_shift, bid,
                                          sh);
@@ -606,8 +609,8 @@ struct SlotInfo {
 //   ORD_XCD_ROW: workgroup b runs on XCD b mod 8 (round-robin dispatch); each XCD takes whole rows
 //            (rows r with r mod 8 = its XCD, tiles in order), so that tiles whose rows are not
 //            line-aligned (natural half spectrum, pitch M + 1) share their boundary lines in one
-//            L2.  Needs nrows % 8 == 0, else ORD_TILE.  Used by the step's fused pass too, where
-//            it measured 1.5-2 % faster than ORD_TILE (512^3 and 2048^3 FP32).
+//            L2; rows past the last multiple of 8 keep the ORD_TILE order.  Used by the step's fused
+//            pass too, where it measured 1.5-2 % faster than ORD_TILE (512^3 and 2048^3 FP32).
 // IL: in the pair tiles, slots alternate between the two rows (slot p and its mirror p ^ 1 hold the
 // same column), so that a pencil and its mirror stay in one group of adjacent slots; otherwise the
 // first W/2 slots hold row k_y and the others row -k_y.
@@ -628,7 +631,7 @@ __device__ __forceinline__ SlotInfo la_slot(int64_t nrows, int TR, int W, int p,
         if (ORD == ORD_ROW) {
             s.row = bid % nrows;
             s.kx = (int)(1 + bid / nrows) * W + p;
-        } else if (ORD == ORD_XCD_ROW && (nrows & 7) == 0) {
+        } else if (ORD == ORD_XCD_ROW && bid < (nrows - (nrows & 7)) * (TR - 1)) {
             const int64_t k = bid >> 3;
             s.row = (k / (TR - 1)) * 8 + (bid & 7);
             s.kx = (int)(1 + k % (TR - 1)) * W + p;
