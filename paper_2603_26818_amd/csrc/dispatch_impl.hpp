@@ -199,8 +199,9 @@ hipError_t launch_y_c2c(const Geom &g, cx<T> *data, int dir, const cx<T> *tw, hi
                 const int W = (int)(g.M < WM ? g.M : WM);
                 const int64_t tiles = cdiv(g.M, W);
                 const dim3 grid((unsigned)(tiles * g.n0)), block(WM * PL::Tp);
-                // whole-line single-group tiles: whole planes per XCD (xg = 0, see axis_c2c_kernel)
-                const int xg = (line_group<T>(W) == 1 && TL::G == 1) ? 0 : line_group<T>(W);
+                // whole-line tiles: whole planes per XCD (xg = 0, see axis_c2c_kernel), except the
+                // grouped power-of-two tiles (2048 points), where it measured slower
+                const int xg = (line_group<T>(W) == 1 && (TL::G == 1 || !is_pow2c(L))) ? 0 : line_group<T>(W);
                 // non-temporal only with whole-line tiles (measured slower on 64-byte tiles)
                 return with_nt(g.nt && xg <= 1, [&](auto ntc) -> hipError_t {
                     constexpr bool NT = decltype(ntc)::value;
