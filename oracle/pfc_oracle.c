@@ -13,10 +13,11 @@
  *     output group otherwise) applied row-column along every axis;
  *   - the PFC free energy, Eq. (3), and the PFC dynamics, Eq. (4), with the correlation operator
  *     written as a polynomial in q = |k|^2 (Eq. (2): a derivative of order n becomes (ik)^n);
- *   - the semi-implicit step of Listing 1 (the update of psiF): the cubic term is evaluated
- *     pointwise in real space and transformed, the linear part is treated implicitly,
- *         psiF <- (psiF + dt*lap*FFT(psi^3)) / (1 - dt*lin),   lap = -q,   lin = -q (eps + L(q)),
- *     followed by the inverse transform back to real space;
+ *   - the semi-implicit step of Listing 1: the cubic term is evaluated pointwise in real space
+ *     and transformed, the linear part is treated implicitly,
+ *         S_k <- (S_k - dt q C_k) / (1 + dt q (eps + L(q))),   C = FFT(psi^3),
+ *     (the listing's Laplacian and linear multipliers are -q and -q (eps + L(q))), followed by
+ *     the inverse transform back to real space;
  *   - the discrete adjoint (transpose of the Jacobian) of that step, used for gradients;
  *   - the hydrodynamic PFC step of the multiphysics section (Eq. (5), (6), Listing 2);
  *   - the complex-amplitude form of the PFC model named at the end of that section (equations and
@@ -385,7 +386,7 @@ int or_step(const or_params *p, double *psi, double *state, int64_t nsteps)
         for (int64_t i = 0; i < N; ++i) cube[i] = p->linear_only ? 0.0 : psi[i] * psi[i] * psi[i];
         e = rfftn_impl(ndim, p->n, cube, NF, !p->no_projection);
         if (e) break;
-        /* semi-implicit update: psiF = (psiF + dt*lap.*FFT(psi^3)) ./ (1 - dt*lin) */
+        /* semi-implicit update: S <- (S + dt lap C) / (1 - dt lin), C = FFT(psi^3) */
 #pragma omp parallel for schedule(static)
         for (int64_t i = 0; i < H; ++i) {
             double q = q_at(p, i);
