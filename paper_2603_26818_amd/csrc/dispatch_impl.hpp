@@ -320,8 +320,8 @@ hipError_t launch_last(const Geom &g, int mode, const cx<T> *src, cx<T> *dst, cx
             // natural layout (rows of M + 1, not line-aligned): whole rows per XCD, so the lines two
             // tiles share meet in one L2 (measured at 512^3: r2c 403 -> 348 us, c2r 274 -> 262 us)
             case LAST_R2C_NATURAL: {
-                // line-aligned chunks where the geometry allows (3D; measured 348 -> see DESIGN), else
-                // column tiles in whole rows per XCD
+                // line-aligned output chunks where the geometry allows (3D r2c at 512^3 FP32: 0.734 ->
+                // 0.660 ms against the tiles below), else column tiles in whole rows per XCD
                 using TL = PencilTile<T, L>;
                 constexpr int C = 128 / (int)sizeof(cx<T>);
                 if constexpr (TL::W == C && L <= 1024) {  // at 2048 the two rounds' registers would spill
