@@ -365,7 +365,7 @@ int or_state_init(const or_params *p, const double *psi0, double *state)
 }
 
 /* nsteps semi-implicit steps (Listing 1).  psi: real field psi^n in, psi^{n+nsteps} out.
- * state: half spectrum psiF, updated in place. */
+ * state: half spectrum S of psi^n, updated in place. */
 int or_step(const or_params *p, double *psi, double *state, int64_t nsteps)
 {
     if (!check_params(p) || nsteps < 0) return OR_ERR_ARG;
@@ -386,13 +386,14 @@ int or_step(const or_params *p, double *psi, double *state, int64_t nsteps)
         for (int64_t i = 0; i < N; ++i) cube[i] = p->linear_only ? 0.0 : psi[i] * psi[i] * psi[i];
         e = rfftn_impl(ndim, p->n, cube, NF, !p->no_projection);
         if (e) break;
-        /* semi-implicit update: S <- (S + dt lap C) / (1 - dt lin), C = FFT(psi^3) */
+        /* semi-implicit update (Eq. (4) in Fourier space: the Laplacian multiplies by -q, the linear
+         * operator by -q (r + L(q)); the cube explicit, the linear part implicit):
+         *     S <- (S - dt q C) / (1 + dt q (r + L(q))),   C = FFT(psi^3) */
 #pragma omp parallel for schedule(static)
         for (int64_t i = 0; i < H; ++i) {
             double q = q_at(p, i);
-            double lap = -q;
-            double lin = -q * (p->r + corr_op(p, q));
-            S[i] = (S[i] + p->dt * lap * NF[i]) / (1.0 - p->dt * lin);
+            double den = 1.0 + p->dt * (q * (p->r + corr_op(p, q)));
+            S[i] = (S[i] - (p->dt * q) * NF[i]) / den;
         }
         if (!p->no_projection) project_hermitian(S, ndim, p->n);
         e = irfftn_impl(ndim, p->n, S, psi);
@@ -513,11 +514,12 @@ int or_step_backward(const or_params *p, const double *psi_n, const double *psi_
  *     d_t psi = lap(dF/dpsi) - v . grad psi,
  *     rho0 d_t v = Gamma lap v - < psi grad(dF/dpsi) >,
  * dF/dpsi = (r + L)psi + psi^3, <.> a Gaussian average of width a0, in Fourier space the factor
- * G(q) = exp(-a0^2 q / 2).  One step, in the order of Listing 2 (psi first; the velocity update
- * then uses the new psi):
- *     psiF <- (psiF + dt (lap FFT(psi^3) - FFT(sum_j v_j IFFT(D_j psiF)))) / (1 - dt lin)
- *     mu   =  FFT(psi^3) + (r + L(q)) psiF                       (the new psi)
- *     vjF  <- (vjF - dt/rho0 G FFT(psi IFFT(D_j mu))) / (1 + dt/rho0 Gamma q)
+ * G(q) = exp(-a0^2 q / 2).  One step, density first (the velocity update then uses the new
+ * density), with S the density's half spectrum, V_j that of v_j and A(q) = 1/(1 + dt q (r + L(q))):
+ *     N = FFT(psi^3),  T = FFT(sum_j v_j IFFT(D_j S))              (advection, explicit)
+ *     S   <- A(q) (S - dt q N - dt T)
+ *     M   =  FFT(psi^3) + (r + L(q)) S                             (chemical potential, new psi)
+ *     V_j <- (V_j - (dt/rho0) G(q) FFT(psi IFFT(D_j M))) / (1 + (dt/rho0) Gamma q)
  * with D_j = i k_j the spectral first derivative.  Readings: k_j is taken as 0 at the Nyquist
  * index of each axis (a first derivative of a real field has no real Nyquist component); both
  * updates use the same dt; every spectrum is projected like the PFC state. */
@@ -579,13 +581,13 @@ int or_hydro_step(const or_params *p, const or_hydro *hp, double *psi, double *p
 #pragma omp parallel for schedule(static)
         for (int64_t i = 0; i < H; ++i) {
             double q = q_at(p, i);
-            double lap = -q, lin = -q * (p->r + corr_op(p, q));
-            S[i] = (S[i] + dt * (lap * NF[i] - th[i])) / (1.0 - dt * lin);
+            double den = 1.0 + dt * (q * (p->r + corr_op(p, q)));
+            S[i] = (S[i] - dt * (q * NF[i] + th[i])) / den;
         }
         project_hermitian(S, ndim, p->n);
         e = irfftn_impl(ndim, p->n, S, psi);
         if (e) break;
-        /* velocity: mu = FFT(psi^3) + (r + L) psiF of the new psi */
+        /* velocity: M = FFT(psi^3) + (r + L) S of the new psi */
 #pragma omp parallel for schedule(static)
         for (int64_t i = 0; i < N; ++i) cube[i] = p->linear_only ? 0.0 : psi[i] * psi[i] * psi[i];
         e = rfftn_impl(ndim, p->n, cube, mu, 1);

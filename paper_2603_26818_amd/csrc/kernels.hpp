@@ -9,8 +9,8 @@
 //         X0_hat(k) = (Z(k) + conj Z(-k)) / 2,   XN_hat(k) = -i (Z(k) - conj Z(-k)) / 2.
 //   natural half    [n0][nrows][M+1] complex
 //
-// Pass schedule of one step (arxiv 2603.26818, Listing 1: cube, forward transform, update of
-// psiF, inverse transform), 3D:
+// Pass schedule of one step (arxiv 2603.26818, Listing 1: cube, forward transform, update of the
+// spectrum, inverse transform), 3D:
 //   x_r2c (cube prologue) -> y forward -> last-axis (z forward, update, z inverse) -> y inverse
 //   -> x_c2r (1/N epilogue);   2D: x_r2c -> last-axis along y -> x_c2r.
 #pragma once

@@ -265,6 +265,55 @@ def test_energy_forms_agree_and_decrease_128sq():
     assert checked == 100
 
 
+def _anti_hermitian_kx0(S):
+    """Norm of X(k) - conj X(-k) on the kx = 0 plane of a 2D half spectrum (0 for a real field)."""
+    X0 = S[:, 0]
+    mirror = np.conj(X0[(-np.arange(X0.shape[0])) % X0.shape[0]])
+    return float(np.linalg.norm(X0 - mirror))
+
+
+def test_half_spectrum_needs_the_hermitian_projection():
+    """The projection of the self-conjugate planes (reading of the half-spectrum state; the paper
+    keeps psi complex in MATLAB and never states one): the same 128^2 run as above, with and without
+    it.  Without it, rounding-level anti-Hermitian content of the kx = 0 plane, which the inverse
+    real transform discards, is multiplied by A(q) = 1/(1 + dt q (r + L(q))) > 1 at every step where
+    r + L(q) < 0; it grows geometrically until the field itself blows up.  With it, that content is
+    exactly zero, the run stays bounded and F does not increase."""
+    shape = (128, 128)
+    psi0 = P.pfc_initial_field(1, shape, -0.25)
+    runs = {}
+    for noproj in (True, False):
+        p = oracle.Params(shape, r=-0.25, dt=0.5, no_projection=noproj)
+        psi, S = psi0.copy(), oracle.state_init(p, psi0)
+        hist = []
+        for _ in range(24):  # 600 steps, recorded every 25
+            psi, S = oracle.step(p, psi, S, 25)
+            m = float(np.abs(psi).max())
+            F, Freal, _ = oracle.energy(p, psi, S)
+            hist.append((m, F, Freal, _anti_hermitian_kx0(S)))
+            if not np.isfinite(m) or m > 10:
+                break
+        runs[noproj] = hist
+    free, proj = runs[True], runs[False]
+    # projected: exactly Hermitian, bounded, F non-increasing, both energy forms agree
+    assert len(proj) == 24
+    assert all(h[3] == 0.0 for h in proj)
+    assert all(h[0] < 1.0 for h in proj)
+    assert all(b[1] <= a[1] + 1e-12 * abs(a[1]) for a, b in zip(proj, proj[1:]))
+    assert all(abs(h[1] - h[2]) < 1e-12 * abs(h[1]) for h in proj)
+    # unprojected: anti-Hermitian content appears at rounding level and grows by many orders
+    assert 0.0 < free[0][3] < 1e-10
+    assert free[-1][3] > 1e6 * free[0][3] or not np.isfinite(free[-1][3])
+    # ... while the field it steps still agrees with the projected run at first
+    assert abs(free[0][0] - proj[0][0]) < 1e-12
+    # it blows up within 600 steps: max|psi| > 10 or non-finite
+    last = free[-1][0]
+    assert not np.isfinite(last) or last > 10
+    # and the spectral energy departs from the real-space one (the state no longer is a real
+    # field's spectrum) before the field does
+    assert any(np.isfinite(h[0]) and h[0] < 1.0 and abs(h[1] - h[2]) > 1e-3 * abs(h[2]) for h in free)
+
+
 # ------------------------------------------------------------------------------------ adjoint pins
 def _fd_jvp(p, psi, v, h=1e-2):
     """J v by central differences.  One step is a cubic polynomial map of psi, so the central
