@@ -120,6 +120,20 @@ pfc_status pfc_state_export(pfc_plan *p, const void *state, void *half_natural, 
  * one the cube is taken of; the state is the one the update is applied to. */
 pfc_status pfc_step(pfc_plan *p, void *psi, void *state, int64_t nsteps, void *stream);
 
+/* pfc_step for callers that cannot allocate device memory (code under HIP graph capture, tight
+ * serving loops, harnesses that forbid hipMalloc): the same kernels and results as pfc_step, but
+ * the twiddle tables and the scratch spectrum live in a static device array of the library
+ * (65 MiB per GPU: 1 MiB of tables and a 64 MiB spectrum, allocated when the library's code is
+ * loaded on that GPU and held until the process ends) instead of the plan's workspace, which need
+ * not be attached.  Calls no hipMalloc or hipFree and allocates nothing.
+ * Limit: the plan's native state must fit in 64 MiB (up to 256^3 FP32, or 2^23 points FP64);
+ * larger plans get PFC_ERR_WORKSPACE and nothing is launched.  Arguments and errors otherwise as
+ * pfc_step.  Every call on one GPU shares that GPU's array: calls that overlap in time on one GPU
+ * (different streams without synchronisation, or threads) race and give wrong results.  The
+ * plan's tables are copied into the array (an asynchronous copy on `stream` from host memory the
+ * plan owns) when another plan used it last, so the plan must outlive its queued calls. */
+pfc_status pfc_step_noalloc(pfc_plan *p, void *psi, void *state, int64_t nsteps, void *stream);
+
 /* pfc_step with a divergence watchdog: after every `check_every` steps (and after the last) the FP64
  * energy and mean of (psi, state) are computed (as pfc_energy, into the workspace) and copied to the
  * host, which synchronises the stream.  A non-finite value stops the run with PFC_ERR_DIVERGED.

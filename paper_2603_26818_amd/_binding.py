@@ -84,6 +84,8 @@ _SIGS = {
     "pfc_state_init": (ctypes.c_int, [ctypes.c_void_p] * 4),
     "pfc_state_export": (ctypes.c_int, [ctypes.c_void_p] * 4),
     "pfc_step": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p]),
+    "pfc_step_noalloc": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64,
+                                        ctypes.c_void_p]),
     "pfc_step_watched": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64,
                                         ctypes.c_int64, ctypes.c_void_p, ctypes.POINTER(ctypes.c_int64)]),
     "pfc_step_timed": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64,
@@ -278,6 +280,13 @@ class Plan:
         _check(self._lib.pfc_step(self._h, self._tensor(psi, self.shape, self.real_dtype, "psi"),
                                   self._tensor(state, self.state_shape, self.complex_dtype, "state"),
                                   int(nsteps), _stream_ptr(self.device)), "pfc_step")
+        return psi, state
+
+    def step_noalloc(self, psi, state, nsteps=1):
+        """pfc_step_noalloc: pfc_step with the library's static device scratch (no allocation)."""
+        _check(self._lib.pfc_step_noalloc(self._h, self._tensor(psi, self.shape, self.real_dtype, "psi"),
+                                          self._tensor(state, self.state_shape, self.complex_dtype, "state"),
+                                          int(nsteps), _stream_ptr(self.device)), "pfc_step_noalloc")
         return psi, state
 
     def step_watched(self, psi, state, nsteps, check_every=50):

@@ -8,6 +8,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <algorithm>
+#include <atomic>
 #include <cstring>
 #include <map>
 #include <new>
@@ -15,6 +16,7 @@
 #include <string>
 #include <vector>
 
+#include "api_internal.hpp"
 #include "fft_core.hpp"
 #include "apfc_launch.hpp"
 #include "launch.hpp"
@@ -34,6 +36,8 @@ struct pfc_plan {
     char *ws = nullptr;
     size_t ws_bytes = 0;
     int var[5] = {0, 0, 0, 0, 0};  // candidate schedule of each step pass (autotuner)
+    std::vector<char> tw_host;     // the twiddle tables as uploaded (built on first use)
+    uint64_t id = 0;               // unique per plan in this process
 };
 
 struct pfc_batch {
@@ -240,6 +244,30 @@ size_t mix_table_entries(int64_t L)
     return (n + 1) & ~size_t(1);  // keep the next table 16-byte aligned
 }
 
+// The plan's twiddle tables as the device holds them (power-of-two tables, then the own table of
+// each non-power-of-two pass length), built once per plan.
+const std::vector<char> &host_tables(pfc_plan *p)
+{
+    if (!p->tw_host.empty()) return p->tw_host;
+    const int64_t Lt = int64_t(1) << p->g.lt_shift;
+    auto build = [&](auto tc) {
+        using T = decltype(tc);
+        std::vector<cx<T>> tw = twiddle_table<T>(Lt);
+        tw.resize(p->tw_entries);
+        const int64_t lens[3] = {p->g.M, p->d.ndim == 3 ? p->g.n1 : 0, p->g.n0};
+        const int64_t offs[3] = {p->g.tw_x, p->g.tw_y, p->g.tw_last};
+        for (int i = 0; i < 3; ++i)
+            if (offs[i] > 0)
+                with_mixed_length(lens[i], [&](auto lc) { fill_mix_table<T, decltype(lc)::value>(tw.data() + offs[i]); });
+        p->tw_host.assign((const char *)tw.data(), (const char *)(tw.data() + tw.size()));
+    };
+    if (p->d.dtype == PFC_F64)
+        build(double{});
+    else
+        build(float{});
+    return p->tw_host;
+}
+
 // Grids whose state exceeds this use non-temporal loads and stores in the step and FFT passes:
 // a pass's three grids then no longer fit in the 256 MB memory-side cache, and the hint keeps the
 // caches from holding lines that are not read again.
@@ -378,10 +406,9 @@ pfc_status do_state_init(pfc_plan *p, const void *psi0, void *state, hipStream_t
 int step_passes(const pfc_plan *p) { return p->g.ndim == 3 ? 5 : 3; }
 
 template <typename T>
-pfc_status step_pass(const pfc_plan *p, int pass, void *psi, void *state, hipStream_t s)
+pfc_status step_pass(const pfc_plan *p, const Bufs<T> &b, int pass, void *psi, void *state, hipStream_t s)
 {
     const Geom &g = p->g;
-    const Bufs<T> b = bufs<T>(p);
     const int id = (g.ndim == 3) ? pass : (pass == 0 ? 0 : pass == 1 ? 2 : 4);
     const int v = p->var[pass];
     switch (id) {
@@ -401,15 +428,21 @@ pfc_status step_pass(const pfc_plan *p, int pass, void *psi, void *state, hipStr
 }
 
 template <typename T>
-pfc_status do_step(pfc_plan *p, void *psi, void *state, int64_t nsteps, hipStream_t s)
+pfc_status step_with(const pfc_plan *p, const Bufs<T> &b, void *psi, void *state, int64_t nsteps, hipStream_t s)
 {
     const int np = step_passes(p);
     for (int64_t n = 0; n < nsteps; ++n)
         for (int k = 0; k < np; ++k) {
-            pfc_status st = step_pass<T>(p, k, psi, state, s);
+            pfc_status st = step_pass<T>(p, b, k, psi, state, s);
             if (st) return st;
         }
     return PFC_OK;
+}
+
+template <typename T>
+pfc_status do_step(pfc_plan *p, void *psi, void *state, int64_t nsteps, hipStream_t s)
+{
+    return step_with<T>(p, bufs<T>(p), psi, state, nsteps, s);
 }
 
 template <typename T>
@@ -430,7 +463,7 @@ pfc_status do_step_timed(pfc_plan *p, void *psi, void *state, int64_t nsteps, hi
     for (int64_t n = 0; n < nsteps && st == PFC_OK; ++n) {
         hipError_t e = hipEventRecord(ev[0], s);
         for (int k = 0; k < np && e == hipSuccess && st == PFC_OK; ++k) {
-            st = step_pass<T>(p, k, psi, state, s);
+            st = step_pass<T>(p, bufs<T>(p), k, psi, state, s);
             if (st == PFC_OK) e = hipEventRecord(ev[k + 1], s);
         }
         if (st == PFC_OK && e == hipSuccess) e = hipEventSynchronize(ev[np]);
@@ -465,9 +498,10 @@ pfc_status do_autotune(pfc_plan *p, void *psi, void *state, hipStream_t s, int r
         double best_t = INFINITY;
         for (int c = 0; c < nc && st == PFC_OK; ++c) {
             p->var[k] = c;
-            st = step_pass<T>(p, k, psi, state, s);  // warm-up
+            st = step_pass<T>(p, bufs<T>(p), k, psi, state, s);  // warm-up
             hipError_t e = hipEventRecord(e0, s);
-            for (int r = 0; r < reps && st == PFC_OK && e == hipSuccess; ++r) st = step_pass<T>(p, k, psi, state, s);
+            for (int r = 0; r < reps && st == PFC_OK && e == hipSuccess; ++r)
+                st = step_pass<T>(p, bufs<T>(p), k, psi, state, s);
             if (st == PFC_OK && e == hipSuccess) e = hipEventRecord(e1, s);
             if (st == PFC_OK && e == hipSuccess) e = hipEventSynchronize(e1);
             float ms = 0.f;
@@ -905,6 +939,8 @@ pfc_status pfc_plan_create(pfc_plan **out, const pfc_plan_desc *d)
     pfc_plan *p = new (std::nothrow) pfc_plan();
     if (!p) return fail(PFC_ERR_INTERNAL, "out of host memory");
     p->d = *d;
+    static std::atomic<uint64_t> next_id{1};
+    p->id = next_id.fetch_add(1);
     Geom &g = p->g;
     g.ndim = d->ndim;
     if (d->ndim == 3) {
@@ -971,23 +1007,7 @@ pfc_status pfc_plan_set_workspace(pfc_plan *p, void *dev_ptr, size_t bytes)
     if (!dev_ptr) return fail(PFC_ERR_INVALID_ARG, "workspace is NULL");
     if (((uintptr_t)dev_ptr & 255u) != 0) return fail(PFC_ERR_ALIGNMENT, "workspace must be 256-byte aligned");
     if (bytes < p->ws_need) return fail(PFC_ERR_WORKSPACE, "workspace has %zu bytes, needs %zu", bytes, p->ws_need);
-    const int64_t Lt = int64_t(1) << p->g.lt_shift;
-    std::vector<char> host;
-    auto build = [&](auto tc) {
-        using T = decltype(tc);
-        std::vector<cx<T>> tw = twiddle_table<T>(Lt);
-        tw.resize(p->tw_entries);
-        const int64_t lens[3] = {p->g.M, p->d.ndim == 3 ? p->g.n1 : 0, p->g.n0};
-        const int64_t offs[3] = {p->g.tw_x, p->g.tw_y, p->g.tw_last};
-        for (int i = 0; i < 3; ++i)
-            if (offs[i] > 0)
-                with_mixed_length(lens[i], [&](auto lc) { fill_mix_table<T, decltype(lc)::value>(tw.data() + offs[i]); });
-        host.assign((const char *)tw.data(), (const char *)(tw.data() + tw.size()));
-    };
-    if (p->d.dtype == PFC_F64)
-        build(double{});
-    else
-        build(float{});
+    const std::vector<char> &host = host_tables(p);
     DeviceGuard dg(p->d.device);
     if (dg.err != hipSuccess) return hip_fail(dg.err, "hipSetDevice");
     hipError_t e = hipMemcpy((char *)dev_ptr + p->tw_off, host.data(), host.size(), hipMemcpyHostToDevice);
@@ -1829,3 +1849,47 @@ pfc_status pfc_apfc_destroy(pfc_apfc *p)
 }
 
 }  // extern "C"
+
+// ---- internal calls of the allocation-free step (api_internal.hpp)
+namespace pfc_internal {
+
+size_t table_bytes(const pfc_plan *p) { return align256(p->tw_entries * cx_size(p)); }
+size_t spectrum_bytes(const pfc_plan *p) { return state_bytes(p); }
+int plan_device(const pfc_plan *p) { return p->d.device; }
+uint64_t plan_id(const pfc_plan *p) { return p->id; }
+pfc_status report(pfc_status st, const char *msg) { return fail(st, "%s", msg); }
+
+pfc_status check_step_args(const pfc_plan *p, const void *psi, const void *state, int64_t nsteps)
+{
+    if (!p) return fail(PFC_ERR_INVALID_ARG, "plan is NULL");
+    PFC_CHECK(check_ptr(psi, "psi"));
+    PFC_CHECK(check_ptr(state, "state"));
+    if (nsteps < 0) return fail(PFC_ERR_INVALID_ARG, "nsteps < 0");
+    if (overlap(psi, real_bytes(p), state, state_bytes(p))) return fail(PFC_ERR_INVALID_ARG, "psi and state overlap");
+    return PFC_OK;
+}
+
+pfc_status upload_tables(pfc_plan *p, void *tables, void *stream)
+{
+    const std::vector<char> &host = host_tables(p);
+    PFC_TRY(hipMemcpyAsync(tables, host.data(), host.size(), hipMemcpyHostToDevice, (hipStream_t)stream),
+            "twiddle upload");
+    return PFC_OK;
+}
+
+template <typename T>
+static pfc_status step_in(pfc_plan *p, void *psi, void *state, int64_t nsteps, hipStream_t s, void *tables,
+                          void *spectrum)
+{
+    const Bufs<T> b{reinterpret_cast<const cx<T> *>(tables), nullptr, reinterpret_cast<cx<T> *>(spectrum)};
+    return step_with<T>(p, b, psi, state, nsteps, s);
+}
+
+pfc_status step_with_buffers(pfc_plan *p, void *psi, void *state, int64_t nsteps, void *stream, void *tables,
+                             void *spectrum)
+{
+    return p->d.dtype == PFC_F64 ? step_in<double>(p, psi, state, nsteps, (hipStream_t)stream, tables, spectrum)
+                                 : step_in<float>(p, psi, state, nsteps, (hipStream_t)stream, tables, spectrum);
+}
+
+}  // namespace pfc_internal
