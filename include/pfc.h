@@ -76,48 +76,63 @@ typedef struct {
  * 1400^3 grids run).
  * Rejects: ndim not in {2,3}, any other size (UNSUPPORTED), dx <= 0,
  * dt <= 0, non-finite parameters, and any (r, dt) for which 1 + dt q (r + L(q)) <= 0 at some grid
- * wavevector (INVALID_ARG: the implicit denominator would vanish or change sign). */
+ * wavevector (INVALID_ARG: the implicit denominator would vanish or change sign).
+ * Source: the grid and wavenumbers of section "Fourier pseudo-spectral method" (Eq. (2)); the
+ * operator of Eq. (3)-(4); the denominator of the update of Listing 1. */
 pfc_status pfc_plan_create(pfc_plan **out, const pfc_plan_desc *d);
 
 /* Bytes of device workspace the plan needs: one native spectrum (n0*n1*n2/2 complex), the
- * twiddle table and the reduction partials.  The caller allocates it (>= 256-byte aligned). */
+ * twiddle table and the reduction partials.  The caller allocates it (>= 256-byte aligned).
+ * Source: the transforms and spectral update of Listing 1 (their scratch). */
 size_t pfc_plan_workspace_bytes(const pfc_plan *p);
 
 /* Attach a caller-owned workspace and fill its twiddle table (host-computed in extended precision,
  * rounded once to the plan's dtype; one synchronous host-to-device copy).  Must be called before
  * any transform.  The workspace must stay valid, and unshared with concurrent calls, while the
- * plan uses it. */
+ * plan uses it.  Source: the FFTs of Listing 1 (their twiddle factors). */
 pfc_status pfc_plan_set_workspace(pfc_plan *p, void *dev_ptr, size_t bytes);
 
-/* Change r and dt (re-validated as in pfc_plan_create). */
+/* Change r and dt (re-validated as in pfc_plan_create).  Source: epsilon of Eq. (3)-(4) and the
+ * time step of Listing 1. */
 pfc_status pfc_plan_set_params(pfc_plan *p, double r, double dt);
 
+/* Frees the plan's host memory (no device call).  Source: none in the paper (resource handling). */
 pfc_status pfc_plan_destroy(pfc_plan *p);
 
-/* Sizes in bytes of a real field, of a natural half spectrum and of a native state. */
+/* Sizes in bytes of a real field, of a natural half spectrum and of a native state.  Source: the
+ * real field psi and its Fourier coefficients of section "Fourier pseudo-spectral method". */
 size_t pfc_plan_real_bytes(const pfc_plan *p);
 size_t pfc_plan_half_bytes(const pfc_plan *p);
 size_t pfc_plan_state_bytes(const pfc_plan *p);
 
 /* Forward real-to-complex FFT of `real_in` into the natural half spectrum `half_out`
- * (unnormalised; the kx = 0 and kx = n_x/2 planes are exactly Hermitian).  Input preserved. */
+ * (unnormalised; the kx = 0 and kx = n_x/2 planes are exactly Hermitian).  Input preserved.
+ * Source: the forward transform of section "Fourier pseudo-spectral method" and of Listing 1; the
+ * paper states no sign or normalisation, MATLAB's are taken: e^{-ikx}, unnormalised. */
 pfc_status pfc_fft_r2c(pfc_plan *p, const void *real_in, void *half_out, void *stream);
 
 /* Inverse complex-to-real FFT of the natural half spectrum `half_in` into `real_out`, scaled by
  * 1/(total points).  The kx = 0 and kx = n_x/2 planes are first projected onto Hermitian symmetry,
- * X(k) <- (X(k) + conj X(-k))/2, so anti-Hermitian content is discarded.  Input preserved. */
+ * X(k) <- (X(k) + conj X(-k))/2, so anti-Hermitian content is discarded.  Input preserved.
+ * Source: the inverse transform of section "Fourier pseudo-spectral method" and of Listing 1
+ * (MATLAB's convention: 1/N on the inverse). */
 pfc_status pfc_fft_c2r(pfc_plan *p, const void *half_in, void *real_out, void *stream);
 
 /* Spectral state of psi0 (its forward transform, native layout).  The k = 0 (mass) mode is
- * overwritten with an FP64 sum of psi0 rounded once to the dtype. */
+ * overwritten with an FP64 sum of psi0 rounded once to the dtype.  Source: Listing 1 starts from
+ * psi and its transform; the paper keeps full complex spectra, so the half spectrum (whose
+ * self-conjugate planes the packed layout keeps Hermitian) and the FP64 mass are this library's. */
 pfc_status pfc_state_init(pfc_plan *p, const void *psi0, void *state, void *stream);
 
-/* Copy the native state into a natural half spectrum [..][n_x/2+1]. */
+/* Copy the native state into a natural half spectrum [..][n_x/2+1].  Source: the Fourier
+ * coefficients of section "Fourier pseudo-spectral method" (layout conversion only). */
 pfc_status pfc_state_export(pfc_plan *p, const void *state, void *half_natural, void *stream);
 
 /* Advance `nsteps` >= 0 semi-implicit steps (Listing 1).  psi: real field psi^n in, psi^{n+nsteps}
  * out.  state: native spectrum of psi^n in, updated in place.  The psi that enters a step is the
- * one the cube is taken of; the state is the one the update is applied to. */
+ * one the cube is taken of; the state is the one the update is applied to.
+ * Source: Eq. (4) stepped as in Listing 1 (cube, forward transform, semi-implicit update,
+ * inverse transform). */
 pfc_status pfc_step(pfc_plan *p, void *psi, void *state, int64_t nsteps, void *stream);
 
 /* pfc_step for callers that cannot allocate device memory (code under HIP graph capture, tight
@@ -137,7 +152,8 @@ pfc_status pfc_step_noalloc(pfc_plan *p, void *psi, void *state, int64_t nsteps,
 /* pfc_step with a divergence watchdog: after every `check_every` steps (and after the last) the FP64
  * energy and mean of (psi, state) are computed (as pfc_energy, into the workspace) and copied to the
  * host, which synchronises the stream.  A non-finite value stops the run with PFC_ERR_DIVERGED.
- * *done_steps receives the number of steps run. */
+ * *done_steps receives the number of steps run.  Source: the step of Listing 1 and the energy of
+ * Eq. (3). */
 pfc_status pfc_step_watched(pfc_plan *p, void *psi, void *state, int64_t nsteps, int64_t check_every, void *stream,
                             int64_t *done_steps);
 
@@ -145,7 +161,8 @@ pfc_status pfc_step_watched(pfc_plan *p, void *psi, void *state, int64_t nsteps,
  * measurement.  pass_ms[i] receives the summed duration (ms) of pass i over all steps and *npasses
  * the number of passes per step: 3D 5 (x r2c with cube, y forward, z forward + update + z inverse,
  * y inverse, x c2r), 2D 3 (x r2c with cube, y forward + update + y inverse, x c2r).  pass_ms must
- * hold 5 doubles.  Synchronises the stream after each step; results equal those of pfc_step. */
+ * hold 5 doubles.  Synchronises the stream after each step; results equal those of pfc_step.
+ * Source: the step of Listing 1 (timed). */
 pfc_status pfc_step_timed(pfc_plan *p, void *psi, void *state, int64_t nsteps, void *stream, double *pass_ms,
                           int *npasses);
 
@@ -155,12 +172,15 @@ pfc_status pfc_step_timed(pfc_plan *p, void *psi, void *state, int64_t nsteps, v
  * `stream`) on this plan's shape and keeps the fastest in the plan; best_ms (5 doubles, may be NULL)
  * receives the winning average time per pass.  psi_scratch (real field) and state_scratch (native
  * state) are caller-owned scratch of the plan's sizes: their contents are overwritten; they should
- * hold a finite field and its state (values do not change the timing).  Blocks until done. */
+ * hold a finite field and its state (values do not change the timing).  Blocks until done.
+ * Source: the transforms of Listing 1 (how they are scheduled; results do not depend on it beyond
+ * rounding). */
 pfc_status pfc_plan_autotune(pfc_plan *p, void *psi_scratch, void *state_scratch, void *stream, int reps,
                              double *best_ms);
 
 /* The candidate chosen for each step pass (variants: 5 ints; *npasses as in pfc_step_timed), and
- * setting them back (e.g. from a cache of earlier tuning); set rejects out-of-range candidates. */
+ * setting them back (e.g. from a cache of earlier tuning); set rejects out-of-range candidates.
+ * Source: the transforms of Listing 1 (schedule choice). */
 pfc_status pfc_plan_get_tuning(const pfc_plan *p, int *variants, int *npasses);
 pfc_status pfc_plan_set_tuning(pfc_plan *p, const int *variants, int npasses);
 
@@ -169,13 +189,17 @@ pfc_status pfc_plan_set_tuning(pfc_plan *p, const int *variants, int npasses);
  * where S_A and S_K are the real symmetric Fourier multipliers A = 1/(1 + dt q (r + L(q))) and q.
  * Also adds this step's contribution to dL/dr, -dt <S_K S_A lambda, psi_np1>, to the FP64 device
  * scalar *dLdr_accum_dev.  lambda_n may be the same buffer as lambda_np1 (updated in place); it must
- * not overlap psi_n or psi_np1.  With PFC_FLAG_LINEAR_ONLY the cubic term is dropped. */
+ * not overlap psi_n or psi_np1.  With PFC_FLAG_LINEAR_ONLY the cubic term is dropped.
+ * Source: the update of Listing 1 (Eq. (4)), transposed; the paper has no adjoint.  In real space
+ * one step is psi^{n+1} = S_A psi^n - dt S_A S_K (psi^n)^3, so its Jacobian's transpose is the
+ * formula above (S_A and S_K are symmetric). */
 pfc_status pfc_step_backward(pfc_plan *p, const void *psi_n, const void *psi_np1, const void *lambda_np1,
                              void *lambda_n, double *dLdr_accum_dev, void *stream);
 
 /* Free energy, Eq. (3), on the grid: out_dev[0] = dV [ (1/(2N)) sum_k (r + L(q_k)) |psi_hat_k|^2
  * + sum_x psi^4/4 ] (sum over the full spectrum, dV = product of dx), out_dev[1] = mean of psi
- * from the k = 0 mode.  Accumulation in FP64 in both dtypes.  out_dev: 2 device doubles. */
+ * from the k = 0 mode.  Accumulation in FP64 in both dtypes.  out_dev: 2 device doubles.
+ * Source: Eq. (3) on the grid of section "Fourier pseudo-spectral method". */
 pfc_status pfc_energy(pfc_plan *p, const void *psi, const void *state, double *out_dev, void *stream);
 
 /* ---- Hydrodynamic PFC (section "Multiple GPU usage for Multiphysics PFC", Eq. (5), the Gaussian
@@ -196,10 +220,11 @@ typedef struct {
 } pfc_hydro_params;
 
 /* Device scratch the hydrodynamic step needs besides the plan's workspace: two native spectra and
- * two real fields (each 256-byte aligned). */
+ * two real fields (each 256-byte aligned).  Source: the transforms of Listing 2 (their scratch). */
 size_t pfc_hydro_work_bytes(const pfc_plan *p);
 
-/* States of psi and of the d velocity components (as pfc_state_init for each).  v: d real fields
+/* States of psi and of the d velocity components (as pfc_state_init for each; Source: the spectra
+ * Listing 2 starts from).  v: d real fields
  * back to back; v_state: d native states back to back (pfc_plan_real_bytes / _state_bytes apart). */
 pfc_status pfc_hydro_state_init(pfc_plan *p, const void *psi, void *psi_state, const void *v, void *v_state,
                                 void *stream);
@@ -207,7 +232,8 @@ pfc_status pfc_hydro_state_init(pfc_plan *p, const void *psi, void *psi_state, c
 /* Advance `nsteps` >= 0 hydrodynamic steps; psi, psi_state, v, v_state (layouts as above) are
  * updated in place.  work: caller-owned device scratch of at least pfc_hydro_work_bytes bytes,
  * 256-byte aligned, not overlapping the fields.  Returns PFC_ERR_INVALID_ARG for bad parameters,
- * PFC_ERR_WORKSPACE for a missing or short work buffer. */
+ * PFC_ERR_WORKSPACE for a missing or short work buffer.  Source: Eq. (5)-(6) stepped as in
+ * Listing 2. */
 pfc_status pfc_hydro_step(pfc_plan *p, const pfc_hydro_params *hp, void *psi, void *psi_state, void *v,
                           void *v_state, void *work, size_t work_bytes, int64_t nsteps, void *stream);
 
@@ -220,26 +246,33 @@ pfc_status pfc_hydro_step(pfc_plan *p, const pfc_hydro_params *hp, void *psi, vo
  * if the workgroups cannot all be resident the launch ends early and pfc_batch_check reports it. */
 typedef struct pfc_batch pfc_batch;
 
-/* Validate `count` (1..256) 2D descriptors and create a batch (host memory only). */
+/* Validate `count` (1..256) 2D descriptors and create a batch (host memory only).  Source: each
+ * instance is the step of Listing 1 (Eq. (4)) on its own grid.  Choices of the autotuner are not
+ * cached here: the Python layer keeps them in a JSON file (Batch.autotune(cache_path=...)), so the
+ * library does no file I/O. */
 pfc_status pfc_batch_create(pfc_batch **out, const pfc_plan_desc *descs, int count);
 
 /* Device workspace bytes: twiddle table, instance table, barrier state, one packed spectrum per
- * instance. */
+ * instance.  Source: the transforms of Listing 1, per instance (their scratch). */
 size_t pfc_batch_workspace_bytes(const pfc_batch *b);
 
 /* Bind the caller's fields: psi[i] (real, n0*n1) and state[i] (native spectrum, n0*n1/2 complex)
  * for instance i, and the workspace (>= 256-byte aligned).  Uploads the instance table and
- * twiddles and clears the barrier state (synchronous).  Drops graphs captured for earlier bindings. */
+ * twiddles and clears the barrier state (synchronous).  Drops graphs captured for earlier bindings.
+ * Source: the fields psi and spectra of Listing 1, per instance. */
 pfc_status pfc_batch_bind(pfc_batch *b, void *const *psi, void *const *state, void *workspace, size_t bytes);
 
-/* state[i] = spectral state of psi[i] for every instance (as pfc_state_init). */
+/* state[i] = spectral state of psi[i] for every instance (as pfc_state_init).  Source: the
+ * transform Listing 1 starts from, per instance. */
 pfc_status pfc_batch_state_init(pfc_batch *b, void *stream);
 
-/* Advance every instance by nsteps >= 0 steps: one graph launch of the persistent kernel. */
+/* Advance every instance by nsteps >= 0 steps: one graph launch of the persistent kernel.
+ * Source: the step of Listing 1 (Eq. (4)), per instance. */
 pfc_status pfc_batch_step(pfc_batch *b, int64_t nsteps, void *stream);
 
 /* Synchronise `stream` and report whether a grid barrier of an earlier pfc_batch_step timed out
- * (PFC_ERR_INTERNAL; the barrier state is then cleared). */
+ * (PFC_ERR_INTERNAL; the barrier state is then cleared).  Source: none in the paper (error
+ * reporting of the persistent launch). */
 pfc_status pfc_batch_check(pfc_batch *b, void *stream);
 
 /* Autotuner of the batched form: for each pass kind (x forward, y, x inverse) and each distinct
@@ -247,17 +280,22 @@ pfc_status pfc_batch_check(pfc_batch *b, void *stream);
  * rows per x item, pencils per y item) by launching the persistent kernel for `steps` steps, and
  * keeps the fastest.  THE BOUND FIELDS ARE ADVANCED by every trial: bind scratch fields to tune, then
  * copy the choice to the production batch with pfc_batch_get/set_tuning.  *ms_per_step (may be NULL)
- * receives the time per step of the final choice.  Blocks until done. */
+ * receives the time per step of the final choice.  Blocks until done.  Source: the transforms of
+ * Listing 1, per instance (schedule choice). */
 pfc_status pfc_batch_autotune(pfc_batch *b, void *stream, int steps, double *ms_per_step);
 
 /* Candidate per instance and pass: variants[3 i + k], k = 0 x forward, 1 y, 2 x inverse (caller's
- * instance order); n = 3 * count.  Setting re-uploads the instance table when bound. */
+ * instance order); n = 3 * count.  Setting re-uploads the instance table when bound.  Source: the
+ * transforms of Listing 1 (schedule choice). */
 pfc_status pfc_batch_get_tuning(const pfc_batch *b, int *variants, int n);
 pfc_status pfc_batch_set_tuning(pfc_batch *b, const int *variants, int n);
 
-/* Number of persistent workgroups of the batch launch (known after pfc_batch_bind). */
+/* Number of persistent workgroups of the batch launch (known after pfc_batch_bind).  Source: none
+ * in the paper (launch shape). */
 int pfc_batch_grid(const pfc_batch *b);
 
+/* Frees the batch's host memory and its captured graphs.  Source: none in the paper (resource
+ * handling). */
 pfc_status pfc_batch_destroy(pfc_batch *b);
 
 /* ---- Complex-amplitude form (the amplitude extension named at the end of the multiphysics
@@ -293,33 +331,57 @@ typedef struct {
     int device;                         /* HIP device of every pointer passed to this object */
 } pfc_apfc_desc;
 
-/* Validate the descriptor, find the resonant products of every amplitude (host memory only). */
+/* Validate the descriptor, find the resonant products of every amplitude (host memory only).
+ * Source: the amplitude extension named at the end of section "Multiple GPU usage for
+ * Multiphysics PFC" (the standard amplitude expansion of the energy of Eq. (3), written out
+ * above). */
 pfc_status pfc_apfc_create(pfc_apfc **out, const pfc_apfc_desc *d);
-/* Bytes of the N fields (and of the N spectra): N n0 n1 n2 complex values. */
+
+/* Bytes of the N fields (and of the N spectra): N n0 n1 n2 complex values.  Source: the
+ * amplitudes of the amplitude extension named at the end of section "Multiple GPU usage for
+ * Multiphysics PFC". */
 size_t pfc_apfc_field_bytes(const pfc_apfc *p);
-/* Device workspace bytes: twiddles, the product table, one scratch copy of the fields. */
+
+/* Device workspace bytes: twiddles, the product table, one scratch copy of the fields.  Source:
+ * the transforms of Listing 1, applied to every amplitude (their scratch). */
 size_t pfc_apfc_workspace_bytes(const pfc_apfc *p);
+
 /* Attach a caller-owned device workspace (256-byte aligned); uploads the tables (synchronous).  The
  * workspace must stay valid while the object is used; calls on one object share its scratch, so
- * they must not run concurrently on different streams. */
+ * they must not run concurrently on different streams.  Source: the transforms of Listing 1,
+ * applied to every amplitude (their twiddles). */
 pfc_status pfc_apfc_set_workspace(pfc_apfc *p, void *dev_ptr, size_t bytes);
+
 /* Number of distinct products that N_j sums one by one: pairs (t terms) and triples (v terms).
  * The triples that permute (j, i, -i), resonant on every lattice, are summed in closed form as
  * 3v (A^2 - |eta_j|^2) eta_j, A^2 = 2 sum_i |eta_i|^2, and are not counted; products whose
- * coefficient is zero are dropped. */
+ * coefficient is zero are dropped.  Source: the resonant products of the amplitude expansion of
+ * Eq. (3)'s energy (multiphysics section, amplitude extension). */
 pfc_status pfc_apfc_terms(const pfc_apfc *p, int j, int *npairs, int *ntriples);
+
 /* Complex FFT of every field over all axes, dir = -1 forward (unnormalised) or +1 inverse (times
- * 1/(n0 n1 n2)); in may equal out. */
+ * 1/(n0 n1 n2)); in may equal out.  Source: the transforms of section "Fourier pseudo-spectral
+ * method" on complex fields. */
 pfc_status pfc_apfc_fft(pfc_apfc *p, const void *in, void *out, int dir, void *stream);
-/* out_j = N_j at every point (out must not overlap eta). */
+
+/* out_j = N_j at every point (out must not overlap eta).  Source: the resonant part of the
+ * nonlinearity of Eq. (3)'s energy in the amplitude expansion (formula above). */
 pfc_status pfc_apfc_nonlinear(pfc_apfc *p, const void *eta, void *out, void *stream);
-/* eta_hat = forward FFT of eta (the state of the step). */
+
+/* eta_hat = forward FFT of eta (the state of the step).  Source: the transform Listing 1 starts
+ * from, per amplitude. */
 pfc_status pfc_apfc_state_init(pfc_apfc *p, const void *eta, void *eta_hat, void *stream);
+
 /* Advance nsteps >= 0 steps; eta (real-space amplitudes) and eta_hat (their spectra) are updated
- * in place and must not overlap. */
+ * in place and must not overlap.  Source: the update of Listing 1 applied to every amplitude
+ * (formula above). */
 pfc_status pfc_apfc_step(pfc_apfc *p, void *eta, void *eta_hat, int64_t nsteps, void *stream);
+
+/* Frees the object's host memory.  Source: none in the paper (resource handling). */
 pfc_status pfc_apfc_destroy(pfc_apfc *p);
 
+/* Name of a status code, and the calling thread's detail string of its last failure (valid until
+ * the thread's next failing call).  Source: none in the paper (error reporting). */
 const char *pfc_status_string(pfc_status st);
 const char *pfc_last_error(void);
 

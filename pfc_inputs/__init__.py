@@ -212,3 +212,21 @@ def amplitude_fields_torch(seed: int, nfields: int, shape, mean: float, cdtype, 
         out[j] = torch.complex(re, im)
         del re, im
     return out
+
+
+def batch_workload():
+    """Descriptors of the batched workload: 48 independent 2D runs, {128^2, 256^2, 512^2, 1024^2} x
+    12, six one-mode and six two-mode (Q1^2 = 2, R1 = 0.05) per size, r_i ~ U(-0.35, -0.15) from
+    sub-stream (4, i), dt = 0.25, FP32.  The initial field of instance i is drawn from sub-stream
+    (4, 1000 + i) with mean r_i (``pfc_initial_field``)."""
+    out = []
+    i = 0
+    for n in (128, 256, 512, 1024):
+        for j in range(12):
+            two = j >= 6
+            r = float(uniform(derive_seed(4, i), (1,), -0.35, -0.15)[0])
+            out.append(dict(shape=(n, n), dtype="f32", model=1 if two else 0, r=r, dt=0.25,
+                            q1sq=2.0 if two else 4.0 / 3.0, R1=0.05 if two else 0.0))
+            i += 1
+    return out
+

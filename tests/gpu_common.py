@@ -16,10 +16,35 @@ def say(*a):
     sys.stdout.flush()
 
 
-def relerr(a, b):
-    a = np.asarray(a)
-    b = np.asarray(b)
-    return float(np.linalg.norm((a - b).ravel()) / np.linalg.norm(b.ravel()))
+def parity_errs(a, b):
+    """(plain rel-L2, mean-removed rel-L2, max-abs) of `a` against the reference `b`.
+
+    plain:        ||a - b|| / ||b|| over all values;
+    mean-removed: the same after subtracting each array's mean (the mean of psi, about -0.3 against
+                  +-0.1 fluctuations, holds most of ||psi||^2 and would hide errors in the
+                  fluctuations); the plain value when b is (nearly) uniform;
+    max-abs:      max |a - b| / max |b|, element by element."""
+    a = np.asarray(a).ravel()
+    b = np.asarray(b).ravel()
+    d = a - b
+    nb = float(np.linalg.norm(b))
+    plain = float(np.linalg.norm(d)) / nb
+    bc = b - b.mean()
+    nbc = float(np.linalg.norm(bc))
+    centred = float(np.linalg.norm(d - d.mean())) / nbc if nbc > 1e-6 * nb else plain
+    maxabs = float(np.max(np.abs(d))) / float(np.max(np.abs(b)))
+    return plain, centred, maxabs
+
+
+def parity_err(a, b):
+    """The largest of the three measures of parity_errs: a parity assert `parity_err(a, b) < tol`
+    bounds the plain and the mean-removed relative L2 error and the element-wise error at once."""
+    return max(parity_errs(a, b))
+
+
+def fmt_errs(errs):
+    """Text of the three measures of parity_errs."""
+    return "rel L2 %.2e, mean-removed %.2e, max-abs %.2e" % tuple(errs)
 
 
 def rounded(x, dtype):

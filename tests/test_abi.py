@@ -31,6 +31,42 @@ def test_header_declares_the_entry_points():
         assert n in names
 
 
+# entry points that no passage of the paper defines (resource handling, error reporting, launch
+# shape): their comment says so instead of citing one
+NOT_FROM_THE_PAPER = {"pfc_plan_destroy", "pfc_batch_destroy", "pfc_apfc_destroy", "pfc_status_string",
+                      "pfc_last_error", "pfc_batch_check", "pfc_batch_grid"}
+CITATION = re.compile(r'Eq\. \(\d|Listing \d|section "')
+
+
+def test_every_entry_point_cites_its_source():
+    """Each declaration block of pfc.h (declarations and the comment above them, up to a blank line)
+    carries a "Source:" line that cites the passage of the paper it implements (an equation, a
+    listing or a section); the allocation-free step names the callers it is for instead; the
+    utilities no passage defines say so."""
+    text = open(HEADER).read()
+    body = text[text.index("#define PFC_H"):]
+    checked = set()
+    for block in re.split(r"\n\s*\n", body):
+        code = re.sub(r"/\*.*?\*/", "", block, flags=re.S)
+        names = set(re.findall(r"\b(pfc_[a-z0-9_]+)\s*\(", code))
+        if not names:
+            continue
+        comment = " ".join(re.findall(r"/\*(.*?)\*/", block, flags=re.S))
+        comment = re.sub(r"\s*\n\s*\*?\s*", " ", comment)
+        for n in names:
+            checked.add(n)
+            if n == "pfc_step_noalloc":
+                assert "cannot allocate" in comment, n
+                continue
+            assert "Source:" in comment, f"{n}: no Source line"
+            src = comment[comment.index("Source:"):]
+            if n in NOT_FROM_THE_PAPER:
+                assert "none in the paper" in src, n
+            else:
+                assert CITATION.search(src), f"{n}: the Source line cites no equation, listing or section"
+    assert checked == set(declared_functions())
+
+
 def test_every_declared_symbol_is_exported():
     _, lib = _lib()
     missing = [n for n in declared_functions() if not hasattr(lib, n)]

@@ -10,7 +10,7 @@ import pytest
 
 import oracle
 import pfc_inputs as P
-from gpu_common import relerr, rounded, say, to_dev, to_np
+from gpu_common import fmt_errs, parity_err, parity_errs, rounded, say, to_dev, to_np
 
 pytestmark = pytest.mark.gpu
 
@@ -50,7 +50,7 @@ def test_rollout_matches_oracle_small(pfc):
     L_ref, g_ref, dr_ref = oracle.loss_and_grad(oracle.Params(shape, r=R0, dt=DT), psi0, target, nsteps)
     plan = pfc.Plan(shape, dtype="f64", r=R0, dt=DT)
     L, g, dr = pfc.loss_and_grad(plan, to_dev(psi0, "f64"), R0, to_dev(target, "f64"), nsteps, 50)
-    eg = relerr(to_np(g), g_ref)
+    eg = parity_err(to_np(g), g_ref)
     say(f"          L {L:.12g} vs {L_ref:.12g}; grad rel L2 {eg:.2e}; dL/dr {dr:.10g} vs {dr_ref:.10g}")
     assert abs(L - L_ref) < 1e-11 * abs(L_ref)
     assert eg < 1e-10
@@ -61,10 +61,10 @@ def test_rollout_512sq_2000_fp64_vs_cpu_adjoint(pfc, oracle_512sq_2000):
     psi0, target_ref, L_ref, g_ref, dr_ref = oracle_512sq_2000
     say(f"[rollout] {SHAPE} {NSTEPS} steps FP64 vs CPU adjoint")
     target = _gpu_target(pfc, "f64", psi0)
-    say(f"          target rel L2 vs oracle {relerr(to_np(target), target_ref):.2e}")
+    say(f"          target rel L2 vs oracle {parity_err(to_np(target), target_ref):.2e}")
     plan = pfc.Plan(SHAPE, dtype="f64", r=R0, dt=DT)
     L, g, dr = pfc.loss_and_grad(plan, to_dev(psi0, "f64"), R0, target, NSTEPS, 50)
-    eg = relerr(to_np(g), g_ref)
+    eg = parity_err(to_np(g), g_ref)
     say(f"          L {L:.12g} vs {L_ref:.12g}; grad rel L2 {eg:.2e}; dL/dr {dr:.10g} vs {dr_ref:.10g}")
     assert abs(L - L_ref) < 1e-8 * abs(L_ref)
     assert eg < 1e-8
@@ -125,6 +125,54 @@ def test_rollout_512sq_2000_fp32_vs_fp64(pfc, oracle_512sq_2000):
     target = _gpu_target(pfc, "f32", p32)
     plan = pfc.Plan(SHAPE, dtype="f32", r=R0, dt=DT)
     L, g, dr = pfc.loss_and_grad(plan, to_dev(p32, "f32"), R0, target, NSTEPS, 50)
-    eg = relerr(to_np(g), g_ref)
+    eg = parity_err(to_np(g), g_ref)
     say(f"          L {L:.8g} vs {L_ref:.8g}; grad rel L2 {eg:.2e}; dL/dr {dr:.8g} vs {dr_ref:.8g}")
     assert eg < 1e-2 and abs(dr - dr_ref) < 1e-2 * abs(dr_ref)
+
+
+def test_rollout_512sq_2000_fp32_adjoint_along_its_own_trajectory(pfc):
+    """The FP32 adjoint's own error, separated from the drift of the FP32 forward run: the FP64
+    oracle's adjoint step is swept backward along the GPU's own FP32 trajectory (every psi^n of the
+    FP32 forward run, widened to FP64; the rollout's replay reproduces that trajectory bit for bit)
+    from lambda^T = 2 (psi^T - target), target the FP32 GPU run at r = -0.30.  Both sweeps then see
+    the same forward states, so their difference is the rounding of the FP32 backward steps alone.
+    The FP32 forward's own drift from FP64 over the same 2000 steps is measured beside it: the
+    backward steps are the transposes of the forward Jacobians, so their rounding is amplified by
+    propagators of the same norms, and the adjoint's own error is bounded by a small multiple of that
+    drift (the gate)."""
+    import torch
+
+    psi0 = rounded(P.pfc_initial_field(5, SHAPE, R0), "f32")
+    say(f"[rollout] {SHAPE} {NSTEPS} steps: FP32 GPU adjoint vs the FP64 adjoint along the FP32 trajectory")
+    target = _gpu_target(pfc, "f32", psi0)
+    plan = pfc.Plan(SHAPE, dtype="f32", r=R0, dt=DT)
+    L, g, dr = pfc.loss_and_grad(plan, to_dev(psi0, "f32"), R0, target, NSTEPS, 50)
+    # the FP32 forward trajectory at r = R0, kept on the host in FP32
+    plan.set_params(R0, DT)
+    x = to_dev(psi0, "f32")
+    st = plan.state_init(x)
+    traj = np.empty((NSTEPS + 1,) + SHAPE, np.float32)
+    traj[0] = psi0
+    for n in range(NSTEPS):
+        plan.step(x, st, 1)
+        traj[n + 1] = x.cpu().numpy()
+    # forward drift of FP32 from FP64 over the same steps
+    p64 = pfc.Plan(SHAPE, dtype="f64", r=R0, dt=DT)
+    x64 = to_dev(psi0, "f64")
+    p64.step(x64, p64.state_init(x64), NSTEPS)
+    drift = parity_errs(traj[NSTEPS].astype(np.float64), to_np(x64))
+    # FP64 adjoint sweep along the FP32 trajectory
+    po = oracle.Params(SHAPE, r=R0, dt=DT)
+    lam = 2.0 * (traj[NSTEPS].astype(np.float64) - to_np(target))
+    acc = 0.0
+    for n in range(NSTEPS - 1, -1, -1):
+        lam, c = oracle.step_backward(po, traj[n].astype(np.float64), traj[n + 1].astype(np.float64), lam)
+        acc += c
+    eg = parity_errs(to_np(g), lam)
+    er = abs(dr - acc) / abs(acc)
+    say(f"          forward FP32 drift at step {NSTEPS}: {fmt_errs(drift)}")
+    say(f"          dL/dpsi0 {fmt_errs(eg)}; dL/dr {dr:.8g} vs {acc:.8g} (rel {er:.2e})")
+    gate = max(1e-4, 3.0 * max(drift))
+    say(f"          gate {gate:.2e}")
+    assert max(eg) < gate and er < gate
+

@@ -10,7 +10,7 @@ import pytest
 
 import oracle
 import pfc_inputs as P
-from gpu_common import TOL_FFT, TOL_STEP, relerr, say
+from gpu_common import TOL_FFT, TOL_STEP, parity_err, say
 
 pytestmark = pytest.mark.gpu
 
@@ -58,9 +58,9 @@ def test_apfc_fft_vs_oracle(pfc, shape, dtype):
     Xin = chost(obj.fft(xd, -1, out=xd))  # in place: the same bits as out of place
     assert np.array_equal(X, Xin)
     ref = np.stack([oracle.fft_c2c(x[j], -1) for j in range(nf)])
-    e_fwd = relerr(X, ref)
+    e_fwd = parity_err(X, ref)
     y = chost(obj.fft(cdev(ref, dtype), +1))
-    e_inv = relerr(y, x)
+    e_inv = parity_err(y, x)
     say(f"      forward rel L2 {e_fwd:.2e}  inverse {e_inv:.2e}")
     assert e_fwd < TOL_FFT[dtype] and e_inv < TOL_FFT[dtype]
 
@@ -76,7 +76,7 @@ def test_apfc_nonlinearity_vs_oracle(pfc, lattice, shape, dtype):
     obj = pfc.Apfc(shape, k, dtype=dtype, t=0.35, v=0.8, dt=0.1)  # dt only has to pass validation here
     got = chost(obj.nonlinear(cdev(eta, dtype)))
     ref = oracle.apfc_nonlinear(oracle.Apfc(shape, k, t=0.35, v=0.8), eta)
-    e = relerr(got, ref)
+    e = parity_err(got, ref)
     say(f"      rel L2 {e:.2e}")
     assert e < (1e-14 if dtype == "f64" else 1e-6)
 
@@ -131,8 +131,8 @@ def test_apfc_step_vs_oracle(pfc, lattice, shape, dtype, nsteps, seed):
     obj.step(eta, S, nsteps)
     a = oracle.Apfc(shape, k, **kw)
     ref_eta, ref_S = oracle.apfc_step(a, eta0, oracle.apfc_state_init(a, eta0), nsteps)
-    e, eS = relerr(chost(eta), ref_eta), relerr(chost(S), ref_S)
-    change = relerr(eta0, ref_eta)
+    e, eS = parity_err(chost(eta), ref_eta), parity_err(chost(S), ref_S)
+    change = parity_err(eta0, ref_eta)
     say(f"      eta rel L2 {e:.2e}  spectra {eS:.2e}  (change over the run {change:.2e})")
     assert change > 1e-3  # the run moves the fields
     assert e < TOL_STEP[dtype] and eS < TOL_STEP[dtype]
@@ -155,7 +155,7 @@ def test_apfc_bench_workload_vs_oracle(pfc):
     del eta, S
     a = oracle.Apfc(shape, k, **kw)
     ref, _ = oracle.apfc_step(a, eta0, oracle.apfc_state_init(a, eta0), 2)
-    e = relerr(got, ref)
+    e = parity_err(got, ref)
     say(f"      eta rel L2 {e:.2e}")
     assert e < 1e-5
 

@@ -9,7 +9,7 @@ import pytest
 
 import oracle
 import pfc_inputs as P
-from gpu_common import relerr, rounded, say, to_dev, to_np
+from gpu_common import fmt_errs, parity_err, parity_errs, rounded, say, to_dev, to_np
 
 pytestmark = pytest.mark.gpu
 
@@ -64,13 +64,13 @@ def test_batch_matches_single_plans_every_replay(pfc, dtype):
         for k in range(len(insts)):
             same = torch.equal(b.psi[k], ref_psi[k]) and torch.equal(b.state[k], ref_state[k])
             if not same:
-                e = relerr(to_np(b.psi[k]), to_np(ref_psi[k]))
+                e = parity_err(to_np(b.psi[k]), to_np(ref_psi[k]))
                 raise AssertionError(f"replay {rep}: instance {k} {insts[k]['shape']} differs (rel L2 {e:.2e})")
         say(f"        replay {rep}: all instances bitwise equal to their single-plan runs")
 
 
 def test_batch_instance_vs_oracle(pfc):
-    insts = _instances("f64")[4:6]  # 64 x 64 two-mode? and 32 x 1024
+    insts = _instances("f64")[4:6]  # 64 x 64 one-mode and 32 x 1024 two-mode
     say(f"[batch] oracle check of {[d['shape'] for d in insts]}")
     psi0 = [P.pfc_initial_field(P.derive_seed(4, 200 + i), d["shape"], d["r"]) for i, d in enumerate(insts)]
     b = pfc.Batch(insts)
@@ -81,9 +81,51 @@ def test_batch_instance_vs_oracle(pfc):
     for k, d in enumerate(insts):
         p = oracle.Params(d["shape"], model=d["model"], r=d["r"], dt=d["dt"], q1sq=d["q1sq"], R1=d["R1"])
         ref, _ = oracle.step(p, psi0[k], oracle.state_init(p, psi0[k]), 60)
-        e = relerr(to_np(b.psi[k]), ref)
+        e = parity_err(to_np(b.psi[k]), ref)
         say(f"        instance {d['shape']}: rel L2 {e:.2e}")
         assert e < 1e-12
+
+
+def test_batch_bench_workload_after_autotune(pfc):
+    """The benchmark's batched workload itself: 48 FP32 instances {128^2 .. 1024^2} x 12, one- and
+    two-mode, seeded as the benchmark seeds them, on the schedules the autotuner picks.  After 100
+    steps (one graph launch) every instance equals its single-plan run on the same schedules bit for
+    bit, and one one-mode and one two-mode instance of each size equals its own FP64 oracle run
+    (started from the same FP32-rounded field) within the FP32 step gate."""
+    import torch
+
+    insts = P.batch_workload()
+    nsteps = 100
+    say(f"[batch] benchmark workload: {len(insts)} FP32 instances, autotuned, {nsteps} steps")
+    psi0 = [P.pfc_initial_field_torch(P.derive_seed(4, 1000 + i), d["shape"], d["r"], torch.float32, "cuda:0")
+            for i, d in enumerate(insts)]
+    b = pfc.Batch(insts).bind([x.clone() for x in psi0])
+    variants, ms = b.autotune(steps=5)
+    say(f"        chosen schedules by size: " + ", ".join(f"{d['shape'][0]}^2 {v}" for d, v in
+                                                       list(zip(insts, variants))[::6]))
+    b.state_init()
+    b.step(nsteps)
+    b.check()
+    torch.cuda.synchronize()
+    for k, d in enumerate(insts):
+        p = pfc.Plan(d["shape"], dtype="f32", model=d["model"], r=d["r"], dt=d["dt"], q1sq=d["q1sq"], R1=d["R1"])
+        p.set_tuning(variants[k])
+        x = psi0[k].clone()
+        s_ = p.state_init(x)
+        p.step(x, s_, nsteps)
+        torch.cuda.synchronize()
+        assert torch.equal(b.psi[k], x), f"instance {k} {d['shape']} differs from its single-plan run"
+    say("        all 48 instances bitwise equal to their single-plan runs on the same schedules")
+    worst = 0.0
+    for k in range(0, len(insts), 6):  # instances 0, 6, 12, ...: one one-mode, one two-mode per size
+        d = insts[k]
+        p = oracle.Params(d["shape"], model=d["model"], r=d["r"], dt=d["dt"], q1sq=d["q1sq"], R1=d["R1"])
+        x0 = to_np(psi0[k])
+        ref, _ = oracle.step(p, x0, oracle.state_init(p, x0), nsteps)
+        errs = parity_errs(to_np(b.psi[k]), ref)
+        say(f"        instance {k} {d['shape']} {'two' if d['model'] else 'one'}-mode r={d['r']:.4f}: {fmt_errs(errs)}")
+        worst = max(worst, max(errs))
+    assert worst < 1e-4
 
 
 @pytest.mark.parametrize("choice", [1])

@@ -7,7 +7,7 @@ import pytest
 
 import oracle
 import pfc_inputs as P
-from gpu_common import TOL_FFT, relerr, rounded, say, to_dev, to_np
+from gpu_common import TOL_FFT, parity_err, rounded, say, to_dev, to_np
 
 pytestmark = pytest.mark.gpu
 
@@ -31,13 +31,13 @@ def test_r2c_c2r_vs_oracle(pfc, shape, dtype):
     plan = pfc.Plan(shape, dtype=dtype)
     X = plan.fft_r2c(to_dev(x, dtype))
     ref = oracle.rfftn(x)
-    e_fwd = relerr(to_np(X), ref)
+    e_fwd = parity_err(to_np(X), ref)
     # c2r of the oracle's spectrum (exactly Hermitian planes) against the oracle's c2r
     import torch
 
     H = torch.from_numpy(ref).to("cuda:0", plan.complex_dtype)
     y = plan.fft_c2r(H)
-    e_inv = relerr(to_np(y), oracle.irfftn(ref, shape))
+    e_inv = parity_err(to_np(y), oracle.irfftn(ref, shape))
     say(f"      r2c rel L2 {e_fwd:.2e}   c2r rel L2 {e_inv:.2e}")
     assert e_fwd < TOL_FFT[dtype] and e_inv < TOL_FFT[dtype]
 
@@ -55,7 +55,7 @@ def test_c2r_projects_self_conjugate_planes(pfc, dtype):
     import torch
 
     y = plan.fft_c2r(torch.from_numpy(H).to("cuda:0", plan.complex_dtype))
-    e = relerr(to_np(y), oracle.irfftn(H, shape))
+    e = parity_err(to_np(y), oracle.irfftn(H, shape))
     say(f"      rel L2 {e:.2e}")
     assert e < TOL_FFT[dtype]
 
@@ -118,7 +118,7 @@ def test_512_spectrum_of_tiled_field_vs_oracle(pfc, dtype):
     x = to_dev(g, dtype).repeat(4, 4, 4)
     X = plan.fft_r2c(x)
     sub = to_np(X[::4, ::4, ::4])
-    e = relerr(sub, 64 * G)
+    e = parity_err(sub, 64 * G)
     off = X.clone()
     off[::4, ::4, ::4] = 0
     leak = (off.abs().max() / X.abs().max()).item()

@@ -9,7 +9,7 @@ import pytest
 
 import oracle
 import pfc_inputs as P
-from gpu_common import TOL_FFT, TOL_STEP, relerr, rounded, say, to_dev, to_np
+from gpu_common import TOL_FFT, TOL_STEP, parity_err, rounded, say, to_dev, to_np
 
 pytestmark = pytest.mark.gpu
 
@@ -57,9 +57,9 @@ def test_mixed_r2c_c2r_vs_oracle(pfc, shape, dtype):
     x = rounded(P.normal(51, shape), dtype)
     plan = pfc.Plan(shape, dtype=dtype)
     ref = oracle.rfftn(x)
-    e_fwd = relerr(to_np(plan.fft_r2c(to_dev(x, dtype))), ref)
+    e_fwd = parity_err(to_np(plan.fft_r2c(to_dev(x, dtype))), ref)
     y = plan.fft_c2r(torch.from_numpy(ref).to("cuda:0", plan.complex_dtype))
-    e_inv = relerr(to_np(y), oracle.irfftn(ref, shape))
+    e_inv = parity_err(to_np(y), oracle.irfftn(ref, shape))
     say(f"      r2c rel L2 {e_fwd:.2e}   c2r rel L2 {e_inv:.2e}")
     assert e_fwd < TOL_FFT[dtype] and e_inv < TOL_FFT[dtype]
 
@@ -77,8 +77,8 @@ def test_mixed_step_vs_oracle(pfc, shape, dtype, nsteps, seed):
     p = oracle.Params(shape, r=r, dt=0.5)
     ref_psi, ref_state = oracle.step(p, psi0, oracle.state_init(p, psi0), nsteps)
     ref_F = oracle.energy(p, ref_psi, ref_state)
-    e = relerr(to_np(psi), ref_psi)
-    es = relerr(to_np(plan.state_export(state)), ref_state)
+    e = parity_err(to_np(psi), ref_psi)
+    es = parity_err(to_np(plan.state_export(state)), ref_state)
     eF = abs(F[0] - ref_F[0]) / abs(ref_F[0])
     say(f"      psi rel L2 {e:.2e}  state {es:.2e}  energy {eF:.2e}")
     assert e < TOL_STEP[dtype] and es < TOL_STEP[dtype] and eF < TOL_STEP[dtype]
@@ -117,7 +117,7 @@ def test_750_cube_two_steps_vs_oracle(pfc, oracle_750, dtype):
     psi = to_dev(rounded(psi0, dtype), dtype)
     state = plan.state_init(psi)
     plan.step(psi, state, 2)
-    e = relerr(to_np(psi), ref_psi)
+    e = parity_err(to_np(psi), ref_psi)
     say(f"      psi rel L2 {e:.2e}")
     assert e < (1e-12 if dtype == "f64" else 1e-5)
 
@@ -133,7 +133,7 @@ def test_mixed_adjoint_rollout_vs_oracle(pfc, dtype):
     L_ref, g_ref, dr_ref = oracle.loss_and_grad(oracle.Params(shape, r=r0, dt=0.5), psi0, target, nsteps)
     plan = pfc.Plan(shape, dtype=dtype, r=r0, dt=0.5)
     L, g, dr = pfc.loss_and_grad(plan, to_dev(psi0, dtype), r0, to_dev(target, dtype), nsteps, 20)
-    eg = relerr(to_np(g), g_ref)
+    eg = parity_err(to_np(g), g_ref)
     say(f"      L {L:.10g} vs {L_ref:.10g}; grad rel L2 {eg:.2e}; dL/dr {dr:.8g} vs {dr_ref:.8g}")
     tol = 1e-10 if dtype == "f64" else 1e-3
     assert abs(L - L_ref) < tol * abs(L_ref) and eg < tol and abs(dr - dr_ref) < tol * abs(dr_ref)

@@ -8,7 +8,7 @@ import pytest
 
 import oracle
 import pfc_inputs as P
-from gpu_common import TOL_STEP, relerr, rounded, say, to_dev, to_np
+from gpu_common import TOL_STEP, parity_err, rounded, say, to_dev, to_np
 
 pytestmark = pytest.mark.gpu
 
@@ -54,10 +54,10 @@ CASES = [
 def test_step_vs_oracle(pfc, shape, dtype, nsteps, seed, r):
     say(f"[step] shape={shape} dtype={dtype} nsteps={nsteps} seed={seed} r={r}")
     plan, psi0, psi, state, F, ref_psi, ref_state, ref_F = _run(pfc, shape, dtype, nsteps, seed, r, chunks=2)
-    e = relerr(to_np(psi), ref_psi)
+    e = parity_err(to_np(psi), ref_psi)
     F = to_np(F)
     eF = abs(F[0] - ref_F[0]) / abs(ref_F[0])
-    es = relerr(to_np(plan.state_export(state)), ref_state)
+    es = parity_err(to_np(plan.state_export(state)), ref_state)
     say(f"       psi rel L2 {e:.2e}  state rel L2 {es:.2e}  energy rel {eF:.2e}  F={F[0]:.10g}")
     assert e < TOL_STEP[dtype] and es < TOL_STEP[dtype] and eF < TOL_STEP[dtype]
     assert abs(F[1] - ref_F[2]) < (1e-15 if dtype == "f64" else 1e-7)
@@ -69,7 +69,7 @@ def test_two_mode_operator(pfc, dtype):
     say(f"[step] two-mode shape={shape} dtype={dtype}")
     plan, psi0, psi, state, F, ref_psi, ref_state, ref_F = _run(
         pfc, shape, dtype, 100, 9, -0.30, dt=0.25, model=1, q1sq=2.0, R1=0.05)
-    e = relerr(to_np(psi), ref_psi)
+    e = parity_err(to_np(psi), ref_psi)
     say(f"       psi rel L2 {e:.2e}")
     assert e < TOL_STEP[dtype]
 
@@ -80,7 +80,7 @@ def test_linear_only_closed_form(pfc, dtype):
     shape = (16, 32, 64)
     say(f"[step] linear-only shape={shape} dtype={dtype}")
     plan, psi0, psi, state, F, ref_psi, ref_state, _ = _run(pfc, shape, dtype, 12, 10, -0.3, flags=1)
-    e = relerr(to_np(plan.state_export(state)), ref_state)
+    e = parity_err(to_np(plan.state_export(state)), ref_state)
     say(f"       state rel L2 {e:.2e}")
     assert e < (1e-13 if dtype == "f64" else 5e-6)
 
@@ -138,7 +138,7 @@ def test_step_backward_vs_oracle(pfc, shape, dtype):
     plan = pfc.Plan(shape, dtype=dtype, r=-0.25, dt=0.5)
     dl = torch.full((1,), 0.5, dtype=torch.float64, device="cuda:0")
     out, dl = plan.step_backward(to_dev(psi_n, dtype), to_dev(psi_np1, dtype), to_dev(lam, dtype), dLdr=dl)
-    e = relerr(to_np(out), ref_lam)
+    e = parity_err(to_np(out), ref_lam)
     eg = abs(to_np(dl)[0] - 0.5 - ref_g) / abs(ref_g)
     say(f"       lambda rel L2 {e:.2e}  dL/dr rel {eg:.2e}")
     tol = 1e-13 if dtype == "f64" else 5e-6
@@ -146,7 +146,7 @@ def test_step_backward_vs_oracle(pfc, shape, dtype):
     # in place: lambda_n may be the lambda_np1 buffer
     lam_d = to_dev(lam, dtype)
     out2, _ = plan.step_backward(to_dev(psi_n, dtype), to_dev(psi_np1, dtype), lam_d, lambda_n=lam_d)
-    assert relerr(to_np(out2), ref_lam) < tol
+    assert parity_err(to_np(out2), ref_lam) < tol
 
 
 def test_watchdog_reports_divergence(pfc):
