@@ -55,30 +55,13 @@ def measured_traffic(kernel):
     return t["kernels"][kernel].get("hbm_bytes_per_launch")
 
 
-def batched_instances():
-    """48 independent 2D runs: {128^2, 256^2, 512^2, 1024^2} x 12, six one-mode and six two-mode
-    (Q1^2 = 2, R1 = 0.05) per size, r_i ~ U(-0.35, -0.15) from sub-stream (4, i), dt = 0.25, FP32."""
-    import pfc_inputs
-
-    out = []
-    i = 0
-    for n in (128, 256, 512, 1024):
-        for j in range(12):
-            two = j >= 6
-            r = float(pfc_inputs.uniform(pfc_inputs.derive_seed(4, i), (1,), -0.35, -0.15)[0])
-            out.append(dict(shape=(n, n), dtype="f32", model=1 if two else 0, r=r, dt=0.25,
-                            q1sq=2.0 if two else 4.0 / 3.0, R1=0.05 if two else 0.0))
-            i += 1
-    return out
-
-
 def bench_batched(nsteps):
     import torch
 
     import paper_2603_26818_amd as pfc
     import pfc_inputs
 
-    insts = batched_instances()
+    insts = pfc_inputs.batch_workload()
     psis = [pfc_inputs.pfc_initial_field_torch(pfc_inputs.derive_seed(4, 1000 + i), d["shape"], d["r"],
                                                torch.float32, "cuda:0") for i, d in enumerate(insts)]
     b = pfc.Batch(insts).bind(psis)
@@ -190,39 +173,141 @@ def bench_amplitude(nsteps, shape=(256, 256, 256), lattice="bcc", seed=7):
             "frac": round(alg / ms / 1e6 / PEAK_HBM_GBPS, 4), "fields_finite": finite}
 
 
-def bench_big(nsteps, n=2048, seed=3):
-    """3D one-mode PFC at n^3 FP32 (r = -0.30, dt = 0.5): steps/s and per-pass GB/s.  n = 2048: the
-    full single-GPU size; n = 750: the paper's smaller 3D grid (mixed radix, 750 = 2 3 5^3)."""
+def median_spread(vals):
+    v = sorted(vals)
+    return v[len(v) // 2], v[0], v[-1]
+
+
+def bench_big(nsteps, n=2048, seed=3, dtype="f32", reps=1, profile_steps=3):
+    """3D one-mode PFC at n^3 (r = -0.30, dt = 0.5, psi0 = -0.30 + U(-0.1, 0.1) from `seed`):
+    steps/s (median of `reps` timed runs of nsteps steps, with the spread) and per-pass GB/s on the
+    5-pass model (12 field-sized reads or writes per point).  n = 2048: the full single-GPU size;
+    750 and 1400: the paper's 3D grids (mixed radix); 256 and 512 in FP64 and FP32."""
     import torch
 
     import paper_2603_26818_amd as pfc
     import pfc_inputs
 
     shape = (n, n, n)
-    plan = pfc.Plan(shape, dtype="f32", r=R, dt=DT)
-    psi = pfc_inputs.pfc_initial_field_torch(seed, shape, R, torch.float32, "cuda:0")
+    tdt = torch.float32 if dtype == "f32" else torch.float64
+    plan = pfc.Plan(shape, dtype=dtype, r=R, dt=DT)
+    psi = pfc_inputs.pfc_initial_field_torch(seed, shape, R, tdt, "cuda:0")
     state = plan.state_init(psi)
     plan.step(psi, state, 2)
     stream = torch.cuda.current_stream()
     torch.cuda.synchronize()
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    e0.record(stream)
-    plan.step(psi, state, nsteps)
-    e1.record(stream)
-    torch.cuda.synchronize()
-    ms = e0.elapsed_time(e1) / nsteps
-    pass_ms = plan.step_timed(psi, state, 3)
+    runs = []
+    for _ in range(reps):
+        e0.record(stream)
+        plan.step(psi, state, nsteps)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        runs.append(e0.elapsed_time(e1) / nsteps)
+    ms, ms_lo, ms_hi = median_spread(runs)
+    pass_ms = plan.step_timed(psi, state, profile_steps)
     F = plan.energy(psi, state).cpu().tolist()
-    Rb = n**3 * 4
+    Rb = n**3 * (4 if dtype == "f32" else 8)
     alg = [2 * Rb, 2 * Rb, 4 * Rb, 2 * Rb, 2 * Rb]
-    passes = [{"kernel": k, "avg_ms": round(t / 3, 3), "alg_gbps": round(b / (t / 3) / 1e6, 1),
-               "frac": round(b / (t / 3) / 1e6 / PEAK_HBM_GBPS, 4)} for k, t, b in zip(PASS_NAMES, pass_ms, alg)]
+    passes = [{"kernel": k, "avg_ms": round(t / profile_steps, 4), "alg_bytes": b,
+               "alg_gbps": round(b / (t / profile_steps) / 1e6, 1),
+               "frac": round(b / (t / profile_steps) / 1e6 / PEAK_HBM_GBPS, 4)}
+              for k, t, b in zip(PASS_NAMES, pass_ms, alg)]
     del psi, state, plan
     torch.cuda.empty_cache()
-    return {"workload": f"3D one-mode PFC {n}^3 FP32, r=-0.30, dt=0.5, psi0 seed {seed}", "steps": nsteps,
-            "ms_per_step": round(ms, 3), "steps_per_s": round(1000.0 / ms, 2),
-            "alg_gbps": round(12 * Rb / ms / 1e6, 1), "frac": round(12 * Rb / ms / 1e6 / PEAK_HBM_GBPS, 4),
-            "passes": passes, "energy_finite": all(math.isfinite(v) for v in F)}
+    out = {"workload": f"3D one-mode PFC {n}^3 {dtype.upper()}, r=-0.30, dt=0.5, psi0 seed {seed}", "steps": nsteps,
+           "ms_per_step": round(ms, 4), "steps_per_s": round(1000.0 / ms, 2),
+           "alg_gbps": round(12 * Rb / ms / 1e6, 1), "frac": round(12 * Rb / ms / 1e6 / PEAK_HBM_GBPS, 4),
+           "passes": passes, "energy_finite": all(math.isfinite(v) for v in F)}
+    if reps > 1:
+        out["reps"] = reps
+        out["steps_per_s_min_max"] = [round(1000.0 / ms_hi, 2), round(1000.0 / ms_lo, 2)]
+    return out
+
+
+def bench_fft(n, dtype, reps, seed):
+    """Standalone 3D r2c and c2r on a seeded N(0, 1) field, natural half spectrum: ms per transform
+    (average over `reps`) and GB/s on the 3-pass model Rb + 5 Cn (real field once, the half spectrum
+    written or read once by the x pass and read and written by each of the y and z passes)."""
+    import torch
+
+    import paper_2603_26818_amd as pfc
+    import pfc_inputs
+
+    shape = (n, n, n)
+    tdt = torch.float32 if dtype == "f32" else torch.float64
+    s = 4 if dtype == "f32" else 8
+    plan = pfc.Plan(shape, dtype=dtype, r=R, dt=DT)
+    stream = torch.cuda.current_stream()
+    x = pfc_inputs.normal_torch(seed, shape, tdt, "cuda:0")
+    X = plan.fft_r2c(x)
+    y = plan.fft_c2r(X)
+    torch.cuda.synchronize()
+
+    def timed(fn):
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record(stream)
+        for _ in range(reps):
+            fn()
+        b.record(stream)
+        torch.cuda.synchronize()
+        return a.elapsed_time(b) / reps
+
+    t_r2c = timed(lambda: plan.fft_r2c(x, X))
+    t_c2r = timed(lambda: plan.fft_c2r(X, y))
+    rt_err = (torch.linalg.vector_norm((y - x).double()) / torch.linalg.vector_norm(x.double())).item()
+    Rb = n**3 * s
+    Cn = n * n * (n // 2 + 1) * 2 * s
+    fft_bytes = Rb + 5 * Cn
+    del x, X, y, plan
+    torch.cuda.empty_cache()
+    return {"workload": f"3D r2c/c2r {n}^3 {dtype.upper()}, N(0,1) seed {seed}", "r2c_ms": round(t_r2c, 4),
+            "c2r_ms": round(t_c2r, 4), "r2c_gbps": round(fft_bytes / t_r2c / 1e6, 1),
+            "c2r_gbps": round(fft_bytes / t_c2r / 1e6, 1),
+            "r2c_frac": round(fft_bytes / t_r2c / 1e6 / PEAK_HBM_GBPS, 4),
+            "c2r_frac": round(fft_bytes / t_c2r / 1e6 / PEAK_HBM_GBPS, 4),
+            "alg_bytes": fft_bytes, "roundtrip_rel_l2": rt_err}
+
+
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def bench_cpu(nsteps_all, nsteps_one):
+    """The FP64 C oracle on this host, on the 512^3 headline workload: `nsteps_all` steps with its
+    default thread count (OMP_NUM_THREADS, else all host threads) and `nsteps_one` steps on one
+    thread."""
+    import oracle
+    import pfc_inputs
+
+    shape = (N, N, N)
+    p = oracle.Params(shape, r=R, dt=DT)
+    psi0 = pfc_inputs.pfc_initial_field(SEED, shape, R).astype("float32").astype("float64")
+    s0 = oracle.state_init(p, psi0)
+    threads = oracle.num_threads()
+    t0 = time.perf_counter()
+    oracle.step(p, psi0, s0, nsteps_all)
+    dt_all = time.perf_counter() - t0
+    out = {"value": round(nsteps_all / dt_all, 4), "unit": "steps/s", "cores": threads, "kind": "oracle",
+           "sample": f"{nsteps_all} steps of the 512^3 workload by the FP64 C oracle (recursive Cooley-Tukey "
+                     f"FFT, radix 2 at this size, OpenMP over lines) on {threads} threads, {dt_all:.1f} s",
+           "cpu_model": cpu_model(), "host_cpus": os.cpu_count()}
+    if nsteps_one > 0:
+        oracle.set_num_threads(1)
+        t0 = time.perf_counter()
+        oracle.step(p, psi0, s0, nsteps_one)
+        dt_one = time.perf_counter() - t0
+        oracle.set_num_threads(threads)
+        out["one_thread"] = {"value": round(nsteps_one / dt_one, 4), "unit": "steps/s", "cores": 1,
+                             "sample": f"{nsteps_one} step(s) of the same workload on 1 thread, {dt_one:.1f} s"}
+    return out
 
 
 def bench_adjoint(nsteps, every):
@@ -259,9 +344,10 @@ def bench_adjoint(nsteps, every):
 KERNEL_PASS = {"x_r2c_kernel": "x_r2c_cube", "last_axis_kernel": "z_fused_update", "x_c2r_kernel": "x_c2r"}
 
 
-def counters_workload(steps):
+def counters_workload(steps, n=N):
     """Workload of the counter runs: a plain 1 GiB device copy (calibration of FETCH_SIZE and
-    WRITE_SIZE against known bytes), then `steps` steps of the 512^3 FP32 workload."""
+    WRITE_SIZE against known bytes), then `steps` steps of the n^3 FP32 workload (512: the headline;
+    other sizes use their benchmark seeds: 750 -> 7, 1400 -> 8, 2048 -> 3)."""
     import torch
 
     import paper_2603_26818_amd as pfc
@@ -273,15 +359,17 @@ def counters_workload(steps):
         torch.neg(x, out=y)  # a plain streaming kernel of known bytes with a distinctive name
     torch.cuda.synchronize()
     del x, y
-    shape = (N, N, N)
+    torch.cuda.empty_cache()
+    seed = {512: SEED, 750: 7, 1400: 8, 2048: 3}.get(n, SEED)
+    shape = (n, n, n)
     plan = pfc.Plan(shape, dtype="f32", r=R, dt=DT)
-    psi = pfc_inputs.pfc_initial_field_torch(SEED, shape, R, torch.float32, "cuda:0")
+    psi = pfc_inputs.pfc_initial_field_torch(seed, shape, R, torch.float32, "cuda:0")
     state = plan.state_init(psi)
     plan.step(psi, state, steps)
     torch.cuda.synchronize()
 
 
-def write_traffic(fetch_dir, write_dir, out_path, command):
+def write_traffic(fetch_dir, write_dir, out_path, command, n=N):
     """Per-dispatch HBM bytes of the step kernels from two rocprofv3 --pmc runs (FETCH_SIZE and
     WRITE_SIZE, KiB per dispatch), each scaled by the factor that makes the 1 GiB copy read and
     write exactly 1 GiB."""
@@ -335,21 +423,31 @@ def write_traffic(fetch_dir, write_dir, out_path, command):
         wb = sum(wv) / len(wv) * w_fac
         kernels[short] = {"fetch_bytes_per_launch": round(fb), "write_bytes_per_launch": round(wb),
                           "hbm_bytes_per_launch": round(fb + wb), "dispatches": len(vals), "kernel": bare[:120]}
-    out = {"command": command, "kernel_hash": kernel_hash(), "copy_calibration_bytes": copy_bytes,
+    Rb = n**3 * 4  # algorithmic bytes per launch (FP32): x passes Rb + Cb, y 2 Cb, z 4 Cb (Cb = Rb)
+    alg = {"x_r2c_cube": 2 * Rb, "y_fwd_or_inv": 2 * Rb, "z_fused_update": 4 * Rb, "x_c2r": 2 * Rb}
+    for k, v in kernels.items():
+        v["alg_bytes_per_launch"] = alg[k]
+        v["traffic_over_alg"] = round(v["hbm_bytes_per_launch"] / alg[k], 4)
+    out = {"command": command, "grid": [n, n, n], "kernel_hash": kernel_hash(), "copy_calibration_bytes": copy_bytes,
            "fetch_factor_bytes_per_unit": f_fac, "write_factor_bytes_per_unit": w_fac, "kernels": kernels}
     with open(out_path, "w") as f:
         json.dump(out, f, indent=1)
     print(json.dumps(out, indent=1))
 
 
+LEGS = ("headline", "fft", "fp64", "cube256", "big", "paper", "hydro", "amp", "batch", "adjoint", "cpu")
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=300)
+    ap.add_argument("--steps", type=int, default=300, help="timed steps of each headline repetition")
     ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--reps", type=int, default=5, help="timed repetitions of the headline (median reported)")
     ap.add_argument("--profile-steps", type=int, default=30, help="steps of the per-pass timed run")
     ap.add_argument("--fft-reps", type=int, default=20)
     ap.add_argument("--cpu-steps", type=int, default=3, help="oracle steps of the CPU baseline (0: skip)")
+    ap.add_argument("--cpu-steps-1t", type=int, default=1, help="oracle steps of the one-thread CPU baseline")
     ap.add_argument("--batch-steps", type=int, default=500, help="steps of the batched form (0: skip)")
     ap.add_argument("--adjoint-steps", type=int, default=2000, help="steps of the adjoint form (0: skip)")
     ap.add_argument("--big-steps", type=int, default=50, help="timed steps at 2048^3 (0: skip)")
@@ -357,21 +455,30 @@ def main():
     ap.add_argument("--amp-steps", type=int, default=20, help="timed complex-amplitude steps at 256^3 (0: skip)")
     ap.add_argument("--paper-steps", type=int, default=20,
                     help="timed steps at 750^3 and 1400^3, the paper's 3D grids (0: skip)")
+    ap.add_argument("--legs", default=",".join(LEGS),
+                    help="comma-separated legs to run (default: all): " + ", ".join(LEGS))
     ap.add_argument("--counters", type=int, default=0, metavar="STEPS",
                     help="run only the workload of the rocprofv3 --pmc runs (copy calibration + STEPS steps)")
     ap.add_argument("--write-traffic", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
                     help="summarise two rocprofv3 --pmc output folders into " + os.path.relpath(TRAFFIC_FILE, ROOT))
     ap.add_argument("--traffic-command", default="", help="command line recorded in the traffic summary")
+    ap.add_argument("--grid", type=int, default=N, help="grid size n of the --counters / --write-traffic workload")
     args = ap.parse_args()
     if args.write_traffic:
-        write_traffic(args.write_traffic[0], args.write_traffic[1], TRAFFIC_FILE, args.traffic_command)
+        out = TRAFFIC_FILE if args.grid == N else os.path.join(ROOT, "profiles", f"traffic_{args.grid}cube_f32.txt")
+        write_traffic(args.write_traffic[0], args.write_traffic[1], out, args.traffic_command, args.grid)
         return
     if args.counters:
-        counters_workload(args.counters)
+        counters_workload(args.counters, args.grid)
         return
     if args.gpus != 1:
         print("bench.py runs on one GPU only: the library has no multi-GPU path (the step would shard by "
               "slabs of the slowest axis with two all-to-all transposes per step).", file=sys.stderr)
+        sys.exit(2)
+    legs = set(x.strip() for x in args.legs.split(",") if x.strip())
+    unknown = legs - set(LEGS)
+    if unknown:
+        print(f"unknown legs {sorted(unknown)}; known: {', '.join(LEGS)}", file=sys.stderr)
         sys.exit(2)
 
     import torch
@@ -379,103 +486,101 @@ def main():
     import paper_2603_26818_amd as pfc
     import pfc_inputs
 
-    shape = (N, N, N)
     dev = torch.device("cuda", 0)
     torch.cuda.set_device(dev)
-    plan = pfc.Plan(shape, dtype="f32", r=R, dt=DT, device=0)
-    log(f"[bench] drawing psi0 {shape} seed {SEED}")
-    psi = pfc_inputs.pfc_initial_field_torch(SEED, shape, R, torch.float32, dev)
-    state = plan.state_init(psi)
     stream = torch.cuda.current_stream(dev)
-
-    log(f"[bench] warmup {args.warmup} steps")
-    plan.step(psi, state, args.warmup)
-    torch.cuda.synchronize()
-
-    log(f"[bench] timed {args.steps} steps")
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    e0.record(stream)
-    plan.step(psi, state, args.steps)
-    e1.record(stream)
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    ms_per_step = e0.elapsed_time(e1) / args.steps
-    steps_per_s = 1000.0 / ms_per_step
-    log(f"[bench] {ms_per_step:.4f} ms/step ({steps_per_s:.1f} steps/s), wall {wall:.3f} s")
-
-    F = plan.energy(psi, state).cpu().tolist()
-    if not all(math.isfinite(v) for v in F):
-        log(f"[bench] non-finite energy {F}")
-        sys.exit(1)
-
-    # per-pass durations, HIP events on the same stream, in a separate run of profile-steps steps
-    log(f"[bench] per-pass timing over {args.profile_steps} steps")
-    pass_ms = plan.step_timed(psi, state, args.profile_steps)
-    Rb = N**3 * 4  # real field, FP32
-    Cb = N**3 // 2 * 8  # packed spectrum (same bytes as the real field)
-    alg = [Rb + Cb, 2 * Cb, 4 * Cb, 2 * Cb, Cb + Rb]  # algorithmic HBM bytes per launch
-    passes = []
-    for name, tot, b in zip(PASS_NAMES, pass_ms, alg):
-        avg = tot / args.profile_steps
-        passes.append({"kernel": name, "avg_ms": round(avg, 5), "alg_bytes": b, "alg_gbps": round(b / avg / 1e6, 1),
-                       "frac": round(b / avg / 1e6 / PEAK_HBM_GBPS, 4)})
-    dom = max(passes, key=lambda p: p["avg_ms"])
-    step_bytes = sum(alg)
-    roofline = {"bound": "hbm", "kernel": dom["kernel"], "achieved": dom["alg_gbps"], "peak": PEAK_HBM_GBPS,
-                "unit": "GB/s", "frac": dom["frac"], "traffic": measured_traffic(dom["kernel"]),
-                "alg_bytes_per_launch": dom["alg_bytes"], "avg_ms": dom["avg_ms"]}
-
-    # standalone 3D r2c / c2r at 512^3 FP32 on seeded N(0,1) (seed 22), natural half spectrum
-    log(f"[bench] r2c / c2r {args.fft_reps} reps each")
-    x = pfc_inputs.normal_torch(22, shape, torch.float32, dev)
-    X = plan.fft_r2c(x)
-    y = plan.fft_c2r(X)
-    torch.cuda.synchronize()
-
-    def timed(fn):
-        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        a.record(stream)
-        for _ in range(args.fft_reps):
-            fn()
-        b.record(stream)
+    shape = (N, N, N)
+    ms_per_step = steps_per_s = None
+    roofline = passes = spread = F = None
+    step_bytes = 12 * N**3 * 4
+    if "headline" in legs:
+        plan = pfc.Plan(shape, dtype="f32", r=R, dt=DT, device=0)
+        log(f"[bench] drawing psi0 {shape} seed {SEED}")
+        psi = pfc_inputs.pfc_initial_field_torch(SEED, shape, R, torch.float32, dev)
+        state = plan.state_init(psi)
+        log(f"[bench] warmup {args.warmup} steps")
+        plan.step(psi, state, args.warmup)
         torch.cuda.synchronize()
-        return a.elapsed_time(b) / args.fft_reps
-
-    t_r2c = timed(lambda: plan.fft_r2c(x, X))
-    t_c2r = timed(lambda: plan.fft_c2r(X, y))
-    rt_err = (torch.linalg.vector_norm((y - x).double()) / torch.linalg.vector_norm(x.double())).item()
-    Cn = N * N * (N // 2 + 1) * 8  # natural half spectrum
-    fft_bytes = Rb + 5 * Cn  # three passes: x (Rb + C), y (2C), z (2C)
-    fft = {"r2c_ms": round(t_r2c, 4), "c2r_ms": round(t_c2r, 4),
-           "r2c_gbps": round(fft_bytes / t_r2c / 1e6, 1), "c2r_gbps": round(fft_bytes / t_c2r / 1e6, 1),
-           "r2c_frac": round(fft_bytes / t_r2c / 1e6 / PEAK_HBM_GBPS, 4),
-           "c2r_frac": round(fft_bytes / t_c2r / 1e6 / PEAK_HBM_GBPS, 4),
-           "alg_bytes": fft_bytes, "roundtrip_rel_l2": rt_err}
-
-    del x, X, y
-    big = None
-    if args.big_steps > 0:
+        log(f"[bench] timed: {args.reps} repetitions of {args.steps} steps")
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        runs = []
+        t0 = time.perf_counter()
+        for _ in range(args.reps):
+            torch.cuda.synchronize()
+            e0.record(stream)
+            plan.step(psi, state, args.steps)
+            e1.record(stream)
+            torch.cuda.synchronize()
+            runs.append(e0.elapsed_time(e1) / args.steps)
+        wall = time.perf_counter() - t0
+        ms_per_step, ms_lo, ms_hi = median_spread(runs)
+        steps_per_s = 1000.0 / ms_per_step
+        spread = {"reps": args.reps, "steps_per_rep": args.steps,
+                  "steps_per_s_each": [round(1000.0 / m, 2) for m in runs],
+                  "min": round(1000.0 / ms_hi, 2), "max": round(1000.0 / ms_lo, 2)}
+        log(f"[bench] median {ms_per_step:.4f} ms/step ({steps_per_s:.1f} steps/s; "
+            f"{spread['min']}..{spread['max']}), wall {wall:.3f} s")
+        F = plan.energy(psi, state).cpu().tolist()
+        if not all(math.isfinite(v) for v in F):
+            log(f"[bench] non-finite energy {F}")
+            sys.exit(1)
+        # per-pass durations, HIP events on the same stream, in a separate run of profile-steps steps
+        log(f"[bench] per-pass timing over {args.profile_steps} steps")
+        pass_ms = plan.step_timed(psi, state, args.profile_steps)
+        Rb = N**3 * 4  # real field, FP32
+        Cb = N**3 // 2 * 8  # packed spectrum (same bytes as the real field)
+        alg = [Rb + Cb, 2 * Cb, 4 * Cb, 2 * Cb, Cb + Rb]  # algorithmic HBM bytes per launch
+        passes = []
+        for name, tot, b in zip(PASS_NAMES, pass_ms, alg):
+            avg = tot / args.profile_steps
+            passes.append({"kernel": name, "avg_ms": round(avg, 5), "alg_bytes": b,
+                           "alg_gbps": round(b / avg / 1e6, 1), "frac": round(b / avg / 1e6 / PEAK_HBM_GBPS, 4)})
+        dom = max(passes, key=lambda p: p["avg_ms"])
+        step_bytes = sum(alg)
+        roofline = {"bound": "hbm", "kernel": dom["kernel"], "achieved": dom["alg_gbps"], "peak": PEAK_HBM_GBPS,
+                    "unit": "GB/s", "frac": dom["frac"], "traffic": measured_traffic(dom["kernel"]),
+                    "alg_bytes_per_launch": dom["alg_bytes"], "avg_ms": dom["avg_ms"]}
         del psi, state, plan
         torch.cuda.empty_cache()
+
+    fft = None
+    if "fft" in legs:
+        log(f"[bench] r2c / c2r 512^3 FP32, {args.fft_reps} reps each")
+        fft = bench_fft(N, "f32", args.fft_reps, 22)
+        fft["256cube_f32"] = bench_fft(256, "f32", args.fft_reps, 21)
+    fp64 = None
+    if "fp64" in legs:
+        log(f"[bench] FP64: r2c / c2r 512^3 and 256^3, steps at 512^3 and 256^3")
+        fp64 = {"fft_512": bench_fft(N, "f64", args.fft_reps, 22), "fft_256": bench_fft(256, "f64", args.fft_reps, 21),
+                "step_512": bench_big(max(args.steps // 6, 10), n=N, seed=SEED, dtype="f64", reps=5,
+                                      profile_steps=10),
+                "step_256": bench_big(max(args.steps // 2, 10), n=256, seed=2, dtype="f64", reps=5,
+                                      profile_steps=10)}
+        log(f"[bench] FP64 512^3 step {fp64['step_512']['steps_per_s']} steps/s ({fp64['step_512']['frac']:.3f}), "
+            f"r2c {fp64['fft_512']['r2c_frac']:.3f} c2r {fp64['fft_512']['c2r_frac']:.3f}")
+    cube256 = None
+    if "cube256" in legs:
+        log("[bench] 256^3 FP32 step (state, field and scratch fit the 256 MB memory-side cache)")
+        cube256 = bench_big(args.steps, n=256, seed=2, dtype="f32", reps=5, profile_steps=30)
+    big = None
+    if "big" in legs and args.big_steps > 0:
         log(f"[bench] 2048^3 FP32: {args.big_steps} steps")
         big = bench_big(args.big_steps)
         log(f"[bench] 2048^3: {big['steps_per_s']} steps/s ({big['frac']:.3f} of peak)")
     paper = None
-    if args.paper_steps > 0:
+    if "paper" in legs and args.paper_steps > 0:
         paper = {}
         for n, seed in ((750, 7), (1400, 8)):
             log(f"[bench] {n}^3 FP32 (mixed radix): {args.paper_steps} steps")
             paper[str(n)] = bench_big(args.paper_steps, n=n, seed=seed)
             log(f"[bench] {n}^3: {paper[str(n)]['steps_per_s']} steps/s ({paper[str(n)]['frac']:.3f} of peak)")
     hydro = None
-    if args.hydro_steps > 0:
+    if "hydro" in legs and args.hydro_steps > 0:
         log(f"[bench] hydrodynamic PFC 512^3 FP32: {args.hydro_steps} steps")
         hydro = bench_hydro(args.hydro_steps)
         log(f"[bench] hydro: {hydro['ms_per_step']} ms/step ({hydro['frac']:.3f} of peak)")
     amplitude = None
-    if args.amp_steps > 0:
+    if "amp" in legs and args.amp_steps > 0:
         log(f"[bench] complex-amplitude form, 6 bcc amplitudes on 256^3 FP32: {args.amp_steps} steps")
         amplitude = bench_amplitude(args.amp_steps)
         log(f"[bench] amplitude: {amplitude['ms_per_step']} ms/step ({amplitude['frac']:.3f} of peak)")
@@ -484,47 +589,35 @@ def main():
         log(f"[bench] amplitude 2D: {amplitude['2d_triangular_2048sq']['ms_per_step']} ms/step "
             f"({amplitude['2d_triangular_2048sq']['frac']:.3f} of peak)")
     batched = None
-    if args.batch_steps > 0:
+    if "batch" in legs and args.batch_steps > 0:
         log(f"[bench] batched form: 48 instances, {args.batch_steps} steps")
         batched = bench_batched(args.batch_steps)
         log(f"[bench] batched {batched['batch_steps_per_s']} batch steps/s")
     adjoint = None
-    if args.adjoint_steps > 0:
+    if "adjoint" in legs and args.adjoint_steps > 0:
         log(f"[bench] adjoint form: 512^2, {args.adjoint_steps} steps")
         adjoint = bench_adjoint(args.adjoint_steps, 50)
         log(f"[bench] adjoint {adjoint['fwd_bwd_steps_per_s']} steps/s forward+backward")
-
     cpu = None
-    if args.cpu_steps > 0:
-        import oracle
-
-        log(f"[bench] CPU oracle: {args.cpu_steps} FP64 steps of the same 512^3 workload")
-        p = oracle.Params(shape, r=R, dt=DT)
-        psi0 = pfc_inputs.pfc_initial_field(SEED, shape, R).astype("float32").astype("float64")
-        s0 = oracle.state_init(p, psi0)
-        t0 = time.perf_counter()
-        oracle.step(p, psi0, s0, args.cpu_steps)
-        dt_cpu = time.perf_counter() - t0
-        cpu = {"value": round(args.cpu_steps / dt_cpu, 4), "unit": "steps/s", "cores": oracle.num_threads(),
-               "kind": "oracle",
-               "sample": f"{args.cpu_steps} steps of the 512^3 workload by the FP64 C oracle "
-                         f"(recursive Cooley-Tukey FFT, radix 2 at this size, OpenMP), {dt_cpu:.1f} s"}
-        log(f"[bench] CPU oracle {cpu['value']} steps/s on {cpu['cores']} threads")
+    if "cpu" in legs and args.cpu_steps > 0:
+        log(f"[bench] CPU oracle: {args.cpu_steps} FP64 steps of the same 512^3 workload, then "
+            f"{args.cpu_steps_1t} on one thread")
+        cpu = bench_cpu(args.cpu_steps, args.cpu_steps_1t)
+        log(f"[bench] CPU oracle {cpu['value']} steps/s on {cpu['cores']} threads ({cpu['cpu_model']})")
 
     out = {
-        "metric": METRIC, "value": round(steps_per_s, 2), "unit": "steps/s", "n_gpus": 1, "steps": args.steps,
-        "warmup": args.warmup, "ms_per_step": round(ms_per_step, 5), "higher_is_better": True, "scaling": "weak",
-        "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "metric": METRIC, "value": round(steps_per_s, 2) if steps_per_s else None, "unit": "steps/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_per_step, 5) if ms_per_step else None,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
         "config": {"workload": "3D one-mode PFC step, 512^3 periodic grid, FP32, dx=pi/4, r=-0.30, dt=0.5, "
                                "psi0=-0.30+U(-0.1,0.1) SplitMix64 seed 23", "grid": list(shape)},
-        "roofline": roofline, "cpu_baseline": cpu, "fft": fft, "passes": passes, "big_2048": big,
-        "paper_grids": paper,
-        "hydro": hydro,
-        "amplitude": amplitude,
+        "timing": {"value_is": "median of the repetitions", **spread} if spread else None,
+        "roofline": roofline, "cpu_baseline": cpu, "fft": fft, "passes": passes, "fp64": fp64,
+        "cube256_f32": cube256, "big_2048": big, "paper_grids": paper, "hydro": hydro, "amplitude": amplitude,
         "batched": batched, "adjoint": adjoint,
-        "step_alg_gbps": round(step_bytes / ms_per_step / 1e6, 1),
-        "step_frac": round(step_bytes / ms_per_step / 1e6 / PEAK_HBM_GBPS, 4),
-        "energy_after": F[0],
+        "step_alg_gbps": round(step_bytes / ms_per_step / 1e6, 1) if ms_per_step else None,
+        "step_frac": round(step_bytes / ms_per_step / 1e6 / PEAK_HBM_GBPS, 4) if ms_per_step else None,
+        "energy_after": F[0] if F else None,
     }
     print(json.dumps(out), flush=True)
 

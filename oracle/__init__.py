@@ -46,6 +46,7 @@ def _load():
     lib.or_energy.argtypes = [pp, dp, dp, dp]
     lib.or_step_backward.argtypes = [pp, dp, dp, dp, dp, dp]
     lib.or_num_threads.argtypes = []
+    lib.or_set_num_threads.argtypes = [ctypes.c_int]
     lib.or_hydro_step.argtypes = [pp, ctypes.POINTER(_OrHydro), dp, dp, dp, dp, ctypes.c_int64]
     ap = P(_OrApfc)
     lib.or_apfc_nonlinear.argtypes = [ap, dp, dp]
@@ -53,7 +54,7 @@ def _load():
     lib.or_apfc_state_init.argtypes = [ap, dp, dp]
     lib.or_apfc_step.argtypes = [ap, dp, dp, ctypes.c_int64]
     for f in ("or_fft_c2c", "or_rfftn", "or_irfftn", "or_state_init", "or_step", "or_energy",
-              "or_step_backward", "or_num_threads", "or_hydro_step", "or_apfc_nonlinear", "or_apfc_counts",
+              "or_step_backward", "or_num_threads", "or_set_num_threads", "or_hydro_step", "or_apfc_nonlinear", "or_apfc_counts",
               "or_apfc_state_init", "or_apfc_step"):
         getattr(lib, f).restype = ctypes.c_int
     _lib = lib
@@ -210,6 +211,11 @@ def loss_and_grad(p: Params, psi0: np.ndarray, target: np.ndarray, nsteps: int):
 
 def num_threads() -> int:
     return int(_load().or_num_threads())
+
+
+def set_num_threads(n: int) -> None:
+    """OpenMP threads of later oracle calls."""
+    _check(_load().or_set_num_threads(int(n)), "set_num_threads")
 
 
 @dataclass

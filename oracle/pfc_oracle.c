@@ -862,3 +862,13 @@ int or_num_threads(void)
     }
     return t;
 }
+
+/* Sets the number of OpenMP threads of later calls (the CPU baseline is also timed on one). */
+int or_set_num_threads(int n)
+{
+    if (n < 1) return OR_ERR_ARG;
+#ifdef _OPENMP
+    omp_set_num_threads(n);
+#endif
+    return OR_OK;
+}
