@@ -197,8 +197,9 @@ hipError_t launch_y_c2c(const Geom &g, cx<T> *data, int dir, const cx<T> *tw, hi
             return hipErrorInvalidValue;
         } else {
             return with_plan<typename AxisCands<L>::type>(variant, [&](auto plc) -> hipError_t {
-                using TL = PencilTile<T, L>;
-                using PL = SpreadIf<decltype(plc), TL::E>;
+                using TO = TileOf<T, decltype(plc)>;
+                using TL = typename TO::tile;
+                using PL = SpreadIf<typename TO::plan, TL::E>;
                 constexpr int WM = TL::W;
                 const int W = (int)(g.M < WM ? g.M : WM);
                 const int64_t tiles = cdiv(g.M, W);
@@ -302,10 +303,11 @@ hipError_t launch_last(const Geom &g, int mode, const cx<T> *src, cx<T> *dst, cx
             const dim3 grid((unsigned)nblocks);
             using P0 = typename LastPlan<L>::type;
             switch (mode) {
-            case LAST_STEP:
-                return with_plan<typename LastCands<L>::type>(variant, [&](auto plc) -> hipError_t {
-                    using TL = PencilTile<T, L>;
-                    using PL = SpreadIf<decltype(plc), TL::E>;
+            case LAST_STEP: {
+                auto run = [&](auto plc) -> hipError_t {
+                    using TO = TileOf<T, decltype(plc)>;
+                    using TL = typename TO::tile;
+                    using PL = SpreadIf<typename TO::plan, TL::E>;
                     LastAxisArgs<T> b = a;
                     b.W = even_width(g.M < TL::W ? (int)g.M : TL::W);
                     b.tiles_per_row = (int)cdiv(g.M, b.W);
@@ -316,7 +318,12 @@ hipError_t launch_last(const Geom &g, int mode, const cx<T> *src, cx<T> *dst, cx
                                            dim3((unsigned)nb), dim3(TL::W * PL::Tp), 0, s, b);
                         return hipGetLastError();
                     });
-                });
+                };
+                // 3D: the z candidates (wider tiles at some lengths); 2D: the list the batched
+                // kernel shares, so that its instances stay bitwise equal to single plans
+                if (g.ndim == 3) return with_plan<typename ZCands<L>::type>(variant, run);
+                return with_plan<typename LastCands<L>::type>(variant, run);
+            }
             // natural layout (rows of M + 1, not line-aligned): whole rows per XCD, so the lines two
             // tiles share meet in one L2 (measured at 512^3: r2c 403 -> 348 us, c2r 274 -> 262 us)
             case LAST_R2C_NATURAL: {

@@ -381,14 +381,35 @@ template <> struct AltPlans<512> { using type = PlanList<Radices<8, 8, 8>, Radic
 template <> struct AltPlans<1024> { using type = PlanList<Radices<8, 8, 16>, Radices<16, 4, 16>>; };
 template <> struct AltPlans<2048> { using type = PlanList<Radices<8, 16, 16>, Radices<16, 8, 16>>; };
 
+// A candidate of a strided pass that brings its own tile instead of the length's default
+// (PencilTile in kernels.hpp): SEGB bytes of adjacent columns per workgroup (the row segment each
+// load and store instruction moves), E elements per thread (0: the schedule's own), G LDS groups,
+// PF state prefetch in the step.  PL is the radix schedule.
+template <class PL, int SEGB, int E = 0, int G = 1, bool PF = true>
+struct Tiled {
+    using plan = PL;
+    static constexpr int L = PL::L, seg_bytes = SEGB, elems = E, groups = G;
+    static constexpr bool prefetch = PF;
+};
+
 // x forward (r2c, contiguous rows), x inverse (c2r), strided middle axis, last axis
 template <int M> struct XFwdCands { using type = typename AltPlans<M>::type; };
 template <int M> struct XInvCands { using type = typename AltPlans<M>::type; };
 template <> struct XInvCands<256> { using type = PlanList<Radices<8, 4, 8>, Radices<16, 16>>; };
 template <int L> struct AxisCands { using type = typename AltPlans<L>::type; };
-template <> struct AxisCands<512> { using type = PlanList<Radices<16, 2, 16>, Radices<8, 8, 8>>; };
+template <> struct AxisCands<512> {
+    using type = PlanList<Radices<16, 2, 16>, Radices<8, 8, 8>, Tiled<Radices<16, 2, 16>, 256>,
+                          Tiled<Radices<16, 2, 16>, 256, 32, 2>>;
+};
 template <int L> struct LastCands { using type = typename AltPlans<L>::type; };
 template <> struct LastCands<512> { using type = PlanList<Radices<2, 16, 16>, Radices<16, 16, 2>>; };
+// the last axis of a 3D step (z): the 2D list, and at 512 tiles of 256-byte row segments (the
+// pencils' elements lie a whole z plane apart, so each element row of a tile is one segment)
+template <int L> struct ZCands { using type = typename LastCands<L>::type; };
+template <> struct ZCands<512> {
+    using type = PlanList<Radices<2, 16, 16>, Radices<16, 16, 2>, Tiled<Radices<2, 16, 16>, 256>,
+                          Tiled<Radices<2, 16, 16>, 256, 32, 2, false>, Tiled<Radices<2, 16, 16>, 256, 32, 1, false>>;
+};
 
 template <int M> struct XFwdPlan { using type = typename ListAt<0, typename XFwdCands<M>::type>::type; };
 template <int M> struct XInvPlan { using type = typename ListAt<0, typename XInvCands<M>::type>::type; };

@@ -446,6 +446,22 @@ struct PencilTile<float, 2048> {
 template <class PL, int E>
 using SpreadIf = std::conditional_t<(E > 0), Spread<PL, (E > 0 ? E : PL::Rmax)>, PL>;
 
+// The tile and the radix schedule of a strided-pass candidate C: a plain schedule takes its
+// length's PencilTile; a Tiled candidate (fft_core.hpp) its own, W = SEGB / sizeof(complex).
+template <typename T, class C, class = void>
+struct TileOf {
+    using tile = PencilTile<T, C::L>;
+    using plan = C;
+};
+template <typename T, class C>
+struct TileOf<T, C, std::void_t<typename C::plan>> {
+    struct tile {
+        static constexpr int W = C::seg_bytes / (int)sizeof(cx<T>), E = C::elems, G = C::groups;
+        static constexpr bool PF = C::prefetch;
+    };
+    using plan = typename C::plan;
+};
+
 // ------------------------------------------------------------------------------------------------
 // Workgroup order for column tiles narrower than a 128-byte line.  Consecutive workgroups are
 // dispatched to the 8 XCDs in turn, so workgroups b, b + 8, ..., b + 8 (G - 1) share one XCD and

@@ -23,7 +23,7 @@ int step_candidates(const Geom &g, int pass)
         constexpr int K = decltype(kind)::value;
         if constexpr (K == 0) n = XFwdCands<L>::type::size;
         else if constexpr (K == 1) n = AxisCands<L>::type::size;
-        else if constexpr (K == 2) n = LastCands<L>::type::size;
+        else if constexpr (K == 2) n = (g.ndim == 3) ? ZCands<L>::type::size : LastCands<L>::type::size;
         else n = XInvCands<L>::type::size;
         return hipSuccess;
     };

@@ -116,18 +116,19 @@ def test_rollout_512sq_2000_central_differences(pfc):
 
 
 def test_rollout_512sq_2000_fp32_vs_fp64(pfc, oracle_512sq_2000):
-    """The FP32 run's gradient against the FP64 CPU adjoint.  Over 2000 steps the FP32 trajectory
-    itself departs from FP64 by ~1e-4 (relative L2), and the backward sweep accumulates rounding over
-    as many steps again; 1e-2 bounds the observed 1.6e-3 (psi0 gradient) and 3.6e-3 (dL/dr)."""
+    """The FP32 run's gradient against the FP64 CPU adjoint, end to end: the FP32 forward trajectory
+    departs from FP64 over the 2000 steps, and the backward sweep adds its own rounding (bounded
+    separately below, observed 2.5e-4).  Observed 1.8e-3 for the psi0 gradient and 1.1e-3 for dL/dr;
+    gated at 5e-3."""
     psi0, target_ref, L_ref, g_ref, dr_ref = oracle_512sq_2000
     say(f"[rollout] {SHAPE} FP32 vs FP64 CPU adjoint")
     p32 = rounded(psi0, "f32")
     target = _gpu_target(pfc, "f32", p32)
     plan = pfc.Plan(SHAPE, dtype="f32", r=R0, dt=DT)
     L, g, dr = pfc.loss_and_grad(plan, to_dev(p32, "f32"), R0, target, NSTEPS, 50)
-    eg = parity_err(to_np(g), g_ref)
-    say(f"          L {L:.8g} vs {L_ref:.8g}; grad rel L2 {eg:.2e}; dL/dr {dr:.8g} vs {dr_ref:.8g}")
-    assert eg < 1e-2 and abs(dr - dr_ref) < 1e-2 * abs(dr_ref)
+    eg = parity_errs(to_np(g), g_ref)
+    say(f"          L {L:.8g} vs {L_ref:.8g}; grad {fmt_errs(eg)}; dL/dr {dr:.8g} vs {dr_ref:.8g}")
+    assert max(eg) < 5e-3 and abs(dr - dr_ref) < 5e-3 * abs(dr_ref)
 
 
 def test_rollout_512sq_2000_fp32_adjoint_along_its_own_trajectory(pfc):
@@ -136,12 +137,11 @@ def test_rollout_512sq_2000_fp32_adjoint_along_its_own_trajectory(pfc):
     FP32 forward run, widened to FP64; the rollout's replay reproduces that trajectory bit for bit)
     from lambda^T = 2 (psi^T - target), target the FP32 GPU run at r = -0.30.  Both sweeps then see
     the same forward states, so their difference is the rounding of the FP32 backward steps alone.
-    The FP32 forward's own drift from FP64 over the same 2000 steps is measured beside it: the
-    backward steps are the transposes of the forward Jacobians, so their rounding is amplified by
-    propagators of the same norms, and the adjoint's own error is bounded by a small multiple of that
-    drift (the gate)."""
-    import torch
 
+    Gate 1e-3: one FP32 backward step has relative error d1 (measured here at the middle of the
+    trajectory, about 3e-7: three FP32 transforms); if each step's rounding were carried to lambda^0
+    undamped, 2000 steps would accumulate at most 2000 d1, about 6e-4.  Observed 2.5e-4 (psi0
+    gradient) and 6e-5 (dL/dr).  The FP32 forward drift over the same run is reported beside it."""
     psi0 = rounded(P.pfc_initial_field(5, SHAPE, R0), "f32")
     say(f"[rollout] {SHAPE} {NSTEPS} steps: FP32 GPU adjoint vs the FP64 adjoint along the FP32 trajectory")
     target = _gpu_target(pfc, "f32", psi0)
@@ -165,14 +165,22 @@ def test_rollout_512sq_2000_fp32_adjoint_along_its_own_trajectory(pfc):
     po = oracle.Params(SHAPE, r=R0, dt=DT)
     lam = 2.0 * (traj[NSTEPS].astype(np.float64) - to_np(target))
     acc = 0.0
+    mid = NSTEPS // 2
+    d1 = None
     for n in range(NSTEPS - 1, -1, -1):
-        lam, c = oracle.step_backward(po, traj[n].astype(np.float64), traj[n + 1].astype(np.float64), lam)
+        lam_new, c = oracle.step_backward(po, traj[n].astype(np.float64), traj[n + 1].astype(np.float64), lam)
+        if n == mid:  # one FP32 GPU backward step on the same (FP32-rounded) inputs
+            lam32 = to_dev(lam.astype(np.float32), "f32")
+            got, _ = plan.step_backward(to_dev(traj[n], "f32"), to_dev(traj[n + 1], "f32"), lam32)
+            ref1, _ = oracle.step_backward(po, traj[n].astype(np.float64), traj[n + 1].astype(np.float64),
+                                           lam.astype(np.float32).astype(np.float64))
+            d1 = parity_errs(to_np(got), ref1)
+        lam = lam_new
         acc += c
     eg = parity_errs(to_np(g), lam)
     er = abs(dr - acc) / abs(acc)
     say(f"          forward FP32 drift at step {NSTEPS}: {fmt_errs(drift)}")
+    say(f"          one FP32 backward step (n = {mid}): {fmt_errs(d1)}; {NSTEPS} x that: {NSTEPS * max(d1):.2e}")
     say(f"          dL/dpsi0 {fmt_errs(eg)}; dL/dr {dr:.8g} vs {acc:.8g} (rel {er:.2e})")
-    gate = max(1e-4, 3.0 * max(drift))
-    say(f"          gate {gate:.2e}")
-    assert max(eg) < gate and er < gate
-
+    assert max(d1) < 5e-6
+    assert max(eg) < 1e-3 and er < 1e-3
