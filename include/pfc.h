@@ -15,9 +15,11 @@
  * - "Natural" half spectra are [..][n_x/2+1] complex, unnormalised, forward sign e^{-ikx}.
  * - The spectral "state" carried between steps is in the library's own layout ("native"): the
  *   half spectrum with the self-conjugate planes kx = 0 and kx = n_x/2 folded into one complex
- *   plane, n0*n1*n2/2 complex values in all (the same byte count as the real field).  Because any
- *   complex array in that layout corresponds to exactly one pair of Hermitian planes, the state
- *   always satisfies the symmetry of a real field.  Use pfc_state_export to read it.
+ *   plane, n_x/2 complex values per row.  3D grids pad rows longer than one 128-byte line to whole
+ *   lines, and large power-of-two grids interleave blocks of 4 or 8 z planes line by line; the size
+ *   is pfc_plan_state_bytes (the real field's bytes, plus any row padding).  Because any complex
+ *   array in that layout corresponds to exactly one pair of Hermitian planes, the state always
+ *   satisfies the symmetry of a real field.  Use pfc_state_export to read it.
  * - Device buffers and streams are owned by the caller; the plan owns only host metadata.  All
  *   device pointers must be 16-byte aligned and must not overlap unless an entry point says so.
  * - Every call is asynchronous on `stream` (a hipStream_t passed as void*, NULL = null stream) and
@@ -52,6 +54,15 @@ typedef enum { PFC_ONE_MODE = 0, PFC_TWO_MODE = 1 } pfc_model;
 
 /* flags */
 #define PFC_FLAG_LINEAR_ONLY 1u /* drop the cubic term (FFT(psi^3) := 0): the linear PDE */
+/* Layout hints of the native state (3D plans).  They change where values are stored, not the
+ * arithmetic: every layout gives the same bits.  By default the library pairs z planes (blocks of
+ * 2) on power-of-two grids with z >= 256 and planes of at least 1 MiB, where that measured faster.
+ * PFC_FLAG_ZBLOCK(s) forces blocks of 2^s z planes, s in 0..3 (s > 0 needs a power-of-two z length
+ * >= 256 and rows of whole 128-byte lines, else pfc_plan_create returns PFC_ERR_INVALID_ARG).
+ * PFC_FLAG_XROWS_BLOCK makes the x passes visit the planes of a block in turn instead of the rows
+ * in their natural order. */
+#define PFC_FLAG_ZBLOCK(s) (0x10u | (((unsigned)(s) & 3u) << 5))
+#define PFC_FLAG_XROWS_BLOCK 0x80u
 
 typedef struct pfc_plan pfc_plan;
 
@@ -81,7 +92,7 @@ typedef struct {
  * operator of Eq. (3)-(4); the denominator of the update of Listing 1. */
 pfc_status pfc_plan_create(pfc_plan **out, const pfc_plan_desc *d);
 
-/* Bytes of device workspace the plan needs: one native spectrum (n0*n1*n2/2 complex), the
+/* Bytes of device workspace the plan needs: one native spectrum (pfc_plan_state_bytes), the
  * twiddle table and the reduction partials.  The caller allocates it (>= 256-byte aligned).
  * Source: the transforms and spectral update of Listing 1 (their scratch). */
 size_t pfc_plan_workspace_bytes(const pfc_plan *p);

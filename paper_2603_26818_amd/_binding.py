@@ -8,6 +8,12 @@ import os
 PFC_F32, PFC_F64 = 0, 1
 PFC_ONE_MODE, PFC_TWO_MODE = 0, 1
 PFC_FLAG_LINEAR_ONLY = 1
+PFC_FLAG_XROWS_BLOCK = 0x80
+
+
+def PFC_FLAG_ZBLOCK(s: int) -> int:
+    """Layout hint: blocks of 2^s z planes in the native state (3D; see include/pfc.h)."""
+    return 0x10 | ((int(s) & 3) << 5)
 
 _STATUS = {
     0: "PFC_OK",
@@ -215,7 +221,11 @@ class Plan:
         self.real_dtype = torch.float64 if self.f64 else torch.float32
         self.complex_dtype = torch.complex128 if self.f64 else torch.complex64
         self.half_shape = shape[:-1] + (shape[-1] // 2 + 1,)
-        self.state_shape = shape[:-1] + (shape[-1] // 2,)
+        # the native state is opaque: rows of a pitch >= n_x / 2 (3D grids pad rows to whole 128-byte
+        # lines and may interleave blocks of z planes); its size comes from the library
+        cbytes = 16 if self.f64 else 8
+        rows = math.prod(shape[:-1])
+        self.state_shape = shape[:-1] + (int(lib.pfc_plan_state_bytes(h)) // (cbytes * rows),)
         nbytes = lib.pfc_plan_workspace_bytes(h)
         self.workspace = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
         if self.workspace.data_ptr() % 256:

@@ -95,7 +95,8 @@ __device__ __forceinline__ cx<T> *batch_lds();
 template <typename T, class PL>
 __device__ __noinline__ void batch_x_fwd(const BatchInst<T> *in, int item, const cx<T> *tw, int lt_shift)
 {
-    x_r2c_block<T, PL, BRows<PL>::value, true>(in->psi, in->scratch, in->n0, tw, lt_shift, item, batch_lds<T>());
+    x_r2c_block<T, PL, BRows<PL>::value, true>(in->psi, in->scratch, in->n0, tw, lt_shift, item, batch_lds<T>(),
+                                              row_pack(in->M));
 }
 
 // Lengths whose single-plan step uses a spread tile (PencilTile) use the same tile here, so that
@@ -107,7 +108,7 @@ __device__ __noinline__ void batch_y_step(const BatchInst<T> *in, int item, cons
     using PL = SpreadIf<PL0, TL::E>;
     constexpr int WM = kBatchThreads / PL::Tp;
     static_assert(TL::G == 1 || WM == TL::W, "spread tile must fill the batched workgroup");
-    LastAxisArgs<T> la;
+    LastAxisArgs<T> la{};
     la.src = in->scratch;
     la.dst = in->scratch;
     la.dst2 = nullptr;
@@ -119,6 +120,7 @@ __device__ __noinline__ void batch_y_step(const BatchInst<T> *in, int item, cons
     la.tw = tw;
     la.lt_shift = lt_shift;
     la.mp = in->mp;
+    la.pk = row_pack(in->M);
     last_axis_block<T, PL, WM, LA_STEP, TL::PF, ORD_TILE, false, TL::G>(la, item, batch_lds<T>());
 }
 
@@ -136,7 +138,7 @@ __device__ __noinline__ void batch_x_inv(const BatchInst<T> *in, int item, const
 {
     AdjEpi<T> ea{};
     x_c2r_block<T, PL, BRows<PL>::value, EPI_PLAIN>(in->scratch, in->psi, in->n0, tw, lt_shift, in->sc, ea, item,
-                                                     batch_lds<T>());
+                                                     batch_lds<T>(), row_pack(in->M));
 }
 
 // supported lengths: x 32..1024 (M = 16..512), y 32..1024

@@ -47,6 +47,28 @@ static hipError_t with_nt(bool nt, F &&f)
     return nt ? f(std::true_type{}) : f(std::false_type{});
 }
 
+// Every element step of the schedule PL (b Tp + r L / R for its first and last radix) is a
+// multiple of the layout's plane block 2^zs, as the last-axis addressing requires (AxisMap, Pack).
+template <class PL>
+static bool z_steps_ok(int zs)
+{
+    const int Z = 1 << zs;
+    return PL::Tp % Z == 0 && (PL::L / PL::first) % Z == 0 && (PL::L / PL::last) % Z == 0;
+}
+
+// Addressing of the middle-axis (3D y) pass: batch = z plane, columns kx, elements y.
+static inline AxisMap y_map(const Geom &g)
+{
+    const Pack pk = pack_of(g);
+    return AxisMap{pk.nrows * pk.Mp << pk.zs, pk.Mp << pk.zs, 0, 0, pk.zs, 0, pk.zs, pk.cs};
+}
+// Addressing of a last-axis c2c pass: one batch, columns row M + kx, elements along the last axis.
+static inline AxisMap last_map(const Geom &g)
+{
+    const Pack pk = pack_of(g);
+    return AxisMap{0, pk.e_stride(), pk.Mp << pk.zs, g.M, 0, pk.zs, pk.zs, pk.cs};
+}
+
 // Largest even width <= w (w >= 2).
 static inline int even_width(int w) { return w > 1 ? (w & ~1) : w; }
 
@@ -73,6 +95,7 @@ template <typename T>
 hipError_t launch_x_r2c(const Geom &g, const T *in, cx<T> *out, bool cube, const cx<T> *tw, hipStream_t s,
                         int variant)
 {
+    if (!layout_ok(g)) return hipErrorInvalidValue;
     return by_length(g.M, [&](auto Mc) -> hipError_t {
         constexpr int M = decltype(Mc)::value;
         if constexpr (M > 1024) {
@@ -86,7 +109,7 @@ hipError_t launch_x_r2c(const Geom &g, const T *in, cx<T> *out, bool cube, const
                 // non-temporal hints measured faster at M = 256 and slower at M = 1024
                 return with_nt(g.nt && M < 1024, [&](auto ntc) -> hipError_t {
                     hipLaunchKernelGGL((x_r2c_kernel<T, PL, ROWS, CUBE, false, decltype(ntc)::value>), grid, block, 0,
-                                       s, in, out, g.xrows, tw + g.tw_x, g.lt_shift);
+                                       s, in, out, g.xrows, tw + g.tw_x, g.lt_shift, pack_of(g));
                     return hipGetLastError();
                 });
             };
@@ -99,6 +122,7 @@ hipError_t launch_x_r2c(const Geom &g, const T *in, cx<T> *out, bool cube, const
 template <typename T>
 hipError_t launch_x_c2r(const Geom &g, const cx<T> *in, T *out, const cx<T> *tw, hipStream_t s, int variant)
 {
+    if (!layout_ok(g)) return hipErrorInvalidValue;
     return by_length(g.M, [&](auto Mc) -> hipError_t {
         constexpr int M = decltype(Mc)::value;
         if constexpr (M > 1024) {
@@ -112,7 +136,7 @@ hipError_t launch_x_c2r(const Geom &g, const cx<T> *in, T *out, const cx<T> *tw,
                 AdjEpi<T> ea{};
                 return with_nt(g.nt, [&](auto ntc) -> hipError_t {
                     hipLaunchKernelGGL((x_c2r_kernel<T, PL, ROWS, EPI_PLAIN, false, false, decltype(ntc)::value>), grid,
-                                       block, 0, s, in, out, g.xrows, tw + g.tw_x, g.lt_shift, sc, ea);
+                                       block, 0, s, in, out, g.xrows, tw + g.tw_x, g.lt_shift, sc, ea, pack_of(g));
                     return hipGetLastError();
                 });
             });
@@ -124,6 +148,7 @@ template <typename T>
 hipError_t launch_x_c2r_adjoint(const Geom &g, const cx<T> *mu, const cx<T> *nu, const T *psi_n, const T *psi_np1,
                                 T *out, T c3, double *partial, int64_t *nblocks, const cx<T> *tw, hipStream_t s)
 {
+    if (!layout_ok(g)) return hipErrorInvalidValue;
     return by_length(g.M, [&](auto Mc) -> hipError_t {
         constexpr int M = decltype(Mc)::value;
         if constexpr (M > 1024) {
@@ -137,7 +162,7 @@ hipError_t launch_x_c2r_adjoint(const Geom &g, const cx<T> *mu, const cx<T> *nu,
             const T sc = (T)(1.0 / ((double)g.M * (double)g.n0 * (double)g.nrows));
             AdjEpi<T> ea{nu, psi_n, psi_np1, c3, partial};
             hipLaunchKernelGGL((x_c2r_kernel<T, PL, ROWS, EPI_ADJOINT>), grid, block, 0, s, mu, out, g.xrows,
-                               tw + g.tw_x, g.lt_shift, sc, ea);
+                               tw + g.tw_x, g.lt_shift, sc, ea, pack_of(g));
             return hipGetLastError();
         }
     });
@@ -147,6 +172,7 @@ template <typename T>
 hipError_t launch_x_c2r_mac(const Geom &g, const cx<T> *in, T *out, const T *w, bool add, const cx<T> *tw,
                             hipStream_t s)
 {
+    if (!layout_ok(g)) return hipErrorInvalidValue;
     return by_length(g.M, [&](auto Mc) -> hipError_t {
         constexpr int M = decltype(Mc)::value;
         if constexpr (M > 1024) {
@@ -160,7 +186,7 @@ hipError_t launch_x_c2r_mac(const Geom &g, const cx<T> *in, T *out, const T *w, 
             ea.w = w;
             ea.add = add ? 1 : 0;
             hipLaunchKernelGGL((x_c2r_kernel<T, PL, ROWS, EPI_MAC>), grid, block, 0, s, in, out, g.xrows, tw + g.tw_x,
-                               g.lt_shift, sc, ea);
+                               g.lt_shift, sc, ea, pack_of(g));
             return hipGetLastError();
         }
     });
@@ -170,18 +196,22 @@ template <typename T>
 hipError_t launch_spec_update(const Geom &g, int op, cx<T> *out, const cx<T> *x0, const cx<T> *x1,
                               const HydroArgs &h, hipStream_t s)
 {
+    if (!layout_ok(g)) return hipErrorInvalidValue;
     static_assert(HYDRO_PSI == HY_PSI && HYDRO_MU == HY_MU && HYDRO_VEL == HY_VEL, "mode codes");
     const int64_t n = g.n0 * g.nrows * g.M;
     const dim3 grid((unsigned)(cdiv(n, 256) < 16384 ? cdiv(n, 256) : 16384)), block(256);
     switch (op) {
     case HY_PSI:
-        hipLaunchKernelGGL((spec_update_kernel<T, HY_PSI>), grid, block, 0, s, out, x0, x1, g.n0, g.nrows, g.M, h);
+        hipLaunchKernelGGL((spec_update_kernel<T, HY_PSI>), grid, block, 0, s, out, x0, x1, g.n0, g.nrows, g.M, h,
+                           pack_of(g));
         break;
     case HY_MU:
-        hipLaunchKernelGGL((spec_update_kernel<T, HY_MU>), grid, block, 0, s, out, x0, x1, g.n0, g.nrows, g.M, h);
+        hipLaunchKernelGGL((spec_update_kernel<T, HY_MU>), grid, block, 0, s, out, x0, x1, g.n0, g.nrows, g.M, h,
+                           pack_of(g));
         break;
     case HY_VEL:
-        hipLaunchKernelGGL((spec_update_kernel<T, HY_VEL>), grid, block, 0, s, out, x0, x1, g.n0, g.nrows, g.M, h);
+        hipLaunchKernelGGL((spec_update_kernel<T, HY_VEL>), grid, block, 0, s, out, x0, x1, g.n0, g.nrows, g.M, h,
+                           pack_of(g));
         break;
     default: return hipErrorInvalidValue;
     }
@@ -191,6 +221,7 @@ hipError_t launch_spec_update(const Geom &g, int op, cx<T> *out, const cx<T> *x0
 template <typename T>
 hipError_t launch_y_c2c(const Geom &g, cx<T> *data, int dir, const cx<T> *tw, hipStream_t s, int variant)
 {
+    if (!layout_ok(g)) return hipErrorInvalidValue;
     return by_length(g.n1, [&](auto Lc) -> hipError_t {
         constexpr int L = decltype(Lc)::value;
         if constexpr (L < 4) {
@@ -210,12 +241,13 @@ hipError_t launch_y_c2c(const Geom &g, cx<T> *data, int dir, const cx<T> *tw, hi
                 // non-temporal only with whole-line tiles (measured slower on 64-byte tiles)
                 return with_nt(g.nt && xg <= 1, [&](auto ntc) -> hipError_t {
                     constexpr bool NT = decltype(ntc)::value;
+                    const AxisMap am = y_map(g);
                     if (dir < 0)
                         hipLaunchKernelGGL((axis_c2c_kernel<T, PL, WM, -1, 1, NT, TL::G>), grid, block, 0, s, data,
-                                           data, W, g.M, g.M, g.n1 * g.M, tiles, tw + g.tw_y, g.lt_shift, xg);
+                                           data, W, g.M, am, tiles, tw + g.tw_y, g.lt_shift, xg);
                     else
                         hipLaunchKernelGGL((axis_c2c_kernel<T, PL, WM, +1, 1, NT, TL::G>), grid, block, 0, s, data,
-                                           data, W, g.M, g.M, g.n1 * g.M, tiles, tw + g.tw_y, g.lt_shift, xg);
+                                           data, W, g.M, am, tiles, tw + g.tw_y, g.lt_shift, xg);
                     return hipGetLastError();
                 });
             });
@@ -232,23 +264,26 @@ hipError_t launch_last_fwd(const Geom &g, const cx<T> *src, cx<T> *dst, const cx
 template <typename T>
 hipError_t launch_last_c2c(const Geom &g, const cx<T> *src, cx<T> *dst, int dir, const cx<T> *tw, hipStream_t s)
 {
+    if (!layout_ok(g)) return hipErrorInvalidValue;
     return by_length(g.n0, [&](auto Lc) -> hipError_t {
         constexpr int L = decltype(Lc)::value;
         if constexpr (L < 4) {
             return hipErrorInvalidValue;
         } else {
             using PL = typename AxisPlan<L>::type;
+            if (!z_steps_ok<PL>(g.zs)) return hipErrorInvalidValue;
             constexpr int WM = WMax<T, L>::value;
             const int64_t ncols = g.nrows * g.M;
             const int W = (int)(ncols < WM ? ncols : WM);
             const int64_t tiles = cdiv(ncols, W);
             const dim3 grid((unsigned)tiles), block(WM * PL::Tp);
+            const AxisMap am = last_map(g);
             if (dir < 0)
-                hipLaunchKernelGGL((axis_c2c_kernel<T, PL, WM, -1>), grid, block, 0, s, src, dst, W, ncols, ncols,
-                                   (int64_t)0, tiles, tw + g.tw_last, g.lt_shift, 1);
+                hipLaunchKernelGGL((axis_c2c_kernel<T, PL, WM, -1>), grid, block, 0, s, src, dst, W, ncols, am, tiles,
+                                   tw + g.tw_last, g.lt_shift, 1);
             else
-                hipLaunchKernelGGL((axis_c2c_kernel<T, PL, WM, +1>), grid, block, 0, s, src, dst, W, ncols, ncols,
-                                   (int64_t)0, tiles, tw + g.tw_last, g.lt_shift, 1);
+                hipLaunchKernelGGL((axis_c2c_kernel<T, PL, WM, +1>), grid, block, 0, s, src, dst, W, ncols, am, tiles,
+                                   tw + g.tw_last, g.lt_shift, 1);
             return hipGetLastError();
         }
     });
@@ -258,19 +293,21 @@ template <typename T>
 hipError_t launch_last_c2c_deriv(const Geom &g, const cx<T> *src, cx<T> *dst, int role, double fk, const cx<T> *tw,
                                  hipStream_t s)
 {
+    if (!layout_ok(g)) return hipErrorInvalidValue;
     return by_length(g.n0, [&](auto Lc) -> hipError_t {
         constexpr int L = decltype(Lc)::value;
         if constexpr (L < 4) {
             return hipErrorInvalidValue;
         } else {
             using PL = typename AxisPlan<L>::type;
+            if (!z_steps_ok<PL>(g.zs)) return hipErrorInvalidValue;
             constexpr int WM = WMax<T, L>::value;
             const int64_t ncols = g.nrows * g.M;
             const int W = (int)(ncols < WM ? ncols : WM);
             const int64_t tiles = cdiv(ncols, W);
             const DerivArgs da{role, fk, g.nrows, g.M};
             hipLaunchKernelGGL((axis_c2c_deriv_kernel<T, PL, WM>), dim3((unsigned)tiles), dim3(WM * PL::Tp), 0, s, src,
-                               dst, W, ncols, ncols, tw + g.tw_last, g.lt_shift, da);
+                               dst, W, ncols, last_map(g), tw + g.tw_last, g.lt_shift, da);
             return hipGetLastError();
         }
     });
@@ -280,13 +317,14 @@ template <typename T>
 hipError_t launch_last(const Geom &g, int mode, const cx<T> *src, cx<T> *dst, cx<T> *dst2, cx<T> *state,
                        const ModelParams<T> &mp, const cx<T> *tw, hipStream_t s, int variant)
 {
+    if (!layout_ok(g)) return hipErrorInvalidValue;
     return by_length(g.n0, [&](auto Lc) -> hipError_t {
         constexpr int L = decltype(Lc)::value;
         if constexpr (L < 4) {
             return hipErrorInvalidValue;
         } else {
             constexpr int WM = WMax<T, L>::value;
-            LastAxisArgs<T> a;
+            LastAxisArgs<T> a{};
             a.src = src;
             a.dst = dst;
             a.dst2 = dst2;
@@ -299,15 +337,19 @@ hipError_t launch_last(const Geom &g, int mode, const cx<T> *src, cx<T> *dst, cx
             a.tw = tw + g.tw_last;
             a.lt_shift = g.lt_shift;
             a.mp = mp;
+            a.pk = pack_of(g);
+            a.pk2 = Pack{g.nrows, g.M, 0, 0};  // ADJOINT's nu: plain rows of M
             const int64_t nblocks = (g.nrows == 1) ? a.tiles_per_row : g.nrows * a.tiles_per_row;
             const dim3 grid((unsigned)nblocks);
             using P0 = typename LastPlan<L>::type;
+            if (mode != LAST_STEP && !z_steps_ok<P0>(g.zs)) return hipErrorInvalidValue;
             switch (mode) {
             case LAST_STEP: {
                 auto run = [&](auto plc) -> hipError_t {
                     using TO = TileOf<T, decltype(plc)>;
                     using TL = typename TO::tile;
                     using PL = SpreadIf<typename TO::plan, TL::E>;
+                    if (!z_steps_ok<PL>(g.zs)) return hipErrorInvalidValue;
                     LastAxisArgs<T> b = a;
                     b.W = even_width(g.M < TL::W ? (int)g.M : TL::W);
                     b.tiles_per_row = (int)cdiv(g.M, b.W);
@@ -334,11 +376,12 @@ hipError_t launch_last(const Geom &g, int mode, const cx<T> *src, cx<T> *dst, cx
                 if constexpr (TL::W == C && L <= 1024) {  // at 2048 the two rounds' registers would spill
                     if (g.nrows > 1 && (g.nrows * (g.M + 1)) % C == 0 && g.M >= C) {
                         using PL = SpreadIf<P0, TL::E>;
+                        if (!z_steps_ok<PL>(g.zs)) return hipErrorInvalidValue;
                         const int64_t nchunks = g.nrows * (g.M + 1) / C;
                         return with_nt(g.nt, [&](auto ntc) -> hipError_t {
                             hipLaunchKernelGGL((r2c_natural_chunk_kernel<T, PL, C, TL::G, decltype(ntc)::value>),
                                                dim3((unsigned)nchunks), dim3(C * PL::Tp), 0, s, src, dst, g.nrows,
-                                               (int)g.M, tw + g.tw_last, g.lt_shift);
+                                               (int)g.M, tw + g.tw_last, g.lt_shift, pack_of(g));
                             return hipGetLastError();
                         });
                     }
@@ -378,8 +421,9 @@ template <typename T>
 hipError_t launch_energy(const Geom &g, const T *psi, const cx<T> *state, const double fk[3], double r, double q1sq,
                          double R1, int model, double dV, double *partial, double *out, hipStream_t s)
 {
+    if (!layout_ok(g)) return hipErrorInvalidValue;
     hipLaunchKernelGGL((energy_spec_kernel<T>), dim3(kReduceBlocks), dim3(256), 0, s, state, g.n0, g.nrows, g.M,
-                       fk[0], fk[1], fk[2], r, q1sq, R1, model, partial);
+                       fk[0], fk[1], fk[2], r, q1sq, R1, model, partial, pack_of(g));
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     const int64_t ntot = g.n0 * g.nrows * g.nx;
@@ -394,9 +438,11 @@ hipError_t launch_energy(const Geom &g, const T *psi, const cx<T> *state, const 
 template <typename T>
 hipError_t launch_export(const Geom &g, const cx<T> *state, cx<T> *out, hipStream_t s)
 {
+    if (!layout_ok(g)) return hipErrorInvalidValue;
     const int64_t n = g.n0 * g.nrows * (g.M + 1);
     const int64_t blocks = cdiv(n, 256) < 65536 ? cdiv(n, 256) : 65536;
-    hipLaunchKernelGGL((export_kernel<T>), dim3((unsigned)blocks), dim3(256), 0, s, state, out, g.n0, g.nrows, g.M);
+    hipLaunchKernelGGL((export_kernel<T>), dim3((unsigned)blocks), dim3(256), 0, s, state, out, g.n0, g.nrows, g.M,
+                       pack_of(g));
     return hipGetLastError();
 }
 

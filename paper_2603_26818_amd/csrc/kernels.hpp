@@ -129,21 +129,27 @@ struct XPitch {
 template <bool PAD>
 __device__ __forceinline__ int xidx(int e) { return PAD ? xpad(e) : e; }
 
+// Identity layout of a packed spectrum with rows of M values (2D plans, the batched form).
+__host__ __device__ inline Pack row_pack(int64_t M) { return Pack{1, M, 0, 0}; }
+
 // One block of ROWS rows (block index `bid`); `sh` holds ROWS * XPitch<M, PAD> LDS slots.
 // Uses threads 0 .. ROWS*Tp-1, which must be all threads of the workgroup.  FROM_LDS: the rows'
 // reals are not read from `in` but from `sh` (row p at sh[p M], as packed pairs), where the caller
-// has left them.
+// has left them.  Output row rr (= e nrows + row) goes to the layout `pk`.
 template <typename T, class PL, int ROWS, bool CUBE, bool PAD = false, bool NT = false, bool FROM_LDS = false>
 __device__ __forceinline__ void x_r2c_block(const T *__restrict__ in, cx<T> *__restrict__ out, int64_t nrows,
-                                            const cx<T> *__restrict__ tw, int lt_shift, int64_t bid, cx<T> *sh)
+                                            const cx<T> *__restrict__ tw, int lt_shift, int64_t bid, cx<T> *sh,
+                                            const Pack &pk)
 {
     static_assert(!FROM_LDS || !PAD, "staged rows are unpadded");
     constexpr int M = PL::L, Tp = PL::Tp, R0 = PL::first, Rl = PL::last, Rmax = PL::Rmax;
     constexpr int LD = XPitch<M, PAD>::value;  // row pitch in LDS
     const int tid = threadIdx.x, p = tid / Tp, t = tid - p * Tp;
-    const int64_t row = bid * ROWS + p;
-    const bool valid = row < nrows;
-    const cx<T> *src = FROM_LDS ? sh + p * M : reinterpret_cast<const cx<T> *>(in) + (valid ? row : 0) * M;
+    const int64_t rho = bid * ROWS + p;  // position in the pass's row order (Pack::x_row)
+    const bool valid = rho < nrows;
+    int64_t obase;
+    const int64_t row = pk.x_row(valid ? rho : 0, &obase);
+    const cx<T> *src = FROM_LDS ? sh + p * M : reinterpret_cast<const cx<T> *>(in) + row * M;
     cx<T> v[Rmax];
 #pragma unroll
     for (int b = 0; b < PL::nb(R0); ++b)
@@ -167,7 +173,7 @@ __device__ __forceinline__ void x_r2c_block(const T *__restrict__ in, cx<T> *__r
 #pragma unroll
         for (int r = 0; r < Rl; ++r) lds(t + b * Tp + r * (M / Rl)) = v[b * Rl + r];
     __syncthreads();
-    cx<T> *dst = out + (valid ? row : 0) * M;
+    cx<T> *dst = out + obase;
     const T h = T(0.5);
 #pragma unroll
     for (int b = 0; b < PL::nb(Rl); ++b)
@@ -185,17 +191,17 @@ __device__ __forceinline__ void x_r2c_block(const T *__restrict__ in, cx<T> *__r
                 const cx<T> O = {(Zk.y + Zp.y) * h, (Zp.x - Zk.x) * h};
                 X = E + cmul(split_twiddle<T, M>(tw, lt_shift, k), O);
             }
-            if (valid) st_grid<NT>(&dst[k], X);
+            if (valid) st_grid<NT>(&dst[pk.col(k)], X);
         }
 }
 
 template <typename T, class PL, int ROWS, bool CUBE, bool PAD = false, bool NT = false>
 __global__ __launch_bounds__(ROWS *PL::Tp) void x_r2c_kernel(const T *__restrict__ in, cx<T> *__restrict__ out,
                                                               int64_t nrows, const cx<T> *__restrict__ tw,
-                                                              int lt_shift)
+                                                              int lt_shift, Pack pk)
 {
     __shared__ cx<T> sh[ROWS * XPitch<PL::L, PAD>::value];
-    x_r2c_block<T, PL, ROWS, CUBE, PAD, NT>(in, out, nrows, tw, lt_shift, blockIdx.x, sh);
+    x_r2c_block<T, PL, ROWS, CUBE, PAD, NT>(in, out, nrows, tw, lt_shift, blockIdx.x, sh, pk);
 }
 
 // ------------------------------------------------------------------------------------------------
@@ -204,9 +210,11 @@ __global__ __launch_bounds__(ROWS *PL::Tp) void x_r2c_kernel(const T *__restrict
 // Z(0) = ((X0 + XM) + i (X0 - XM)) / 2 from the packed slot; z = IFFT_M(Z) (unnormalised);
 // x[2m] = Re z[m] * scale, x[2m+1] = Im z[m] * scale.
 //
-// EPI_PLAIN stores x.  EPI_ADJOINT transforms two spectra (mu from `in`, nu from `in2`) and stores
+// EPI_PLAIN stores x.  EPI_ADJOINT transforms two spectra (mu from `in`, in the layout `pk`; nu
+// from `in2`, always in the plain layout of rows of M, so that nu's row r covers the same bytes as
+// the real row r) and stores
 //   out = mu - c3 * psi_n^2 * nu,   and writes the block's FP64 sum of nu * psi_np1 to partial[].
-// `in2` and `out` may be the same buffer: each block reads its rows completely before writing.
+// `in2` and `out` may be the same buffer: each block reads its rows completely before writing them.
 // EPI_MAC (hydrodynamic step) stores out = w * x (+ out when `add`), w a real field.
 enum { EPI_PLAIN = 0, EPI_ADJOINT = 1, EPI_MAC = 2 };
 
@@ -221,12 +229,12 @@ struct AdjEpi {
     int add;     // EPI_MAC
 };
 
-// Pre-combination of one row for the c2r: own elements X(k) from `src`; the mirror X(M-k) either
-// through LDS (PG = false) or straight from `src` (PG = true: a second, reversed but coalesced load of
-// the same cache lines, without the LDS round trip and its barrier).
+// Pre-combination of one row for the c2r: own elements X(k) from `src` (column k at src[pk.col(k)]);
+// the mirror X(M-k) either through LDS (PG = false) or straight from `src` (PG = true: a second,
+// reversed but coalesced load of the same cache lines, without the LDS round trip and its barrier).
 template <typename T, class PL, int ROWS, bool PAD, bool PG = false, bool NT = false>
 __device__ __forceinline__ void x_c2r_row(cx<T> *v, const cx<T> *src, bool valid, int t, cx<T> *rowlds,
-                                          const cx<T> *__restrict__ tw, int lt_shift)
+                                          const cx<T> *__restrict__ tw, int lt_shift, const Pack &pk)
 {
     constexpr int M = PL::L, Tp = PL::Tp, R0 = PL::first, Rmax = PL::Rmax;
     cx<T> mir[PG ? Rmax : 1];
@@ -237,8 +245,8 @@ __device__ __forceinline__ void x_c2r_row(cx<T> *v, const cx<T> *src, bool valid
 #pragma unroll
             for (int r = 0; r < R0; ++r) {
                 const int k = t + b * Tp + r * (M / R0);
-                v[b * R0 + r] = valid ? ld_grid<NT>(&src[k]) : cx<T>{T(0), T(0)};
-                mir[b * R0 + r] = valid ? ld_grid<NT>(&src[neg_mod<M>(k)]) : cx<T>{T(0), T(0)};
+                v[b * R0 + r] = valid ? ld_grid<NT>(&src[pk.col(k)]) : cx<T>{T(0), T(0)};
+                mir[b * R0 + r] = valid ? ld_grid<NT>(&src[pk.col(neg_mod<M>(k))]) : cx<T>{T(0), T(0)};
             }
     } else {
         __syncthreads();
@@ -248,7 +256,7 @@ __device__ __forceinline__ void x_c2r_row(cx<T> *v, const cx<T> *src, bool valid
 #pragma unroll
             for (int r = 0; r < R0; ++r) {
                 const int k = t + b * Tp + r * (M / R0);
-                v[b * R0 + r] = valid ? ld_grid<NT>(&src[k]) : cx<T>{T(0), T(0)};
+                v[b * R0 + r] = valid ? ld_grid<NT>(&src[pk.col(k)]) : cx<T>{T(0), T(0)};
                 rowlds[xidx<PAD>(k)] = v[b * R0 + r];
             }
         __syncthreads();
@@ -282,18 +290,20 @@ __device__ __forceinline__ void x_c2r_row(cx<T> *v, const cx<T> *src, bool valid
 template <typename T, class PL, int ROWS, int EPI, bool PAD = false, bool PG = false, bool NT = false,
           bool TO_LDS = false>
 __device__ __forceinline__ void x_c2r_block(const cx<T> *in, T *out, int64_t nrows, const cx<T> *__restrict__ tw,
-                                            int lt_shift, T sc, const AdjEpi<T> &ea, int64_t bid, cx<T> *sh)
+                                            int lt_shift, T sc, const AdjEpi<T> &ea, int64_t bid, cx<T> *sh,
+                                            const Pack &pk)
 {
     static_assert(!TO_LDS || (EPI == EPI_PLAIN && !PAD), "staging only for the plain epilogue, unpadded");
     constexpr int M = PL::L, Tp = PL::Tp, Rl = PL::last, Rmax = PL::Rmax;
     constexpr int LD = XPitch<M, PAD>::value;
     const int tid = threadIdx.x, p = tid / Tp, t = tid - p * Tp;
-    const int64_t row = bid * ROWS + p;
-    const bool valid = row < nrows;
-    const int64_t r0 = valid ? row : 0;
+    const int64_t rho = bid * ROWS + p;  // position in the pass's row order (Pack::x_row)
+    const bool valid = rho < nrows;
+    int64_t ibase;
+    const int64_t r0 = pk.x_row(valid ? rho : 0, &ibase);  // real-field row
     auto lds = [&](int e) -> cx<T> & { return sh[p * LD + xidx<PAD>(e)]; };
     cx<T> v[Rmax];
-    x_c2r_row<T, PL, ROWS, PAD, PG, NT>(v, in + r0 * M, valid, t, &sh[p * LD], tw, lt_shift);
+    x_c2r_row<T, PL, ROWS, PAD, PG, NT>(v, in + ibase, valid, t, &sh[p * LD], tw, lt_shift, pk);
     fft_stages<T, PL, +1>(v, t, lds, tw, lt_shift);
     cx<T> *dst = reinterpret_cast<cx<T> *>(out) + r0 * M;
     if constexpr (EPI == EPI_MAC) {
@@ -329,7 +339,7 @@ __device__ __forceinline__ void x_c2r_block(const cx<T> *in, T *out, int64_t nro
         }
     } else {
         cx<T> w[Rmax];
-        x_c2r_row<T, PL, ROWS, PAD, PG>(w, ea.in2 + r0 * M, valid, t, &sh[p * LD], tw, lt_shift);
+        x_c2r_row<T, PL, ROWS, PAD, PG>(w, ea.in2 + r0 * M, valid, t, &sh[p * LD], tw, lt_shift, row_pack(M));
         fft_stages<T, PL, +1>(w, t, lds, tw, lt_shift);
         const cx<T> *pn = reinterpret_cast<const cx<T> *>(ea.psi_n) + r0 * M;
         const cx<T> *pn1 = reinterpret_cast<const cx<T> *>(ea.psi_np1) + r0 * M;
@@ -356,10 +366,10 @@ __device__ __forceinline__ void x_c2r_block(const cx<T> *in, T *out, int64_t nro
 template <typename T, class PL, int ROWS, int EPI, bool PAD = false, bool PG = false, bool NT = false>
 __global__ __launch_bounds__(ROWS *PL::Tp) void x_c2r_kernel(const cx<T> *in, T *out, int64_t nrows,
                                                               const cx<T> *__restrict__ tw, int lt_shift, T sc,
-                                                              AdjEpi<T> ea)
+                                                              AdjEpi<T> ea, Pack pk)
 {
     __shared__ cx<T> sh[ROWS * XPitch<PL::L, PAD>::value];
-    x_c2r_block<T, PL, ROWS, EPI, PAD, PG, NT>(in, out, nrows, tw, lt_shift, sc, ea, blockIdx.x, sh);
+    x_c2r_block<T, PL, ROWS, EPI, PAD, PG, NT>(in, out, nrows, tw, lt_shift, sc, ea, blockIdx.x, sh, pk);
 }
 
 // ------------------------------------------------------------------------------------------------
@@ -395,12 +405,13 @@ __device__ __forceinline__ void x_c2r_r2c_block(const cx<T> *in, cx<T> *out, int
 #pragma unroll
     for (int s = 0; s < F::R / F::RI; ++s)
         x_c2r_block<T, PLI, F::RI, EPI_PLAIN, false, false, NT, true>(in, nullptr, nrows, tw, lt_shift, sc, ea,
-                                                                      bid * (F::R / F::RI) + s, sh + s * F::RI * M);
+                                                                      bid * (F::R / F::RI) + s, sh + s * F::RI * M,
+                                                                      row_pack(M));
     __syncthreads();  // all staged rows written
 #pragma unroll
     for (int s = 0; s < F::R / F::RF; ++s)
         x_r2c_block<T, PLF, F::RF, true, false, NT, true>(nullptr, out, nrows, tw, lt_shift, bid * (F::R / F::RF) + s,
-                                                          sh + s * F::RF * M);
+                                                          sh + s * F::RF * M, row_pack(M));
 }
 
 
@@ -490,29 +501,30 @@ struct DerivArgs {
 
 // ------------------------------------------------------------------------------------------------
 // Strided complex FFT along one axis, out of place or in place (src == dst).
-// Pencil (batch, col) has element e at  batch*bstride + e*estride + col,  col < ncols contiguous.
-// A workgroup handles W adjacent columns (W <= WMAX); its threads are laid out column-fastest so
-// each load/store instruction moves W * sizeof(cx) contiguous bytes per element row.  `bid` is the
-// logical tile index (see xcd_tile_order).
+// Pencil (batch, col), col < ncols, has element e = t + k at am.base(batch, col) + am.elem(t) +
+// k am.estride (AxisMap in types.hpp; every step k the schedule takes is a multiple of 2^am.ezs, which
+// the launcher checks).  A workgroup handles W adjacent columns (W <= WMAX); its threads are laid out
+// column-fastest so each load/store instruction moves W * sizeof(cx) contiguous bytes per element
+// row (within one 128-byte column chunk).  `bid` is the logical tile index (see xcd_tile_order).
 template <typename T, class PL, int WMAX, int DIR, bool NT = false, int G = 1, bool DERIV = false>
-__device__ __forceinline__ void axis_c2c_block(const cx<T> *src, cx<T> *dst, int W, int64_t ncols, int64_t estride,
-                                               int64_t bstride, int64_t tiles_per_batch,
-                                               const cx<T> *__restrict__ tw, int lt_shift, int64_t bid, cx<T> *sh,
-                                               const DerivArgs &da = DerivArgs{})
+__device__ __forceinline__ void axis_c2c_block(const cx<T> *src, cx<T> *dst, int W, int64_t ncols, const AxisMap &am,
+                                               int64_t tiles_per_batch, const cx<T> *__restrict__ tw, int lt_shift,
+                                               int64_t bid, cx<T> *sh, const DerivArgs &da = DerivArgs{})
 {
     constexpr int L = PL::L, Tp = PL::Tp, R0 = PL::first, Rl = PL::last, Rmax = PL::Rmax;
     const int tid = threadIdx.x, p = tid % WMAX, t = tid / WMAX;
     const int64_t batch = bid / tiles_per_batch, tile = bid - batch * tiles_per_batch;
     const int64_t col = tile * W + p;
     const bool valid = p < W && col < ncols;
-    const int64_t base = batch * bstride + (valid ? col : 0);
+    const int64_t base = am.base(batch, valid ? col : 0) + am.elem(t);
+    const int64_t estride = am.estride;
     cx<T> v[Rmax];
 #pragma unroll
     for (int b = 0; b < PL::nb(R0); ++b)
         if (PL::jok(t + b * Tp, R0))
 #pragma unroll
         for (int r = 0; r < R0; ++r)
-            v[b * R0 + r] = valid ? ld_grid<NT>(&src[base + (int64_t)(t + b * Tp + r * (L / R0)) * estride])
+            v[b * R0 + r] = valid ? ld_grid<NT>(&src[base + (int64_t)(b * Tp + r * (L / R0)) * estride])
                                   : cx<T>{T(0), T(0)};
     if constexpr (DERIV) {
         const int64_t crow = valid ? col / da.M : 0, ckx = valid ? col - crow * da.M : 0;
@@ -542,7 +554,7 @@ __device__ __forceinline__ void axis_c2c_block(const cx<T> *src, cx<T> *dst, int
             if (PL::jok(t + b * Tp, Rl))
 #pragma unroll
             for (int r = 0; r < Rl; ++r)
-                st_grid<NT>(&dst[base + (int64_t)(t + b * Tp + r * (L / Rl)) * estride], v[b * Rl + r]);
+                st_grid<NT>(&dst[base + (int64_t)(b * Tp + r * (L / Rl)) * estride], v[b * Rl + r]);
     }
 }
 
@@ -559,30 +571,39 @@ __device__ __forceinline__ int64_t plane_xcd_order(int64_t b, int64_t tiles_per_
     return ((k / tiles_per_batch) * 8 + (b & 7)) * tiles_per_batch + k % tiles_per_batch;
 }
 
+// With batch blocks (am.bzs > 0: 2^bzs batches share the rows of one block), the plane order runs
+// over whole blocks, and inside a block over tiles first, then the batches of the block, so that
+// consecutive workgroups of an XCD read neighbouring 128-byte chunks.
 template <typename T, class PL, int WMAX, int DIR, int OCC = 1, bool NT = false, int G = 1>
 __global__ __launch_bounds__(WMAX *PL::Tp, OCC) void axis_c2c_kernel(const cx<T> *src, cx<T> *dst, int W,
-                                                                 int64_t ncols, int64_t estride, int64_t bstride,
-                                                                 int64_t tiles_per_batch,
+                                                                 int64_t ncols, AxisMap am, int64_t tiles_per_batch,
                                                                  const cx<T> *__restrict__ tw, int lt_shift, int xg)
 {
     static_assert(WMAX % G == 0, "groups of whole pencils");
     __shared__ cx<T> sh[PL::L * WMAX / G];
-    const int64_t bid = xg == 0 ? plane_xcd_order(blockIdx.x, tiles_per_batch, gridDim.x)
-                                : xcd_tile_order(blockIdx.x, gridDim.x, xg);
-    axis_c2c_block<T, PL, WMAX, DIR, NT, G>(src, dst, W, ncols, estride, bstride, tiles_per_batch, tw, lt_shift, bid,
-                                         sh);
+    int64_t bid;
+    if (xg == 0) {
+        const int64_t tb = tiles_per_batch << am.bzs;
+        const int64_t u = plane_xcd_order(blockIdx.x, tb, gridDim.x);
+        const int64_t sb = u / tb, w = u - sb * tb;
+        const int64_t batch = (sb << am.bzs) + (w & ((int64_t(1) << am.bzs) - 1));
+        bid = batch * tiles_per_batch + (w >> am.bzs);
+    } else {
+        bid = xcd_tile_order(blockIdx.x, gridDim.x, xg);
+    }
+    axis_c2c_block<T, PL, WMAX, DIR, NT, G>(src, dst, W, ncols, am, tiles_per_batch, tw, lt_shift, bid, sh);
 }
 
 // Inverse strided FFT of the spectral derivative i k_role of `src` (DerivArgs), out of place.
 template <typename T, class PL, int WMAX>
 __global__ __launch_bounds__(WMAX *PL::Tp) void axis_c2c_deriv_kernel(const cx<T> *src, cx<T> *dst, int W,
-                                                                   int64_t ncols, int64_t estride,
+                                                                   int64_t ncols, AxisMap am,
                                                                    const cx<T> *__restrict__ tw, int lt_shift,
                                                                    DerivArgs da)
 {
     __shared__ cx<T> sh[PL::L * WMAX];
-    axis_c2c_block<T, PL, WMAX, +1, false, 1, true>(src, dst, W, ncols, estride, 0, (ncols + W - 1) / W, tw,
-                                                    lt_shift, blockIdx.x, sh, da);
+    axis_c2c_block<T, PL, WMAX, +1, false, 1, true>(src, dst, W, ncols, am, (ncols + W - 1) / W, tw, lt_shift,
+                                                    blockIdx.x, sh, da);
 }
 
 // ------------------------------------------------------------------------------------------------
@@ -609,6 +630,8 @@ struct LastAxisArgs {
     const cx<T> *tw;
     int lt_shift;
     ModelParams<T> mp;
+    Pack pk;   // layout of the packed arrays src, dst, state (natural arrays: rows of M + 1)
+    Pack pk2;  // layout of dst2 (ADJOINT's nu: plain rows of M, see x_c2r_block's EPI_ADJOINT)
 };
 
 struct SlotInfo {
@@ -690,11 +713,25 @@ __device__ __forceinline__ void last_axis_block(const LastAxisArgs<T> &a, int64_
     constexpr int Rl = PL::last;
     const int tid = threadIdx.x, p = tid % WMAX, t = tid / WMAX, grp = p / GW;
     const int W = a.W;
-    const int64_t nrows = a.nrows, M = a.M, estride = nrows * M;
+    const int64_t nrows = a.nrows, M = a.M;
     const SlotInfo si = la_slot<ORD, IL>(nrows, a.tiles_per_row, W, p < W ? p : 0, bid);
     const bool valid = p < W && si.kx < M;  // the last column tile of a row may be partial
-    const int64_t coloff = si.row * M + si.kx;
     auto lds = [&](int e) -> cx<T> & { return sh[e * GW + p % GW]; };
+    // Element e = t + k of this lane's pencil in a packed array lies at pk.at(t, row, kx) + k estride
+    // (k a multiple of the layout's block size Z, which the launcher checks).  The address is split
+    // into a wave-uniform part (the tile origin, the wave's first t, and k * estride: scalar
+    // registers) and a per-lane 32-bit byte offset, so no per-element 64-bit vector arithmetic is
+    // needed.
+    const Pack &pk = a.pk;
+    const int64_t estride = pk.e_stride();
+    const SlotInfo s0 = la_slot<ORD, IL>(nrows, a.tiles_per_row, W, 0, bid);
+    const int t0 = __builtin_amdgcn_readfirstlane(t);
+    const int64_t uoff = pk.at(t0, s0.row, s0.kx);
+    const uint32_t loff = (uint32_t)((pk.at(t, si.row, si.kx) - uoff) * (int64_t)sizeof(cx<T>));
+    auto gp = [&](const cx<T> *base, int k) -> cx<T> * {
+        return reinterpret_cast<cx<T> *>(
+            reinterpret_cast<char *>(const_cast<cx<T> *>(base) + uoff + (int64_t)k * estride) + loff);
+    };
     const ModelParams<T> &mp = a.mp;
     const T ky = mp.fk[1] * (T)signed_index(si.row, nrows);
     const T kx = mp.fk[2] * (T)si.kx;
@@ -737,25 +774,10 @@ __device__ __forceinline__ void last_axis_block(const LastAxisArgs<T> &a, int64_
             for (int b = 0; b < PL::nb(Rf); ++b)
                 if (PL::jok(t + b * Tp, Rf))
 #pragma unroll
-                for (int r = 0; r < Rf; ++r)
-                    st_grid<NT>(&a.dst[(int64_t)(t + b * Tp + r * (L / Rf)) * estride + coloff], v[b * Rf + r]);
+                for (int r = 0; r < Rf; ++r) st_grid<NT>(gp(a.dst, b * Tp + r * (L / Rf)), v[b * Rf + r]);
         }
         return;
     } else {
-        // Element e = t + k of this lane's pencil lies at (t + k) * estride + coloff.  The address
-        // is split into a wave-uniform part (the tile origin, the wave's first t, and k * estride:
-        // scalar registers) and a per-lane 32-bit byte offset (t below the wave's first t by less
-        // than 64 / WMAX, row and column inside the tile), so no per-element 64-bit vector
-        // arithmetic is needed.
-        const SlotInfo s0 = la_slot<ORD, IL>(nrows, a.tiles_per_row, W, 0, bid);
-        const int t0 = __builtin_amdgcn_readfirstlane(t);
-        const int64_t uoff = (int64_t)t0 * estride + s0.row * M + s0.kx;
-        const uint32_t loff =
-            (uint32_t)(((int64_t)(t - t0) * estride + (si.row - s0.row) * M + (si.kx - s0.kx)) * (int64_t)sizeof(cx<T>));
-        auto gp = [&](const cx<T> *base, int k) -> cx<T> * {
-            return reinterpret_cast<cx<T> *>(
-                reinterpret_cast<char *>(const_cast<cx<T> *>(base) + uoff + (int64_t)k * estride) + loff);
-        };
         // STEP with PF: the state values this thread updates are loaded before the forward FFT so
         // that their latency overlaps the FFT
         cx<T> spre[(MODE == LA_STEP && PF) ? Rmax : 1];
@@ -957,14 +979,18 @@ __device__ __forceinline__ void last_axis_block(const LastAxisArgs<T> &a, int64_
                     w[b * Rl + r] = nu;
                 }
             constexpr int Rf = PR::last;
+            const int64_t uoff2 = a.pk2.at(t0, s0.row, s0.kx), estride2 = a.pk2.e_stride();
+            const uint32_t loff2 = (uint32_t)((a.pk2.at(t, si.row, si.kx) - uoff2) * (int64_t)sizeof(cx<T>));
+            auto gp2 = [&](cx<T> *base, int k) -> cx<T> * {
+                return reinterpret_cast<cx<T> *>(reinterpret_cast<char *>(base + uoff2 + (int64_t)k * estride2) + loff2);
+            };
             fft_stages<T, PR, +1>(v, t, lds, a.tw, a.lt_shift);
             if (valid) {
 #pragma unroll
                 for (int b = 0; b < PL::nb(Rf); ++b)
                     if (PL::jok(t + b * Tp, Rf))
 #pragma unroll
-                    for (int r = 0; r < Rf; ++r)
-                        a.dst[(int64_t)(t + b * Tp + r * (L / Rf)) * estride + coloff] = v[b * Rf + r];
+                    for (int r = 0; r < Rf; ++r) *gp(a.dst, b * Tp + r * (L / Rf)) = v[b * Rf + r];
             }
             fft_stages<T, PR, +1>(w, t, lds, a.tw, a.lt_shift);
             if (valid) {
@@ -972,8 +998,7 @@ __device__ __forceinline__ void last_axis_block(const LastAxisArgs<T> &a, int64_
                 for (int b = 0; b < PL::nb(Rf); ++b)
                     if (PL::jok(t + b * Tp, Rf))
 #pragma unroll
-                    for (int r = 0; r < Rf; ++r)
-                        a.dst2[(int64_t)(t + b * Tp + r * (L / Rf)) * estride + coloff] = w[b * Rf + r];
+                    for (int r = 0; r < Rf; ++r) *gp2(a.dst2, b * Tp + r * (L / Rf)) = w[b * Rf + r];
             }
         }
     }
@@ -1027,25 +1052,28 @@ __device__ __forceinline__ void hy_mode(const HydroArgs &h, double q, double o[2
 template <typename T, int OP>
 __global__ __launch_bounds__(256) void spec_update_kernel(cx<T> *out, const cx<T> *__restrict__ x0,
                                                           const cx<T> *__restrict__ x1, int64_t L, int64_t nrows,
-                                                          int64_t M, HydroArgs h)
+                                                          int64_t M, HydroArgs h, Pack pk)
 {
     const int64_t n = L * nrows * M;
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
         const int64_t kx = i % M, rest = i / M, row = rest % nrows, e = rest / nrows;
+        const int64_t j = pk.at(e, row, kx);  // i: logical index, j: its place in memory
         const double kz = h.fk[0] * signed_index(e, L), ky = h.fk[1] * signed_index(row, nrows);
-        const cx<T> zx1 = x1 ? x1[i] : cx<T>{T(0), T(0)};
+        const cx<T> zx1 = x1 ? x1[j] : cx<T>{T(0), T(0)};
         if (kx != 0) {
             const double kk = h.fk[2] * (double)kx, q = kz * kz + ky * ky + kk * kk;
-            double o[2] = {(double)out[i].x, (double)out[i].y}, a[2] = {(double)x0[i].x, (double)x0[i].y},
+            double o[2] = {(double)out[j].x, (double)out[j].y}, a[2] = {(double)x0[j].x, (double)x0[j].y},
                    b[2] = {(double)zx1.x, (double)zx1.y};
             hy_mode<OP>(h, q, o, a, b);
-            out[i] = {(T)o[0], (T)o[1]};
+            out[j] = {(T)o[0], (T)o[1]};
             continue;
         }
-        const int64_t im = (((L - e) % L) * nrows + (nrows - row) % nrows) * M;
-        if (im < i) continue;  // the pair is updated by the thread of its lower index
-        const cx<T> mx1 = x1 ? x1[im] : cx<T>{T(0), T(0)};
-        const cx<T> Z[3] = {out[i], x0[i], zx1}, Zm[3] = {out[im], x0[im], mx1};
+        const int64_t em = (L - e) % L, rm = (nrows - row) % nrows;
+        const int64_t im = (em * nrows + rm) * M;
+        if (im < i) continue;  // the pair is updated by the thread of its lower (logical) index
+        const int64_t jm = pk.at(em, rm, 0);
+        const cx<T> mx1 = x1 ? x1[jm] : cx<T>{T(0), T(0)};
+        const cx<T> Z[3] = {out[j], x0[j], zx1}, Zm[3] = {out[jm], x0[jm], mx1};
         double p0[3][2], pn[3][2];  // X0 and XN of each operand at k
         for (int j = 0; j < 3; ++j) {
             p0[j][0] = 0.5 * ((double)Z[j].x + (double)Zm[j].x);
@@ -1057,8 +1085,8 @@ __global__ __launch_bounds__(256) void spec_update_kernel(cx<T> *out, const cx<T
         hy_mode<OP>(h, q0, p0[0], p0[1], p0[2]);
         hy_mode<OP>(h, qn, pn[0], pn[1], pn[2]);
         // Y = Y0 + i YN at k; at -k the planes are conjugated: conj Y0 + i conj YN
-        out[i] = {(T)(p0[0][0] - pn[0][1]), (T)(p0[0][1] + pn[0][0])};
-        if (im != i) out[im] = {(T)(p0[0][0] + pn[0][1]), (T)(pn[0][0] - p0[0][1])};
+        out[j] = {(T)(p0[0][0] - pn[0][1]), (T)(p0[0][1] + pn[0][0])};
+        if (im != i) out[jm] = {(T)(p0[0][0] + pn[0][1]), (T)(pn[0][0] - p0[0][1])};
     }
 }
 
@@ -1076,7 +1104,8 @@ __global__ __launch_bounds__(256) void spec_update_kernel(cx<T> *out, const cx<T
 template <typename T, class PL, int C, int G, bool NT = false>
 __global__ __launch_bounds__(C *PL::Tp) void r2c_natural_chunk_kernel(const cx<T> *__restrict__ src,
                                                                       cx<T> *__restrict__ dst, int64_t nrows, int M,
-                                                                      const cx<T> *__restrict__ tw, int lt_shift)
+                                                                      const cx<T> *__restrict__ tw, int lt_shift,
+                                                                      Pack pk)
 {
     constexpr int L = PL::L, Tp = PL::Tp, Rmax = PL::Rmax, R0 = PL::first, Rl = PL::last, GW = C / G;
     __shared__ cx<T> sh[L * GW];
@@ -1088,16 +1117,16 @@ __global__ __launch_bounds__(C *PL::Tp) void r2c_natural_chunk_kernel(const cx<T
     const int64_t row = f / pitch;
     const int kx = (int)(f - row * pitch);
     const bool fold = (kx == 0 || kx == M);
-    const int64_t estride = nrows * M;
+    const int64_t estride = pk.e_stride();  // element steps k below are multiples of the layout's block
     cx<T> v[Rmax];
     // round 1: own pencil (folded slots: packed column 0 of this row)
     {
-        const cx<T> *col = src + row * M + (fold ? 0 : kx);
+        const cx<T> *col = src + pk.at(t, row, fold ? 0 : kx);
 #pragma unroll
         for (int b = 0; b < PL::nb(R0); ++b)
             if (PL::jok(t + b * Tp, R0))
 #pragma unroll
-            for (int r = 0; r < R0; ++r) v[b * R0 + r] = col[(int64_t)(t + b * Tp + r * (L / R0)) * estride];
+            for (int r = 0; r < R0; ++r) v[b * R0 + r] = col[(int64_t)(b * Tp + r * (L / R0)) * estride];
     }
     fft_stages<T, PL, -1, TW_STAGE, G>(v, t, lds, tw, lt_shift, grp);
     if (!fold) {
@@ -1114,13 +1143,13 @@ __global__ __launch_bounds__(C *PL::Tp) void r2c_natural_chunk_kernel(const cx<T
     for (int i = 0; i < Rmax; ++i) z[i] = v[i];
     {
         const int64_t mrow = (nrows - row) % nrows;
-        const cx<T> *col = src + mrow * M;
+        const cx<T> *col = src + pk.at(t, mrow, 0);
 #pragma unroll
         for (int b = 0; b < PL::nb(R0); ++b)
             if (PL::jok(t + b * Tp, R0))
 #pragma unroll
             for (int r = 0; r < R0; ++r)
-                v[b * R0 + r] = fold ? col[(int64_t)(t + b * Tp + r * (L / R0)) * estride] : cx<T>{T(0), T(0)};
+                v[b * R0 + r] = fold ? col[(int64_t)(b * Tp + r * (L / R0)) * estride] : cx<T>{T(0), T(0)};
     }
     fft_stages<T, PL, -1, TW_STAGE, G>(v, t, lds, tw, lt_shift, grp);
     const T h = T(0.5);
@@ -1186,7 +1215,7 @@ __global__ void accumulate_kernel(const double *partial, int np, double coef, do
 template <typename T>
 __global__ __launch_bounds__(256) void energy_spec_kernel(const cx<T> *__restrict__ state, int64_t L, int64_t nrows,
                                                           int64_t M, double fk0, double fk1, double fk2, double r,
-                                                          double q1sq, double R1, int model, double *partial)
+                                                          double q1sq, double R1, int model, double *partial, Pack pk)
 {
     const int64_t n = L * nrows * M;
     auto corr = [&](double q) {
@@ -1199,13 +1228,13 @@ __global__ __launch_bounds__(256) void energy_spec_kernel(const cx<T> *__restric
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
         const int64_t kx = i % M, rest = i / M, row = rest % nrows, e = rest / nrows;
         const double kz = fk0 * signed_index(e, L), ky = fk1 * signed_index(row, nrows);
-        const cx<T> s = state[i];
+        const cx<T> s = state[pk.at(e, row, kx)];
         if (kx != 0) {
             const double k = fk2 * (double)kx, q = kz * kz + ky * ky + k * k;
             acc += 2.0 * (r + corr(q)) * ((double)s.x * s.x + (double)s.y * s.y);
         } else {
             const int64_t ep = (L - e) % L, rp = (nrows - row) % nrows;
-            const cx<T> sp = state[(ep * nrows + rp) * M];
+            const cx<T> sp = state[pk.at(ep, rp, 0)];
             const double ax = 0.5 * ((double)s.x + sp.x), ay = 0.5 * ((double)s.y - sp.y);
             const double bx = 0.5 * ((double)s.y + sp.y), by = 0.5 * ((double)sp.x - s.x);
             const double q0 = kz * kz + ky * ky, kn = fk2 * (double)M, qn = q0 + kn * kn;
@@ -1247,16 +1276,16 @@ __global__ void energy_final_kernel(const double *ps, const double *pq, int np, 
 // Native state -> natural half spectrum [L][nrows][M+1].
 template <typename T>
 __global__ __launch_bounds__(256) void export_kernel(const cx<T> *__restrict__ state, cx<T> *__restrict__ out,
-                                                     int64_t L, int64_t nrows, int64_t M)
+                                                     int64_t L, int64_t nrows, int64_t M, Pack pk)
 {
     const int64_t n = L * nrows * (M + 1);
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
         const int64_t kx = i % (M + 1), rest = i / (M + 1), row = rest % nrows, e = rest / nrows;
         if (kx > 0 && kx < M) {
-            out[i] = state[rest * M + kx];
+            out[i] = state[pk.at(e, row, kx)];
         } else {
             const int64_t ep = (L - e) % L, rp = (nrows - row) % nrows;
-            const cx<T> s = state[rest * M], sp = state[(ep * nrows + rp) * M];
+            const cx<T> s = state[pk.at(e, row, 0)], sp = state[pk.at(ep, rp, 0)];
             const T h = T(0.5);
             out[i] = (kx == 0) ? cx<T>{(s.x + sp.x) * h, (s.y - sp.y) * h} : cx<T>{(s.y + sp.y) * h, (sp.x - s.x) * h};
         }

@@ -21,7 +21,26 @@ struct Geom {
     // twiddle table of each pass, as an entry offset from the plan's twiddle buffer: 0 (the
     // power-of-two tables) or the own table of a length that is not a power of two
     int64_t tw_x, tw_y, tw_last;
+    // layout of the packed spectra (Pack in types.hpp): row pitch (0: M), plane-block and column-chunk
+    // shifts; zero is the plain layout
+    int64_t Mp = 0;
+    int zs = 0, cs = 0;
+    int xnat = 0;  // x passes in natural row order
 };
+
+// The Pack of a geometry.
+inline Pack pack_of(const Geom &g) { return Pack{g.nrows, g.Mp > 0 ? g.Mp : g.M, g.zs, g.cs, g.xnat}; }
+
+// A layout the kernels can address: shifts in range, pitch >= M, and with plane blocks a pitch of
+// whole column chunks and a last-axis length of whole blocks.  Every launcher of a packed-layout
+// kernel checks it, so a bad geometry is an error, not an out-of-bounds access.
+inline bool layout_ok(const Geom &g)
+{
+    const int64_t Mp = g.Mp > 0 ? g.Mp : g.M;
+    if (g.zs < 0 || g.zs > 3 || g.cs < 0 || g.cs > 4 || Mp < g.M) return false;
+    if (g.zs == 0) return true;
+    return g.ndim == 3 && Mp % (int64_t(1) << g.cs) == 0 && g.n0 % (int64_t(1) << g.zs) == 0;
+}
 
 // Lengths other than powers of two that have compiled schedules (factors 2, 3, 5, 7); a grid axis
 // of length n needs n here (y and last axis) or n / 2 here (x).

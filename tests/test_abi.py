@@ -110,7 +110,10 @@ def test_plan_create_and_sizes(shape, dtype):
     npts = math.prod(shape)
     cs = 16 if dtype == 1 else 8
     assert lib.pfc_plan_real_bytes(h) == npts * cs // 2
-    assert lib.pfc_plan_state_bytes(h) == npts // 2 * cs  # packed: same bytes as the real field
+    # packed: the real field's bytes, with 3D rows longer than one 128-byte line padded to whole lines
+    M, CB = shape[-1] // 2, 128 // cs
+    Mp = M if (len(shape) == 2 or M <= CB or M % CB == 0) else -(-M // CB) * CB
+    assert lib.pfc_plan_state_bytes(h) == npts // shape[-1] * Mp * cs
     assert lib.pfc_plan_half_bytes(h) == npts // shape[-1] * (shape[-1] // 2 + 1) * cs
     ws = lib.pfc_plan_workspace_bytes(h)
     assert ws >= lib.pfc_plan_state_bytes(h) and ws < lib.pfc_plan_state_bytes(h) + (64 << 20)
@@ -134,7 +137,7 @@ def test_plan_rejects_bad_parameters():
     assert _create(b, lib, _desc(b, dt=float("nan")))[0] == 1
     assert _create(b, lib, _desc(b, dx=0.0))[0] == 1
     assert _create(b, lib, _desc(b, model=7))[0] == 1
-    assert _create(b, lib, _desc(b, flags=0x80))[0] == 1
+    assert _create(b, lib, _desc(b, flags=0x100))[0] == 1
     # r = -1.5: r + L(q) < 0 near q = 1, and dt = 5 makes 1 + dt q (r + L) negative there
     assert _create(b, lib, _desc(b, r=-1.5, dt=5.0))[0] == 1
     assert _create(b, lib, _desc(b, r=-1.5, dt=0.1))[0] == 0
@@ -278,3 +281,17 @@ def test_apfc_calls_without_workspace_fail_cleanly():
     assert lib.pfc_apfc_step(h, buf, buf, 1, None) == 4  # PFC_ERR_WORKSPACE
     assert lib.pfc_apfc_fft(h, buf, buf, -1, None) == 4
     lib.pfc_apfc_destroy(h)
+
+
+def test_layout_hint_flags_are_validated():
+    """PFC_FLAG_ZBLOCK(s > 0) needs a power-of-two z length >= 256 with rows of whole lines; unknown
+    flag bits are rejected; the state of a paired-plane layout keeps the real field's bytes."""
+    b, lib = _lib()
+    ok, h = _create(b, lib, _desc(b, (256, 64, 2048), 1, flags=b.PFC_FLAG_ZBLOCK(3) | b.PFC_FLAG_XROWS_BLOCK))
+    assert ok == 0, lib.pfc_last_error()
+    assert lib.pfc_plan_state_bytes(h) == 256 * 64 * 1024 * 16
+    for shape in ((128, 64, 2048), (750, 750, 750), (16, 32, 64)):
+        st, _ = _create(b, lib, _desc(b, shape, 0, flags=b.PFC_FLAG_ZBLOCK(1)))
+        assert st == 1, shape  # PFC_ERR_INVALID_ARG
+    st, _ = _create(b, lib, _desc(b, (64, 64), 0, flags=0x100))
+    assert st == 1
