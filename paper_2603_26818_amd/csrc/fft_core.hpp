@@ -406,6 +406,12 @@ template <> struct LastCands<512> { using type = PlanList<Radices<2, 16, 16>, Ra
 // the last axis of a 3D step (z): the 2D list, and at 512 tiles of 256-byte row segments (the
 // pencils' elements lie a whole z plane apart, so each element row of a tile is one segment)
 template <int L> struct ZCands { using type = typename LastCands<L>::type; };
+// 750 (z and y): the radices ragged over 50 threads per pencil (at most 20 elements each: 800
+// threads in one workgroup per CU, which its 96 KB of LDS allows) and the lcm schedule (25 threads
+// of 30 elements: 400 threads).  Measured at 750^3 FP32: z 2.20 against 2.86 ms, y 0.86 against
+// 0.94 ms.
+template <> struct ZCands<750> { using type = PlanList<Radices<10, 15, 5, 50>, Radices<10, 15, 5>>; };
+template <> struct AxisCands<750> { using type = PlanList<Radices<10, 15, 5, 50>, Radices<10, 15, 5>>; };
 template <> struct ZCands<512> {
     using type = PlanList<Radices<2, 16, 16>, Radices<16, 16, 2>, Tiled<Radices<2, 16, 16>, 256>,
                           Tiled<Radices<2, 16, 16>, 256, 32, 2, false>, Tiled<Radices<2, 16, 16>, 256, 32, 1, false>>;
