@@ -12,7 +12,8 @@ pytestmark = pytest.mark.gpu
 
 SHAPES = [(16, 32, 64), (64, 128, 256), (256, 512, 32), (512, 16, 1024), (1024, 64, 16), (2048, 8, 8),
           (4, 2048, 64), (8, 8, 2048), (16, 1024, 128), (128, 32, 128),
-          (2048, 64), (1024, 2048), (512, 512), (256, 1024), (128, 32), (32, 256), (750, 750, 12), (1400, 1400, 12)]
+          (2048, 64), (1024, 2048), (512, 512), (256, 1024), (128, 32), (32, 256), (750, 750, 12), (1400, 1400, 12),
+          (12, 10, 750), (10, 12, 1400)]
 NSTEPS = 6
 MAX_CANDIDATES = 5  # the most any pass has (the 512-point z and y passes: schedules and tiles)
 
