@@ -420,10 +420,16 @@ template <> struct LastCands<512> { using type = PlanList<Radices<2, 16, 16>, Ra
 template <int L> struct ZCands { using type = typename LastCands<L>::type; };
 // 750 (z and y): the radices ragged over 50 threads per pencil (at most 20 elements each: 800
 // threads in one workgroup per CU, which its 96 KB of LDS allows) and the lcm schedule (25 threads
-// of 30 elements: 400 threads).  Measured at 750^3 FP32: z 2.20 against 2.86 ms, y 0.86 against
-// 0.94 ms.
+// of 30 elements: 400 threads).  Measured at 750^3 FP32: z 2.20 against 2.86 ms.  Narrower z
+// tiles, so that two workgroups share a CU, measured slower: half a line (8 pencils, 48 KB) 2.23 ms,
+// two LDS groups (48 KB) 2.43 ms; so did persistent workgroups looping over the tiles at 512^3 (z
+// 539 against 506 us).
 template <> struct ZCands<750> { using type = PlanList<Radices<10, 15, 5, 50>, Radices<10, 15, 5>>; };
-template <> struct AxisCands<750> { using type = PlanList<Radices<10, 15, 5, 50>, Radices<10, 15, 5>>; };
+// y at 750: half-line tiles (8 pencils, 48 KB, two workgroups per CU; the plane order keeps the two
+// tiles of a line on one XCD) first: 0.74 against 0.85 ms per direction at 750^3 FP32
+template <> struct AxisCands<750> {
+    using type = PlanList<Tiled<Radices<10, 15, 5, 50>, 64, 0, 1, false>, Radices<10, 15, 5, 50>, Radices<10, 15, 5>>;
+};
 // 2048-point y and z pencils (2048^3): 16 8 16 first, measured at 2048^3 FP32: y 16.2 against
 // 16.5 ms per direction, z 39.4 against 40.0 ms
 template <> struct ZCands<2048> { using type = PlanList<Radices<16, 8, 16>, Radices<8, 16, 16>>; };
@@ -433,10 +439,20 @@ template <> struct ZCands<512> {
                           Tiled<Radices<2, 16, 16>, 256, 32, 2, false>, Tiled<Radices<2, 16, 16>, 256, 32, 1, false>>;
 };
 
-template <int M> struct XFwdPlan { using type = typename ListAt<0, typename XFwdCands<M>::type>::type; };
-template <int M> struct XInvPlan { using type = typename ListAt<0, typename XInvCands<M>::type>::type; };
-template <int L> struct AxisPlan { using type = typename ListAt<0, typename AxisCands<L>::type>::type; };
-template <int L> struct LastPlan { using type = typename ListAt<0, typename LastCands<L>::type>::type; };
+// The radix schedule of a candidate (a Tiled candidate's own; the default candidate's schedule is
+// what the other kernels of a length take, with the length's default tile)
+template <class C, class = void>
+struct PlanOf {
+    using type = C;
+};
+template <class C>
+struct PlanOf<C, std::void_t<typename C::plan>> {
+    using type = typename C::plan;
+};
+template <int M> struct XFwdPlan { using type = typename PlanOf<typename ListAt<0, typename XFwdCands<M>::type>::type>::type; };
+template <int M> struct XInvPlan { using type = typename PlanOf<typename ListAt<0, typename XInvCands<M>::type>::type>::type; };
+template <int L> struct AxisPlan { using type = typename PlanOf<typename ListAt<0, typename AxisCands<L>::type>::type>::type; };
+template <int L> struct LastPlan { using type = typename PlanOf<typename ListAt<0, typename LastCands<L>::type>::type>::type; };
 
 // Calls f(PL{}) with the schedule number v of List (v out of range: candidate 0).
 template <class List, int I = 0, class F>
