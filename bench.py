@@ -405,19 +405,41 @@ def write_traffic(fetch_dir, write_dir, out_path, command, n=N):
 
     f_fac = calibration(fetch)
     w_fac = calibration(write)
+    def targs(bare):
+        # top-level template arguments of a kernel name "k<a, b<c, d>, e>(...)"
+        out, depth, cur = [], 0, ""
+        for ch in bare[bare.index("<") + 1:]:
+            if ch == "<":
+                depth += 1
+            elif ch == ">":
+                if depth == 0:
+                    break
+                depth -= 1
+            if ch == "," and depth == 0:
+                out.append(cur.strip())
+                cur = ""
+            else:
+                cur += ch
+        return out + [cur.strip()]
+
     kernels = {}
     for name, vals in fetch.items():
         bare = name.replace("void ", "").replace("pfc::", "")
-        if bare.startswith("x_r2c_kernel<") and ", true" in bare.split(">", 1)[1][:12]:
+        if "<" not in bare:
+            continue
+        a4 = (targs(bare) + [""] * 4)[3]  # CUBE of x_r2c, EPI of x_c2r, MODE of last_axis
+        if bare.startswith("x_r2c_kernel<") and a4 == "true":
             short = "x_r2c_cube"
-        elif bare.startswith("x_c2r_kernel<") and bare.split(">", 1)[1].split(",")[2].strip() == "0":
+        elif bare.startswith("x_c2r_kernel<") and a4 == "0":
             short = "x_c2r"
         elif bare.startswith("axis_c2c_kernel<"):
             short = "y_fwd_or_inv"
-        elif bare.startswith("last_axis_kernel<") and bare.split(">", 1)[1].split(",")[2].strip() == "0":
+        elif bare.startswith("last_axis_kernel<") and a4 == "0":
             short = "z_fused_update"
         else:
             continue
+        if short in kernels and kernels[short]["dispatches"] >= len(vals):
+            continue  # several instantiations of one pass (state set-up, the step): keep the step's
         wv = write.get(name, [0.0])
         fb = sum(vals) / len(vals) * f_fac
         wb = sum(wv) / len(wv) * w_fac

@@ -106,8 +106,9 @@ hipError_t launch_x_r2c(const Geom &g, const T *in, cx<T> *out, bool cube, const
                 constexpr bool CUBE = decltype(cubec)::value;
                 constexpr int ROWS = XRows<PL>::value;
                 const dim3 grid((unsigned)cdiv(g.xrows, ROWS)), block(ROWS * PL::Tp);
-                // non-temporal hints measured faster at M = 256 and slower at M = 1024
-                return with_nt(g.nt && M < 1024, [&](auto ntc) -> hipError_t {
+                // non-temporal hints measured faster at M = 256 and slower at M = 1024; mixed-radix
+                // rows are not whole lines (their partial lines then reach HBM unmerged)
+                return with_nt(g.nt && M < 1024 && is_pow2c(M), [&](auto ntc) -> hipError_t {
                     hipLaunchKernelGGL((x_r2c_kernel<T, PL, ROWS, CUBE, false, decltype(ntc)::value>), grid, block, 0,
                                        s, in, out, g.xrows, tw + g.tw_x, g.lt_shift, pack_of(g));
                     return hipGetLastError();
@@ -134,7 +135,7 @@ hipError_t launch_x_c2r(const Geom &g, const cx<T> *in, T *out, const cx<T> *tw,
                 const dim3 grid((unsigned)cdiv(g.xrows, ROWS)), block(ROWS * PL::Tp);
                 const T sc = (T)(1.0 / ((double)g.M * (double)g.n0 * (double)g.nrows));
                 AdjEpi<T> ea{};
-                return with_nt(g.nt, [&](auto ntc) -> hipError_t {
+                return with_nt(g.nt && is_pow2c(M), [&](auto ntc) -> hipError_t {
                     hipLaunchKernelGGL((x_c2r_kernel<T, PL, ROWS, EPI_PLAIN, false, false, decltype(ntc)::value>), grid,
                                        block, 0, s, in, out, g.xrows, tw + g.tw_x, g.lt_shift, sc, ea, pack_of(g));
                     return hipGetLastError();
