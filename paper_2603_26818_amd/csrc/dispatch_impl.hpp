@@ -364,7 +364,7 @@ hipError_t launch_last(const Geom &g, int mode, const cx<T> *src, cx<T> *dst, cx
                 };
                 // 3D: the z candidates (wider tiles at some lengths); 2D: the list the batched
                 // kernel shares, so that its instances stay bitwise equal to single plans
-                if (g.ndim == 3) return with_plan<typename ZCands<L>::type>(variant, run);
+                if (g.ndim == 3) return with_plan<typename ZCandsOf<T, L>::type>(variant, run);
                 return with_plan<typename LastCands<L>::type>(variant, run);
             }
             // natural layout (rows of M + 1, not line-aligned): whole rows per XCD, so the lines two

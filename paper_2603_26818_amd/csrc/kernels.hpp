@@ -682,8 +682,13 @@ __device__ __forceinline__ SlotInfo la_slot(int64_t nrows, int TR, int W, int p,
         s.has_pairs = false;
         return s;
     }
-    const int64_t k = bid - n_normal, i = k >> 1;
-    const int h = (int)(k & 1), hw = W >> 1;
+    // pair tiles: k in [0, nrows) takes pair i (rows i and -i; i = 0: rows 0 and nrows / 2) and half
+    // h of column tile 0.  In whole groups of 16 the two halves of a pair are 8 apart (k and k + 8
+    // run on one XCD under round-robin dispatch), so the lines they share meet in one L2 instead of
+    // being fetched by two XCDs; a last incomplete group takes the halves in turn.
+    const int64_t k = bid - n_normal, full = nrows - nrows % 16;
+    const int64_t i = k < full ? ((k >> 4) << 3) + (k & 7) : (k >> 1);
+    const int h = (int)(k < full ? ((k >> 3) & 1) : (k & 1)), hw = W >> 1;
     const int64_t ra = (i == 0) ? 0 : i, rb = (i == 0) ? nrows / 2 : nrows - i;
     if constexpr (IL) {
         const bool first = (p & 1) == 0;
