@@ -60,24 +60,28 @@ hipError_t launch_apfc_last_step(int64_t L, int nf, ApfcStepArgs<T> a, hipStream
         } else {
             using TL = PencilTile<T, LL>;
             using PL = SpreadIf<typename AxisPlan<LL>::type, TL::E>;
-            constexpr bool PF = is_pow2c(LL) && PL::Rmax <= 16;  // state prefetch while registers allow
-            auto run = [&](auto wc, auto gc) -> hipError_t {
+            auto run = [&](auto wc, auto gc, auto plc) -> hipError_t {
                 constexpr int WM = decltype(wc)::value, G = decltype(gc)::value;
+                using PLr = decltype(plc);
+                constexpr bool PF = is_pow2c(LL) && PLr::Rmax <= 16;  // state prefetch while registers allow
                 a.W = (int)(a.ncols < WM ? a.ncols : WM);
                 a.tiles = cdiv(a.ncols, a.W);
-                const dim3 grid((unsigned)(a.tiles * nf)), block(WM * PL::Tp);
-                hipLaunchKernelGGL((apfc_last_step_kernel<T, PL, WM, PF, G>), grid, block, 0, s, a);
+                const dim3 grid((unsigned)(a.tiles * nf)), block(WM * PLr::Tp);
+                hipLaunchKernelGGL((apfc_last_step_kernel<T, PLr, WM, PF, G>), grid, block, 0, s, a);
                 return hipGetLastError();
             };
             // The grouped long tiles fill a CU each: with few pencil columns (2D grids) their count
             // leaves the last round of workgroups partly empty.  Half-width tiles in one LDS group
-            // (still one per CU) double the count, and the rounds fill up.
+            // (still one per CU) double the count, and the rounds fill up; they take the length's
+            // plain schedule (16 elements per thread, twice the threads of the spread one), whose
+            // registers leave room to prefetch the state.
             if constexpr (TL::G == 2 && TL::W == 16) {
                 const int64_t full = cdiv(a.ncols, TL::W) * nf;
                 if (full < 4 * kApfcCUs && (full % kApfcCUs) != 0)
-                    return run(std::integral_constant<int, TL::W / 2>{}, std::integral_constant<int, 1>{});
+                    return run(std::integral_constant<int, TL::W / 2>{}, std::integral_constant<int, 1>{},
+                               typename AxisPlan<LL>::type{});
             }
-            return run(std::integral_constant<int, TL::W>{}, std::integral_constant<int, TL::G>{});
+            return run(std::integral_constant<int, TL::W>{}, std::integral_constant<int, TL::G>{}, PL{});
         }
     });
 }

@@ -81,14 +81,15 @@ static int line_group(int W)
 }
 
 // Rows per workgroup of the x inverse pass: one wavefront (measured faster than 256 threads; the
-// pass's LDS round trips then need no cross-wave barrier), except for mixed-radix rows of more than
-// half a wavefront (700 points over 50 or 64 threads), which take about 256 threads as the forward
-// pass does (1400^3 FP32, 50 threads: 8.3 against 9.0 ms; for 375-point rows, two per wavefront,
-// 256 threads measured slower: 1.23 against 1.14 ms).
+// pass's LDS round trips then need no cross-wave barrier), except for mixed-radix rows that fill
+// most of a wavefront without dividing it (700 points over 50 threads), which take about 256
+// threads as the forward pass does (1400^3 FP32: 8.3 against 9.0 ms).  Over 64 threads a 700-point
+// row is one whole wavefront: 7.1 against 8.0 ms with four rows per workgroup; 375-point rows take
+// two per wavefront (256 threads measured slower: 1.23 against 1.14 ms).
 template <class PL>
 struct XInvRows {
-    static constexpr int value = (!is_pow2c(PL::L) && PL::Tp > 32) ? XRows<PL>::value
-                                                                    : ((64 / PL::Tp) < 1 ? 1 : 64 / PL::Tp);
+    static constexpr int value = (!is_pow2c(PL::L) && PL::Tp > 32 && PL::Tp < 64) ? XRows<PL>::value
+                                                                                   : ((64 / PL::Tp) < 1 ? 1 : 64 / PL::Tp);
 };
 
 template <typename T>
