@@ -311,34 +311,48 @@ def bench_cpu(nsteps_all, nsteps_one):
 
 
 def bench_adjoint(nsteps, every):
+    """Gradient through the rollout (512^2, loss on psi(T), gradients w.r.t. psi0 and r, checkpoints
+    every `every` steps): the FP32 run, timed forward + backward and forward only, and the FP64 check
+    run of the same workload (psi0 and the target rounded to FP32 first, so both start alike), timed
+    the same way, with the relative difference of dL/dr between the two precisions."""
     import torch
 
     import paper_2603_26818_amd as pfc
     import pfc_inputs
 
     shape = (512, 512)
-    plan_t = pfc.Plan(shape, dtype="f32", r=-0.30, dt=0.5)
-    psi0 = pfc_inputs.pfc_initial_field_torch(5, shape, -0.25, torch.float32, "cuda:0")
-    target = psi0.clone()
-    plan_t.step(target, plan_t.state_init(target), nsteps)
-    plan = pfc.Plan(shape, dtype="f32", r=-0.25, dt=0.5)
-    pfc.loss_and_grad(plan, psi0, -0.25, target, 100, every)  # warm-up
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    L, g, dr = pfc.loss_and_grad(plan, psi0, -0.25, target, nsteps, every)
-    torch.cuda.synchronize()
-    t = time.perf_counter() - t0
-    x = psi0.clone()
-    st = plan.state_init(x)
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    plan.step(x, st, nsteps)
-    torch.cuda.synchronize()
-    tf = time.perf_counter() - t1
+
+    def run(dtype):
+        tdt = torch.float32 if dtype == "f32" else torch.float64
+        plan_t = pfc.Plan(shape, dtype=dtype, r=-0.30, dt=0.5)
+        psi0 = pfc_inputs.pfc_initial_field_torch(5, shape, -0.25, torch.float32, "cuda:0").to(tdt)
+        target = psi0.clone()
+        plan_t.step(target, plan_t.state_init(target), nsteps)
+        plan = pfc.Plan(shape, dtype=dtype, r=-0.25, dt=0.5)
+        pfc.loss_and_grad(plan, psi0, -0.25, target, 100, every)  # warm-up
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        L, g, dr = pfc.loss_and_grad(plan, psi0, -0.25, target, nsteps, every)
+        torch.cuda.synchronize()
+        t = time.perf_counter() - t0
+        x = psi0.clone()
+        st = plan.state_init(x)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        plan.step(x, st, nsteps)
+        torch.cuda.synchronize()
+        tf = time.perf_counter() - t1
+        return t, tf, dr
+
+    t, tf, dr = run("f32")
+    t64, tf64, dr64 = run("f64")
     return {"workload": "2D 512^2 FP32, dt=0.5, loss on psi(T), grads w.r.t. psi0 and r, checkpoints every "
                         f"{every}", "steps": nsteps, "fwd_bwd_s": round(t, 4),
             "fwd_bwd_steps_per_s": round(nsteps / t, 1), "forward_only_steps_per_s": round(nsteps / tf, 1),
-            "dL_dr": dr}
+            "dL_dr": dr,
+            "fp64_check": {"fwd_bwd_s": round(t64, 4), "fwd_bwd_steps_per_s": round(nsteps / t64, 1),
+                           "forward_only_steps_per_s": round(nsteps / tf64, 1), "dL_dr": dr64,
+                           "dL_dr_rel_diff_fp32": abs(dr - dr64) / abs(dr64)}}
 
 
 KERNEL_PASS = {"x_r2c_kernel": "x_r2c_cube", "last_axis_kernel": "z_fused_update", "x_c2r_kernel": "x_c2r"}
@@ -619,7 +633,9 @@ def main():
     if "adjoint" in legs and args.adjoint_steps > 0:
         log(f"[bench] adjoint form: 512^2, {args.adjoint_steps} steps")
         adjoint = bench_adjoint(args.adjoint_steps, 50)
-        log(f"[bench] adjoint {adjoint['fwd_bwd_steps_per_s']} steps/s forward+backward")
+        log(f"[bench] adjoint {adjoint['fwd_bwd_steps_per_s']} steps/s forward+backward (FP64 check run "
+            f"{adjoint['fp64_check']['fwd_bwd_steps_per_s']}; dL/dr FP32 vs FP64 "
+            f"{adjoint['fp64_check']['dL_dr_rel_diff_fp32']:.1e})")
     cpu = None
     if "cpu" in legs and args.cpu_steps > 0:
         log(f"[bench] CPU oracle: {args.cpu_steps} FP64 steps of the same 512^3 workload, then "
