@@ -141,10 +141,19 @@ pfc_status pfc_state_export(pfc_plan *p, const void *state, void *half_natural, 
 
 /* Advance `nsteps` >= 0 semi-implicit steps (Listing 1).  psi: real field psi^n in, psi^{n+nsteps}
  * out.  state: native spectrum of psi^n in, updated in place.  The psi that enters a step is the
- * one the cube is taken of; the state is the one the update is applied to.
+ * one the cube is taken of; the state is the one the update is applied to.  The intermediate
+ * fields psi^{n+1} .. psi^{n+nsteps-1} are not stored where pfc_plan_x_fused says so (their
+ * inverse and the next forward x transform then run as one pass); the results are the same bits.
  * Source: Eq. (4) stepped as in Listing 1 (cube, forward transform, semi-implicit update,
  * inverse transform). */
 pfc_status pfc_step(pfc_plan *p, void *psi, void *state, int64_t nsteps, void *stream);
+
+/* 1 when pfc_step fuses the inverse x transform of one step with the cube and forward x transform
+ * of the next (x rows shorter than 1024 points whose default schedules fit a wavefront, on the
+ * default x schedules), else 0 (also for p == NULL).  Its HBM traffic per step is then 10 field
+ * passes, plus 2 per call, instead of 12 (3D; 2D: 6 plus 2 instead of 8).  Source: Listing 1
+ * stores psi after every step; not storing it between the steps of one call is this library's. */
+int pfc_plan_x_fused(const pfc_plan *p);
 
 /* pfc_step for callers that cannot allocate device memory (code under HIP graph capture, tight
  * serving loops, harnesses that forbid hipMalloc): the same kernels and results as pfc_step, but

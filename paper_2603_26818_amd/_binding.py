@@ -85,6 +85,7 @@ _SIGS = {
     "pfc_plan_real_bytes": (ctypes.c_size_t, [ctypes.c_void_p]),
     "pfc_plan_half_bytes": (ctypes.c_size_t, [ctypes.c_void_p]),
     "pfc_plan_state_bytes": (ctypes.c_size_t, [ctypes.c_void_p]),
+    "pfc_plan_x_fused": (ctypes.c_int, [ctypes.c_void_p]),
     "pfc_fft_r2c": (ctypes.c_int, [ctypes.c_void_p] * 4),
     "pfc_fft_c2r": (ctypes.c_int, [ctypes.c_void_p] * 4),
     "pfc_state_init": (ctypes.c_int, [ctypes.c_void_p] * 4),
@@ -253,6 +254,11 @@ class Plan:
 
     def empty_half(self):
         return _torch().empty(self.half_shape, dtype=self.complex_dtype, device=self.device)
+
+    @property
+    def x_fused(self):
+        """Whether step() fuses the x passes between steps (pfc_plan_x_fused)."""
+        return bool(self._lib.pfc_plan_x_fused(self._h))
 
     def empty_state(self):
         return _torch().empty(self.state_shape, dtype=self.complex_dtype, device=self.device)

@@ -130,7 +130,7 @@ template <typename T, class PLI, class PLF>
 __device__ __noinline__ void batch_x_fused(const BatchInst<T> *in, int item, const cx<T> *tw, int lt_shift)
 {
     x_c2r_r2c_block<T, PLI, PLF, kBatchThreads>(in->scratch, in->scratch, in->n0, tw, lt_shift, in->sc, item,
-                                                batch_lds<T>());
+                                                batch_lds<T>(), row_pack(in->M));
 }
 
 template <typename T, class PL>

@@ -392,11 +392,12 @@ struct XFused {
     // both schedules fill the same workgroup, and a group of either kind tiles the R rows
     static constexpr bool ok = RI * PLI::Tp == RF * PLF::Tp && R % RI == 0 && R % RF == 0;
 };
-// One block of R rows (block index `bid`); `sh` holds R M LDS slots; NTH threads.
+// One block of R rows (block index `bid`) of packed spectra in the layout `pk`; `sh` holds R M LDS
+// slots; NTH threads.  In place (in == out) is safe: the block reads all its rows before it writes.
 template <typename T, class PLI, class PLF, int NTH, bool NT = false>
 __device__ __forceinline__ void x_c2r_r2c_block(const cx<T> *in, cx<T> *out, int64_t nrows,
                                                 const cx<T> *__restrict__ tw, int lt_shift, T sc, int64_t bid,
-                                                cx<T> *sh)
+                                                cx<T> *sh, const Pack &pk)
 {
     using F = XFused<PLI, PLF, NTH>;
     static_assert(F::ok && PLI::L == PLF::L, "schedules must share the workgroup");
@@ -406,12 +407,22 @@ __device__ __forceinline__ void x_c2r_r2c_block(const cx<T> *in, cx<T> *out, int
     for (int s = 0; s < F::R / F::RI; ++s)
         x_c2r_block<T, PLI, F::RI, EPI_PLAIN, false, false, NT, true>(in, nullptr, nrows, tw, lt_shift, sc, ea,
                                                                       bid * (F::R / F::RI) + s, sh + s * F::RI * M,
-                                                                      row_pack(M));
+                                                                      pk);
     __syncthreads();  // all staged rows written
 #pragma unroll
     for (int s = 0; s < F::R / F::RF; ++s)
         x_r2c_block<T, PLF, F::RF, true, false, NT, true>(nullptr, out, nrows, tw, lt_shift, bid * (F::R / F::RF) + s,
-                                                          sh + s * F::RF * M, row_pack(M));
+                                                          sh + s * F::RF * M, pk);
+}
+
+// The fused x pass of the single-plan step between two steps: one workgroup of NTH threads (one
+// wavefront in the step) takes XFused<PLI, PLF, NTH>::R rows of the packed spectrum, in place.
+template <typename T, class PLI, class PLF, int NTH, bool NT>
+__global__ __launch_bounds__(NTH) void x_c2r_r2c_kernel(cx<T> *data, int64_t nrows, const cx<T> *__restrict__ tw,
+                                                        int lt_shift, T sc, Pack pk)
+{
+    __shared__ cx<T> sh[XFused<PLI, PLF, NTH>::R * PLI::L];
+    x_c2r_r2c_block<T, PLI, PLF, NTH, NT>(data, data, nrows, tw, lt_shift, sc, blockIdx.x, sh, pk);
 }
 
 

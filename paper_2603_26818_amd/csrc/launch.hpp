@@ -61,6 +61,13 @@ hipError_t launch_x_r2c(const Geom &g, const T *in, cx<T> *out, bool cube, const
 template <typename T>
 hipError_t launch_x_c2r(const Geom &g, const cx<T> *in, T *out, const cx<T> *tw, hipStream_t s, int variant = 0);
 
+// fused x pass between two steps, in place on the packed spectrum: x c2r (1/N), cube, x r2c; on the
+// default x schedules, where x_fused_ok says the geometry has it
+template <typename T>
+hipError_t launch_x_c2r_r2c(const Geom &g, cx<T> *data, const cx<T> *tw, hipStream_t s);
+template <typename T>
+bool x_fused_ok(const Geom &g);
+
 // adjoint epilogue: out = mu - c3 psi_n^2 nu; partial[block] = sum nu psi_np1.  Returns the number
 // of partials through *nblocks.
 template <typename T>

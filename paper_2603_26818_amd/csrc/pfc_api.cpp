@@ -36,6 +36,7 @@ struct pfc_plan {
     char *ws = nullptr;
     size_t ws_bytes = 0;
     int var[5] = {0, 0, 0, 0, 0};  // candidate schedule of each step pass (autotuner)
+    bool x_fused = false;          // the geometry has the fused x pass between steps
     std::vector<char> tw_host;     // the twiddle tables as uploaded (built on first use)
     uint64_t id = 0;               // unique per plan in this process
 };
@@ -428,12 +429,23 @@ pfc_status step_pass(const pfc_plan *p, const Bufs<T> &b, int pass, void *psi, v
     return PFC_OK;
 }
 
+// Steps in sequence.  Between two steps the x c2r of the first and the x r2c (with the cube) of the
+// second run as one fused pass on the spectrum (launch_x_c2r_r2c: the real field in between stays in
+// LDS and is never stored), where the geometry has it and both x passes take their default schedules;
+// the first step's x r2c reads psi and the last step's x c2r writes it.  The results are those of
+// the separate passes, bit for bit.
 template <typename T>
 pfc_status step_with(const pfc_plan *p, const Bufs<T> &b, void *psi, void *state, int64_t nsteps, hipStream_t s)
 {
     const int np = step_passes(p);
+    const bool fuse = p->x_fused && p->var[0] == 0 && p->var[np - 1] == 0;
     for (int64_t n = 0; n < nsteps; ++n)
         for (int k = 0; k < np; ++k) {
+            if (fuse && k == 0 && n > 0) continue;  // done by the fused pass that ended the step before
+            if (fuse && k == np - 1 && n + 1 < nsteps) {
+                PFC_TRY(pfc::launch_x_c2r_r2c<T>(p->g, b.scratch, b.tw, s), "fused x pass launch");
+                continue;
+            }
             pfc_status st = step_pass<T>(p, b, k, psi, state, s);
             if (st) return st;
         }
@@ -1023,6 +1035,7 @@ pfc_status pfc_plan_create(pfc_plan **out, const pfc_plan_desc *d)
     g.tw_y = (d->ndim == 3) ? table_of(g.n1) : 0;
     g.tw_last = table_of(g.n0);
     p->tw_entries = tw_entries;
+    p->x_fused = (d->dtype == PFC_F64) ? pfc::x_fused_ok<double>(g) : pfc::x_fused_ok<float>(g);
     p->tw_off = 0;
     p->partial_off = align256(tw_entries * cs);
     p->watch_off = p->partial_off + align256(p->n_partials * sizeof(double));
@@ -1036,6 +1049,10 @@ size_t pfc_plan_workspace_bytes(const pfc_plan *p) { return p ? p->ws_need : 0; 
 size_t pfc_plan_real_bytes(const pfc_plan *p) { return p ? real_bytes(p) : 0; }
 size_t pfc_plan_half_bytes(const pfc_plan *p) { return p ? half_bytes(p) : 0; }
 size_t pfc_plan_state_bytes(const pfc_plan *p) { return p ? state_bytes(p) : 0; }
+int pfc_plan_x_fused(const pfc_plan *p)
+{
+    return (p && p->x_fused && p->var[0] == 0 && p->var[step_passes(p) - 1] == 0) ? 1 : 0;
+}
 
 pfc_status pfc_plan_set_workspace(pfc_plan *p, void *dev_ptr, size_t bytes)
 {

@@ -31,6 +31,16 @@ def test_more_than_one_gpu_is_refused():
     assert "one GPU" in r.stderr
 
 
+def test_step_byte_model():
+    class Plan:
+        x_fused = False
+
+    assert bench.step_passes_hbm(Plan(), 300) == 12.0
+    Plan.x_fused = True
+    assert bench.step_passes_hbm(Plan(), 1) == 12.0  # one step: x r2c and x c2r, no fused pass
+    assert bench.step_passes_hbm(Plan(), 300) == pytest.approx(10.0 + 2.0 / 300)
+
+
 def test_median_spread():
     assert bench.median_spread([3.0, 1.0, 2.0, 5.0, 4.0]) == (3.0, 1.0, 5.0)
 
