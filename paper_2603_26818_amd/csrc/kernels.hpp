@@ -375,14 +375,15 @@ __global__ __launch_bounds__(ROWS *PL::Tp) void x_c2r_kernel(const cx<T> *in, T 
 // ------------------------------------------------------------------------------------------------
 // Pencils per workgroup of the strided passes: 128-byte rows (16 FP32 / 8 FP64 complex) as long as
 // the workgroup's LDS tile stays within 128 KB.
-// x pass between two steps of a batched run: the inverse x transform of one step (x c2r) and the
-// forward x transform with the cube of the next (x r2c), over the same rows, with the field between
-// them kept in LDS: a workgroup takes R rows, runs the c2r schedule PLI on them in groups of RI rows
-// (each group leaving its reals in its rows' LDS slots), then the r2c schedule PLF in groups of RF
-// rows reading those slots.  The field of the intermediate step is never stored.  Arithmetic
-// identical to x_c2r_kernel followed by x_r2c_kernel with the cube.  (As a separate kernel of the
-// single-plan step it measured no faster than the two passes it replaces: 0.40 ms against 0.41 ms at
-// 512^3, slower at 2048^3; with half the memory traffic, the two row FFTs then bound it.)
+// x pass between two steps (batched runs, and the single-plan step within one call): the inverse x
+// transform of one step (x c2r) and the forward x transform with the cube of the next (x r2c), over
+// the same rows, with the field between them kept in LDS: a workgroup takes R rows, runs the c2r
+// schedule PLI on them in groups of RI rows (each group leaving its reals in its rows' LDS slots),
+// then the r2c schedule PLF in groups of RF rows reading those slots.  The field of the intermediate
+// step is never stored.  Arithmetic identical to x_c2r_kernel followed by x_r2c_kernel with the
+// cube.  The single-plan step runs it with one wavefront per workgroup (at 512^3: 4 rows, 8 KB of
+// LDS, many workgroups per CU), which keeps the row FFTs, that bound it at half the memory traffic,
+// overlapped; 256-thread workgroups measured no faster than the two separate passes.
 template <class PLI, class PLF, int NTH = 256>
 struct XFused {
     static constexpr int RI = NTH / PLI::Tp < 1 ? 1 : NTH / PLI::Tp;
