@@ -1136,7 +1136,7 @@ __global__ __launch_bounds__(C *PL::Tp) void r2c_natural_chunk_kernel(const cx<T
     const bool fold = (kx == 0 || kx == M);
     const int64_t estride = pk.e_stride();  // element steps k below are multiples of the layout's block
     cx<T> v[Rmax];
-    // round 1: own pencil (folded slots: packed column 0 of this row)
+    // first sweep: own pencil (folded slots: packed column 0 of this row)
     {
         const cx<T> *col = src + pk.at(t, row, fold ? 0 : kx);
 #pragma unroll
@@ -1154,7 +1154,7 @@ __global__ __launch_bounds__(C *PL::Tp) void r2c_natural_chunk_kernel(const cx<T
             for (int r = 0; r < Rl; ++r) st_grid<NT>(&dst[(int64_t)(t + b * Tp + r * (L / Rl)) * plane + f], v[b * Rl + r]);
     }
     if (!__syncthreads_or(fold)) return;  // uniform: the chunk has no folded slot
-    // round 2: mirror pencils of the folded slots
+    // second sweep: mirror pencils of the folded slots
     cx<T> z[Rmax];
 #pragma unroll
     for (int i = 0; i < Rmax; ++i) z[i] = v[i];
