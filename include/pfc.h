@@ -187,12 +187,15 @@ pfc_status pfc_step_timed(pfc_plan *p, void *psi, void *state, int64_t nsteps, v
                           int *npasses);
 
 /* Autotuner: every pass of the step has a few candidate radix schedules compiled in (tile shapes
- * follow from the schedule: rows per workgroup of the x passes, 128-byte column tiles of the strided
- * passes).  Times each candidate of each pass (`reps` launches after one warm-up, events on
- * `stream`) on this plan's shape and keeps the fastest in the plan; best_ms (5 doubles, may be NULL)
- * receives the winning average time per pass.  psi_scratch (real field) and state_scratch (native
- * state) are caller-owned scratch of the plan's sizes: their contents are overwritten; they should
- * hold a finite field and its state (values do not change the timing).  Blocks until done.
+ * follow from the schedule: rows per workgroup of the x passes, column tiles of the strided passes).
+ * Coordinate descent over whole steps: from the default schedules, each candidate of each pass in
+ * turn is kept when `reps` runs of 4 steps (after one warm-up, events on `stream`) take less time,
+ * so the choice accounts for the passes' interplay in a step, including the fused x pass between
+ * steps (pfc_plan_x_fused), which needs the default x schedules.  The choice stays in the plan;
+ * best_ms (5 doubles, may be NULL) receives the average time per pass of the choice, the passes run
+ * apart as in pfc_step_timed.  psi_scratch (real field) and state_scratch (native state) are
+ * caller-owned scratch of the plan's sizes: their contents are overwritten; they should hold a
+ * finite field and its state (values do not change the timing).  Blocks until done.
  * Source: the transforms of Listing 1 (how they are scheduled; results do not depend on it beyond
  * rounding). */
 pfc_status pfc_plan_autotune(pfc_plan *p, void *psi_scratch, void *state_scratch, void *stream, int reps,

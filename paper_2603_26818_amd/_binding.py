@@ -399,9 +399,10 @@ class Plan:
         return f"{arch}|{'x'.join(map(str, self.shape))}|{'f64' if self.f64 else 'f32'}"
 
     def autotune(self, reps=5, cache_path=None):
-        """Pick the fastest candidate schedule of each step pass (pfc_plan_autotune) on scratch
-        fields; with cache_path, reuse / record the choice in a JSON file keyed by GPU arch, shape
-        and dtype.  Returns (variants, best ms per pass or None when taken from the cache)."""
+        """Pick the candidate schedules of the step passes by whole-step timing (pfc_plan_autotune,
+        coordinate descent from the defaults) on scratch fields; with cache_path, reuse / record the
+        choice in a JSON file keyed by GPU arch, shape and dtype.  Returns (variants, ms per pass of
+        the choice, or None when taken from the cache)."""
         import json
 
         torch = _torch()
