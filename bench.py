@@ -366,9 +366,6 @@ def bench_adjoint(nsteps, every):
                            "dL_dr_rel_diff_fp32": abs(dr - dr64) / abs(dr64)}}
 
 
-KERNEL_PASS = {"x_r2c_kernel": "x_r2c_cube", "last_axis_kernel": "z_fused_update", "x_c2r_kernel": "x_c2r"}
-
-
 def counters_workload(steps, n=N):
     """Workload of the counter runs: a plain 1 GiB device copy (calibration of FETCH_SIZE and
     WRITE_SIZE against known bytes), then `steps` steps of the n^3 FP32 workload (512: the headline;
