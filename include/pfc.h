@@ -57,8 +57,9 @@ typedef enum { PFC_ONE_MODE = 0, PFC_TWO_MODE = 1 } pfc_model;
 /* Layout hints of the native state (3D plans).  They change where values are stored, not the
  * arithmetic: every layout gives the same bits.  By default the library pairs z planes (blocks of
  * 2) on power-of-two grids with z >= 256 and planes of at least 1 MiB, where that measured faster.
- * PFC_FLAG_ZBLOCK(s) forces blocks of 2^s z planes, s in 0..3 (s > 0 needs a power-of-two z length
- * >= 256 and rows of whole 128-byte lines, else pfc_plan_create returns PFC_ERR_INVALID_ARG).
+ * PFC_FLAG_ZBLOCK(s) forces blocks of 2^s z planes, s in 0..3 (s > 0 needs rows of whole 128-byte
+ * lines and a z length that is a power of two >= 256, or one whose last-axis schedules step by
+ * multiples of 2^s, as 750's do for s = 1; else pfc_plan_create returns PFC_ERR_INVALID_ARG).
  * PFC_FLAG_XROWS_BLOCK makes the x passes visit the planes of a block in turn instead of the rows
  * in their natural order. */
 #define PFC_FLAG_ZBLOCK(s) (0x10u | (((unsigned)(s) & 3u) << 5))

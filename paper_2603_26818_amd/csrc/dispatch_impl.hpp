@@ -56,6 +56,24 @@ static bool z_steps_ok(int zs)
     return PL::Tp % Z == 0 && (PL::L / PL::first) % Z == 0 && (PL::L / PL::last) % Z == 0;
 }
 
+// Whether blocks of 2^zs z planes suit this geometry's last-axis passes: the step's default z
+// schedule and the schedule of the other last-axis passes (state set-up, export, transforms) step
+// by multiples of the block.
+template <typename T>
+bool z_blocks_ok(const Geom &g, int zs)
+{
+    bool ok = false;
+    (void)by_length(g.n0, [&](auto Lc) -> hipError_t {
+        constexpr int L = decltype(Lc)::value;
+        using TO = TileOf<T, typename ListAt<0, typename ZCandsOf<T, L>::type>::type>;
+        using PZ = SpreadIf<typename TO::plan, TO::tile::E>;
+        using P0 = SpreadIf<typename LastPlan<L>::type, PencilTile<T, L>::E>;
+        ok = z_steps_ok<PZ>(zs) && z_steps_ok<P0>(zs) && z_steps_ok<typename LastPlan<L>::type>(zs);
+        return hipSuccess;
+    });
+    return ok;
+}
+
 // Addressing of the middle-axis (3D y) pass: batch = z plane, columns kx, elements y.
 static inline AxisMap y_map(const Geom &g)
 {
@@ -507,6 +525,7 @@ hipError_t launch_export(const Geom &g, const cx<T> *state, cx<T> *out, hipStrea
     template hipError_t launch_x_c2r<T>(const Geom &, const cx<T> *, T *, const cx<T> *, hipStream_t, int);           \
     template hipError_t launch_x_c2r_r2c<T>(const Geom &, cx<T> *, const cx<T> *, hipStream_t);                        \
     template bool x_fused_ok<T>(const Geom &);                                                                        \
+    template bool z_blocks_ok<T>(const Geom &, int);                                                                  \
     template hipError_t launch_x_c2r_adjoint<T>(const Geom &, const cx<T> *, const cx<T> *, const T *, const T *, T *, \
                                                 T, double *, int64_t *, const cx<T> *, hipStream_t);                  \
     template hipError_t launch_y_c2c<T>(const Geom &, cx<T> *, int, const cx<T> *, hipStream_t, int);                 \

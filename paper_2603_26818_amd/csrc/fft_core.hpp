@@ -336,7 +336,7 @@ template <> struct DefaultPlan<30> { using type = Radices<10, 3>; };
 template <> struct DefaultPlan<60> { using type = Radices<10, 6>; };
 template <> struct DefaultPlan<150> { using type = Radices<10, 15>; };
 template <> struct DefaultPlan<375> { using type = Radices<15, 5, 5>; };
-template <> struct DefaultPlan<750> { using type = Radices<10, 15, 5>; };
+template <> struct DefaultPlan<750> { using type = Radices<15, 10, 5>; };
 // 700 = 7 10 10 and 1400 = 14 10 10 have lcm 70: 50 threads per pencil with ragged stages instead
 template <> struct DefaultPlan<700> { using type = Radices<7, 10, 10, 50>; };
 template <> struct DefaultPlan<1400> { using type = Radices<14, 10, 10, 50>; };
@@ -418,17 +418,19 @@ template <> struct LastCands<512> { using type = PlanList<Radices<2, 16, 16>, Ra
 // the last axis of a 3D step (z): the 2D list, and at 512 tiles of 256-byte row segments (the
 // pencils' elements lie a whole z plane apart, so each element row of a tile is one segment)
 template <int L> struct ZCands { using type = typename LastCands<L>::type; };
-// 750 (z and y): the radices ragged over 50 threads per pencil (at most 20 elements each: 800
-// threads in one workgroup per CU, which its 96 KB of LDS allows) and the lcm schedule (25 threads
-// of 30 elements: 400 threads).  Measured at 750^3 FP32: z 2.20 against 2.86 ms.  Narrower z
-// tiles, so that two workgroups share a CU, measured slower: half a line (8 pencils, 48 KB) 2.23 ms,
-// two LDS groups (48 KB) 2.43 ms; so did persistent workgroups looping over the tiles at 512^3 (z
-// 539 against 506 us).
-template <> struct ZCands<750> { using type = PlanList<Radices<10, 15, 5, 50>, Radices<10, 15, 5>>; };
+// 750 (z, y and the other last-axis passes): 15 10 5 (every element step even, so that the
+// last-axis passes can address blocks of plane pairs), ragged over 50 threads per pencil (at most
+// 20 elements each: 800 threads in one workgroup per CU, which its 96 KB of LDS allows), and the
+// lcm schedule (25 threads of 30 elements: 400 threads).  Measured at 750^3 FP32 with 10 15 5: z
+// 2.20 against 2.86 ms.  Narrower z tiles, so that two workgroups share a CU, measured slower: half
+// a line (8 pencils, 48 KB) 2.23 ms, two LDS groups (48 KB) 2.43 ms; so did persistent workgroups
+// looping over the tiles at 512^3 (z 539 against 506 us).
+template <> struct ZCands<750> { using type = PlanList<Radices<15, 10, 5, 50>, Radices<15, 10, 5>>; };
+template <> struct LastCands<750> { using type = PlanList<Radices<15, 10, 5, 50>>; };
 // y at 750: half-line tiles (8 pencils, 48 KB, two workgroups per CU; the plane order keeps the two
 // tiles of a line on one XCD) first: 0.74 against 0.85 ms per direction at 750^3 FP32
 template <> struct AxisCands<750> {
-    using type = PlanList<Tiled<Radices<10, 15, 5, 50>, 64, 0, 1, false>, Radices<10, 15, 5, 50>, Radices<10, 15, 5>>;
+    using type = PlanList<Tiled<Radices<15, 10, 5, 50>, 64, 0, 1, false>, Radices<15, 10, 5, 50>, Radices<15, 10, 5>>;
 };
 // 2048-point y and z pencils (2048^3): 16 8 16 first, measured at 2048^3 FP32: y 16.2 against
 // 16.5 ms per direction, z 39.4 against 40.0 ms
@@ -499,6 +501,8 @@ __device__ __forceinline__ void apply_twiddles(cx<T> *v, int jj, const cx<T> *__
     constexpr int R = PL::radix(s), Ns = PL::prefix(s);
     if constexpr (TWM == TW_MIX) {
         using F = typename MixPlan<PL::L>::type;
+        static_assert(same_stages<PL, F>() || same_stages<PL, typename F::Reverse>(),
+                      "a schedule of a length that is not a power of two takes the stages of its table");
         constexpr int base = same_stages<PL, F>() ? 0 : stage_blocks_off<F>(F::nst);
         const cx<T> *st = tw + base + stage_blocks_off<PL>(s) + (unsigned)(jj * R);
 #pragma unroll

@@ -67,6 +67,10 @@ template <typename T>
 hipError_t launch_x_c2r_r2c(const Geom &g, cx<T> *data, const cx<T> *tw, hipStream_t s);
 template <typename T>
 bool x_fused_ok(const Geom &g);
+// whether the last-axis passes can address blocks of 2^zs z planes (their element steps are
+// multiples of the block)
+template <typename T>
+bool z_blocks_ok(const Geom &g, int zs);
 
 // adjoint epilogue: out = mu - c3 psi_n^2 nu; partial[block] = sum nu psi_np1.  Returns the number
 // of partials through *nblocks.

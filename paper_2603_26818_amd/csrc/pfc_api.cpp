@@ -1025,12 +1025,18 @@ pfc_status pfc_plan_create(pfc_plan **out, const pfc_plan_desc *d)
         const int64_t plane = g.nrows * g.Mp * (int64_t)cs;
         const bool blockable = is_pow2(g.n0) && g.n0 >= 256 && g.Mp % CB == 0;
         if (blockable && plane >= (int64_t(1) << 20)) g.zs = 1;
+        // other z lengths take blocks on request where their last-axis schedules step by whole blocks
+        auto blocks_ok = [&](int zs) {
+            if (blockable) return true;
+            if (is_pow2(g.n0) || g.Mp % CB != 0 || g.n0 % (int64_t(1) << zs) != 0) return false;
+            return (d->dtype == PFC_F64) ? pfc::z_blocks_ok<double>(g, zs) : pfc::z_blocks_ok<float>(g, zs);
+        };
         if (d->flags & 0x10u) {  // PFC_FLAG_ZBLOCK(s): forced block size
             const int zs = (int)((d->flags >> 5) & 3u);
-            if (zs > 0 && !blockable) {
+            if (zs > 0 && !blocks_ok(zs)) {
                 delete p;
-                return fail(PFC_ERR_INVALID_ARG, "PFC_FLAG_ZBLOCK(%d) needs a power-of-two z length >= 256 and rows of "
-                            "whole 128-byte lines", zs);
+                return fail(PFC_ERR_INVALID_ARG, "PFC_FLAG_ZBLOCK(%d) needs rows of whole 128-byte lines and a z length "
+                            "that is a power of two >= 256 or whose last-axis schedules step by whole blocks", zs);
             }
             g.zs = zs;
         }

@@ -284,14 +284,18 @@ def test_apfc_calls_without_workspace_fail_cleanly():
 
 
 def test_layout_hint_flags_are_validated():
-    """PFC_FLAG_ZBLOCK(s > 0) needs a power-of-two z length >= 256 with rows of whole lines; unknown
-    flag bits are rejected; the state of a paired-plane layout keeps the real field's bytes."""
+    """PFC_FLAG_ZBLOCK(s > 0) needs rows of whole lines and a z length that is a power of two >= 256,
+    or one whose last-axis schedules step by whole blocks (750 for pairs); unknown flag bits are
+    rejected; the state of a paired-plane layout keeps the real field's bytes (plus row padding)."""
     b, lib = _lib()
     ok, h = _create(b, lib, _desc(b, (256, 64, 2048), 1, flags=b.PFC_FLAG_ZBLOCK(3) | b.PFC_FLAG_XROWS_BLOCK))
     assert ok == 0, lib.pfc_last_error()
     assert lib.pfc_plan_state_bytes(h) == 256 * 64 * 1024 * 16
-    for shape in ((128, 64, 2048), (750, 750, 750), (16, 32, 64)):
-        st, _ = _create(b, lib, _desc(b, shape, 0, flags=b.PFC_FLAG_ZBLOCK(1)))
+    ok, h = _create(b, lib, _desc(b, (750, 750, 750), 0, flags=b.PFC_FLAG_ZBLOCK(1)))
+    assert ok == 0, lib.pfc_last_error()
+    assert lib.pfc_plan_state_bytes(h) == 750 * 750 * 384 * 8  # rows of 375 padded to 384
+    for shape, zs in (((128, 64, 2048), 1), ((750, 750, 750), 2), ((750, 750, 12), 1), ((16, 32, 64), 1)):
+        st, _ = _create(b, lib, _desc(b, shape, 0, flags=b.PFC_FLAG_ZBLOCK(zs)))
         assert st == 1, shape  # PFC_ERR_INVALID_ARG
     st, _ = _create(b, lib, _desc(b, (64, 64), 0, flags=0x100))
     assert st == 1

@@ -34,10 +34,13 @@ def _blocked():
 
     return [((256, 128, 2048), "f32", 0), ((256, 64, 2048), "f64", 0),
             ((256, 128, 2048), "f32", B.PFC_FLAG_ZBLOCK(2) | B.PFC_FLAG_XROWS_BLOCK),
-            ((256, 64, 2048), "f64", B.PFC_FLAG_ZBLOCK(3))]
+            ((256, 64, 2048), "f64", B.PFC_FLAG_ZBLOCK(3)),
+            # mixed radix: plane pairs of a 750-long z axis (its last-axis schedules, 15 10 5, step
+            # by even element counts) with rows of 375 padded to whole lines
+            ((750, 4, 750), "f32", B.PFC_FLAG_ZBLOCK(1)), ((750, 4, 750), "f64", B.PFC_FLAG_ZBLOCK(1))]
 
 
-@pytest.mark.parametrize("case", range(4))
+@pytest.mark.parametrize("case", range(6))
 def test_blocked_layout_transforms_state_energy_step(pfc, case):
     shape, dtype, flags = _blocked()[case]
     say(f"[layout] {shape} {dtype} flags {flags:#x}: r2c, c2r, state, export, energy, 2 steps vs oracle")
@@ -76,7 +79,8 @@ def test_blocked_layout_transforms_state_energy_step(pfc, case):
     tolF = max(tol, 10.0 * own)
     say(f"      energy rel diff {abs(F[0] - Fr[0]) / abs(Fr[0]):.2e} (oracle spectral vs real space {own:.2e})")
     assert abs(F[0] - Fr[0]) < tolF * abs(Fr[0]) and abs(F[1] - Fr[2]) < tol * abs(Fr[2])
-    assert _state_pitch(plan) == shape[-1] // 2  # whole lines already: no padding, only blocks
+    M, cb = shape[-1] // 2, (16 if dtype == "f32" else 8)  # columns of one 128-byte line
+    assert _state_pitch(plan) == (M if M % cb == 0 else (M + cb - 1) // cb * cb)  # rows padded to whole lines
 
 
 @pytest.mark.parametrize("hint", ["default", "zblock4_block_order"])
