@@ -119,37 +119,54 @@ struct XRows {
     static constexpr int value = (256 / PL::Tp) > 64 ? 64 : ((256 / PL::Tp) < 1 ? 1 : 256 / PL::Tp);
 };
 
-// LDS slot of element e in a row of the x pass: one spare slot after every 8 elements, so that the
-// Stockham stage writes (stride R between neighbouring threads) spread over the banks.
-__device__ __forceinline__ int xpad(int e) { return e + (e >> 3); }
-template <int M, bool PAD>
-struct XPitch {
-    static constexpr int value = PAD ? M + M / 8 + (M < 8 ? 1 : 0) : M;
+// Padded LDS rows of the x pass (PAD, power-of-two rows of M complex values): 16 spare bytes after
+// every 256 bytes of a row, i.e. after every S = 256 / sizeof(cx<T>) elements (M, if shorter).  With
+// 64 banks of 4 bytes, a Stockham stage write puts neighbouring threads R elements apart; unpadded,
+// the threads of a power-of-two row then meet on a few bank positions of each 256-byte sweep (up to
+// 16 ways for the first stage of a 512-point r2c).  The 16-byte step keeps 16-byte alignment and
+// fixed offsets between one thread's elements, so merged and paired LDS accesses stay possible.
+template <typename T, int M>
+struct XPad {
+    static constexpr int S0 = 256 / (int)sizeof(cx<T>);
+    static constexpr int S = S0 < M ? S0 : M;
+    static constexpr int k = 16 / (int)sizeof(cx<T>);
+    static constexpr int shift = ilog2c(S);
 };
-template <bool PAD>
-__device__ __forceinline__ int xidx(int e) { return PAD ? xpad(e) : e; }
+template <typename T, int M, bool PAD>
+struct XPitch {
+    static_assert(!PAD || is_pow2c(M), "padded rows are powers of two");
+    static constexpr int value = PAD ? M + XPad<T, M>::k * (M / XPad<T, M>::S) : M;
+};
+template <typename T, int M, bool PAD>
+__device__ __forceinline__ int xidx(int e)
+{
+    if constexpr (PAD)
+        return e + XPad<T, M>::k * (e >> XPad<T, M>::shift);
+    else
+        return e;
+}
 
 // Identity layout of a packed spectrum with rows of M values (2D plans, the batched form).
 __host__ __device__ inline Pack row_pack(int64_t M) { return Pack{1, M, 0, 0}; }
 
-// One block of ROWS rows (block index `bid`); `sh` holds ROWS * XPitch<M, PAD> LDS slots.
+// One block of ROWS rows (block index `bid`); `sh` holds ROWS * XPitch<T, M, PAD> LDS slots.
 // Uses threads 0 .. ROWS*Tp-1, which must be all threads of the workgroup.  FROM_LDS: the rows'
-// reals are not read from `in` but from `sh` (row p at sh[p M], as packed pairs), where the caller
+// reals are not read from `in` but from `sh` (row p at sh[p LD], LD the row pitch, as packed
+// pairs, contiguous), where the caller
 // has left them.  Output row rr (= e nrows + row) goes to the layout `pk`.
 template <typename T, class PL, int ROWS, bool CUBE, bool PAD = false, bool NT = false, bool FROM_LDS = false>
 __device__ __forceinline__ void x_r2c_block(const T *__restrict__ in, cx<T> *__restrict__ out, int64_t nrows,
                                             const cx<T> *__restrict__ tw, int lt_shift, int64_t bid, cx<T> *sh,
                                             const Pack &pk)
 {
-    static_assert(!FROM_LDS || !PAD, "staged rows are unpadded");
     constexpr int M = PL::L, Tp = PL::Tp, R0 = PL::first, Rl = PL::last, Rmax = PL::Rmax;
-    constexpr int LD = XPitch<M, PAD>::value;  // row pitch in LDS
+    constexpr int LD = XPitch<T, M, PAD>::value;  // row pitch in LDS
     const int tid = threadIdx.x, p = tid / Tp, t = tid - p * Tp;
     const int64_t rho = bid * ROWS + p;  // position in the pass's row order (Pack::x_row)
     const bool valid = rho < nrows;
     int64_t obase;
     const int64_t row = pk.x_row(valid ? rho : 0, &obase);
-    const cx<T> *src = FROM_LDS ? sh + p * M : reinterpret_cast<const cx<T> *>(in) + row * M;
+    const cx<T> *src = FROM_LDS ? sh + p * LD : reinterpret_cast<const cx<T> *>(in) + row * M;
     cx<T> v[Rmax];
 #pragma unroll
     for (int b = 0; b < PL::nb(R0); ++b)
@@ -164,7 +181,7 @@ __device__ __forceinline__ void x_r2c_block(const T *__restrict__ in, cx<T> *__r
             if constexpr (CUBE) z = {z.x * z.x * z.x, z.y * z.y * z.y};
             v[b * R0 + r] = z;
         }
-    auto lds = [&](int e) -> cx<T> & { return sh[p * LD + xidx<PAD>(e)]; };
+    auto lds = [&](int e) -> cx<T> & { return sh[p * LD + xidx<T, M, PAD>(e)]; };
     fft_stages<T, PL, -1, TW_LT>(v, t, lds, tw, lt_shift);  // measured faster here than TW_STAGE
     __syncthreads();
 #pragma unroll
@@ -200,7 +217,7 @@ __global__ __launch_bounds__(ROWS *PL::Tp) void x_r2c_kernel(const T *__restrict
                                                               int64_t nrows, const cx<T> *__restrict__ tw,
                                                               int lt_shift, Pack pk)
 {
-    __shared__ cx<T> sh[ROWS * XPitch<PL::L, PAD>::value];
+    __shared__ cx<T> sh[ROWS * XPitch<T, PL::L, PAD>::value];
     x_r2c_block<T, PL, ROWS, CUBE, PAD, NT>(in, out, nrows, tw, lt_shift, blockIdx.x, sh, pk);
 }
 
@@ -257,7 +274,7 @@ __device__ __forceinline__ void x_c2r_row(cx<T> *v, const cx<T> *src, bool valid
             for (int r = 0; r < R0; ++r) {
                 const int k = t + b * Tp + r * (M / R0);
                 v[b * R0 + r] = valid ? ld_grid<NT>(&src[pk.col(k)]) : cx<T>{T(0), T(0)};
-                rowlds[xidx<PAD>(k)] = v[b * R0 + r];
+                rowlds[xidx<T, M, PAD>(k)] = v[b * R0 + r];
             }
         __syncthreads();
     }
@@ -276,7 +293,7 @@ __device__ __forceinline__ void x_c2r_row(cx<T> *v, const cx<T> *src, bool valid
                 if constexpr (PG)
                     c = mir[b * R0 + r];
                 else
-                    c = rowlds[xidx<PAD>(M - k)];
+                    c = rowlds[xidx<T, M, PAD>(M - k)];
                 const cx<T> E = {(a.x + c.x) * h, (a.y - c.y) * h};
                 const cx<T> D = {(a.x - c.x) * h, (a.y + c.y) * h};
                 const cx<T> O = cmul(conj(split_twiddle<T, M>(tw, lt_shift, k)), D);
@@ -285,23 +302,23 @@ __device__ __forceinline__ void x_c2r_row(cx<T> *v, const cx<T> *src, bool valid
         }
 }
 
-// TO_LDS (EPI_PLAIN): the scaled reals of row p are left in sh[p M] (as packed pairs) instead of
-// being stored to `out`.
+// TO_LDS (EPI_PLAIN): the scaled reals of row p are left in sh[p LD] (LD the row pitch, as packed
+// pairs, contiguous) instead of being stored to `out`.
 template <typename T, class PL, int ROWS, int EPI, bool PAD = false, bool PG = false, bool NT = false,
           bool TO_LDS = false>
 __device__ __forceinline__ void x_c2r_block(const cx<T> *in, T *out, int64_t nrows, const cx<T> *__restrict__ tw,
                                             int lt_shift, T sc, const AdjEpi<T> &ea, int64_t bid, cx<T> *sh,
                                             const Pack &pk)
 {
-    static_assert(!TO_LDS || (EPI == EPI_PLAIN && !PAD), "staging only for the plain epilogue, unpadded");
+    static_assert(!TO_LDS || EPI == EPI_PLAIN, "staging only for the plain epilogue");
     constexpr int M = PL::L, Tp = PL::Tp, Rl = PL::last, Rmax = PL::Rmax;
-    constexpr int LD = XPitch<M, PAD>::value;
+    constexpr int LD = XPitch<T, M, PAD>::value;
     const int tid = threadIdx.x, p = tid / Tp, t = tid - p * Tp;
     const int64_t rho = bid * ROWS + p;  // position in the pass's row order (Pack::x_row)
     const bool valid = rho < nrows;
     int64_t ibase;
     const int64_t r0 = pk.x_row(valid ? rho : 0, &ibase);  // real-field row
-    auto lds = [&](int e) -> cx<T> & { return sh[p * LD + xidx<PAD>(e)]; };
+    auto lds = [&](int e) -> cx<T> & { return sh[p * LD + xidx<T, M, PAD>(e)]; };
     cx<T> v[Rmax];
     x_c2r_row<T, PL, ROWS, PAD, PG, NT>(v, in + ibase, valid, t, &sh[p * LD], tw, lt_shift, pk);
     fft_stages<T, PL, +1>(v, t, lds, tw, lt_shift);
@@ -327,7 +344,7 @@ __device__ __forceinline__ void x_c2r_block(const cx<T> *in, T *out, int64_t nro
         for (int b = 0; b < PL::nb(Rl); ++b)
             if (PL::jok(t + b * Tp, Rl))
 #pragma unroll
-            for (int r = 0; r < Rl; ++r) sh[p * M + t + b * Tp + r * (M / Rl)] = scale(v[b * Rl + r], sc);
+            for (int r = 0; r < Rl; ++r) sh[p * LD + t + b * Tp + r * (M / Rl)] = scale(v[b * Rl + r], sc);
     } else if constexpr (EPI == EPI_PLAIN) {
         if (valid) {
 #pragma unroll
@@ -368,7 +385,7 @@ __global__ __launch_bounds__(ROWS *PL::Tp) void x_c2r_kernel(const cx<T> *in, T 
                                                               const cx<T> *__restrict__ tw, int lt_shift, T sc,
                                                               AdjEpi<T> ea, Pack pk)
 {
-    __shared__ cx<T> sh[ROWS * XPitch<PL::L, PAD>::value];
+    __shared__ cx<T> sh[ROWS * XPitch<T, PL::L, PAD>::value];
     x_c2r_block<T, PL, ROWS, EPI, PAD, PG, NT>(in, out, nrows, tw, lt_shift, sc, ea, blockIdx.x, sh, pk);
 }
 
@@ -393,37 +410,38 @@ struct XFused {
     // both schedules fill the same workgroup, and a group of either kind tiles the R rows
     static constexpr bool ok = RI * PLI::Tp == RF * PLF::Tp && R % RI == 0 && R % RF == 0;
 };
-// One block of R rows (block index `bid`) of packed spectra in the layout `pk`; `sh` holds R M LDS
-// slots; NTH threads.  In place (in == out) is safe: the block reads all its rows before it writes.
-template <typename T, class PLI, class PLF, int NTH, bool NT = false>
+// One block of R rows (block index `bid`) of packed spectra in the layout `pk`; `sh` holds
+// R XPitch<T, M, PAD> LDS slots; NTH threads.  In place (in == out) is safe: the block reads all its
+// rows before it writes.
+template <typename T, class PLI, class PLF, int NTH, bool NT = false, bool PAD = false>
 __device__ __forceinline__ void x_c2r_r2c_block(const cx<T> *in, cx<T> *out, int64_t nrows,
                                                 const cx<T> *__restrict__ tw, int lt_shift, T sc, int64_t bid,
                                                 cx<T> *sh, const Pack &pk)
 {
     using F = XFused<PLI, PLF, NTH>;
     static_assert(F::ok && PLI::L == PLF::L, "schedules must share the workgroup");
-    constexpr int M = PLI::L;
+    constexpr int LD = XPitch<T, PLI::L, PAD>::value;
     const AdjEpi<T> ea{};
 #pragma unroll
     for (int s = 0; s < F::R / F::RI; ++s)
-        x_c2r_block<T, PLI, F::RI, EPI_PLAIN, false, false, NT, true>(in, nullptr, nrows, tw, lt_shift, sc, ea,
-                                                                      bid * (F::R / F::RI) + s, sh + s * F::RI * M,
-                                                                      pk);
+        x_c2r_block<T, PLI, F::RI, EPI_PLAIN, PAD, false, NT, true>(in, nullptr, nrows, tw, lt_shift, sc, ea,
+                                                                    bid * (F::R / F::RI) + s, sh + s * F::RI * LD,
+                                                                    pk);
     __syncthreads();  // all staged rows written
 #pragma unroll
     for (int s = 0; s < F::R / F::RF; ++s)
-        x_r2c_block<T, PLF, F::RF, true, false, NT, true>(nullptr, out, nrows, tw, lt_shift, bid * (F::R / F::RF) + s,
-                                                          sh + s * F::RF * M, pk);
+        x_r2c_block<T, PLF, F::RF, true, PAD, NT, true>(nullptr, out, nrows, tw, lt_shift, bid * (F::R / F::RF) + s,
+                                                        sh + s * F::RF * LD, pk);
 }
 
 // The fused x pass of the single-plan step between two steps: one workgroup of NTH threads (one
 // wavefront in the step) takes XFused<PLI, PLF, NTH>::R rows of the packed spectrum, in place.
-template <typename T, class PLI, class PLF, int NTH, bool NT>
+template <typename T, class PLI, class PLF, int NTH, bool NT, bool PAD>
 __global__ __launch_bounds__(NTH) void x_c2r_r2c_kernel(cx<T> *data, int64_t nrows, const cx<T> *__restrict__ tw,
                                                         int lt_shift, T sc, Pack pk)
 {
-    __shared__ cx<T> sh[XFused<PLI, PLF, NTH>::R * PLI::L];
-    x_c2r_r2c_block<T, PLI, PLF, NTH, NT>(data, data, nrows, tw, lt_shift, sc, blockIdx.x, sh, pk);
+    __shared__ cx<T> sh[XFused<PLI, PLF, NTH>::R * XPitch<T, PLI::L, PAD>::value];
+    x_c2r_r2c_block<T, PLI, PLF, NTH, NT, PAD>(data, data, nrows, tw, lt_shift, sc, blockIdx.x, sh, pk);
 }
 
 
