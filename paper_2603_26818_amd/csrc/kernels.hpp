@@ -398,9 +398,9 @@ __global__ __launch_bounds__(ROWS *PL::Tp) void x_c2r_kernel(const cx<T> *in, T 
 // schedule PLI on them in groups of RI rows (each group leaving its reals in its rows' LDS slots),
 // then the r2c schedule PLF in groups of RF rows reading those slots.  The field of the intermediate
 // step is never stored.  Arithmetic identical to x_c2r_kernel followed by x_r2c_kernel with the
-// cube.  The single-plan step runs it with one wavefront per workgroup (at 512^3: 4 rows, 8 KB of
-// LDS, many workgroups per CU), which keeps the row FFTs, that bound it at half the memory traffic,
-// overlapped; 256-thread workgroups measured no faster than the two separate passes.
+// cube.  The single-plan step runs it with one wavefront per workgroup (at 512^3: 4 rows in padded
+// LDS rows, 8.5 KB, many workgroups per CU), which keeps the row FFTs, that bound it at half the
+// memory traffic, overlapped; 256-thread workgroups measured no faster than the two separate passes.
 template <class PLI, class PLF, int NTH = 256>
 struct XFused {
     static constexpr int RI = NTH / PLI::Tp < 1 ? 1 : NTH / PLI::Tp;
