@@ -12,7 +12,9 @@ from gpu_common import TOL_FFT, parity_err, rounded, say, to_dev, to_np
 pytestmark = pytest.mark.gpu
 
 SHAPES = [(4, 4), (8, 8), (16, 64), (64, 16), (128, 128), (256, 32), (4, 4, 4), (8, 8, 8), (16, 8, 32), (4, 16, 8),
-          (32, 32, 32), (64, 64, 64), (128, 64, 32), (32, 256, 16), (1024, 32, 32), (2048, 16, 32)]
+          (32, 32, 32), (64, 64, 64), (128, 64, 32), (32, 256, 16), (1024, 32, 32), (2048, 16, 32),
+          # long x rows (256, 512 and 1024 packed points: the padded LDS rows of the x r2c)
+          (4, 4, 512), (8, 1024), (4, 2048)]
 
 
 @pytest.fixture(scope="module")

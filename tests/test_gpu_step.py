@@ -47,6 +47,10 @@ CASES = [
     ((4, 8, 4), "f64", 20, 6, -0.30),
     ((256, 64), "f32", 50, 7, -0.25),
     ((32, 128, 64), "f32", 40, 8, -0.30),
+    # long x rows: the fused x pass (M = 256, 512) and the separate passes (M = 1024) on padded LDS rows
+    ((4, 4, 512), "f64", 20, 12, -0.30),
+    ((8, 1024), "f32", 40, 13, -0.25),
+    ((4, 2048), "f64", 20, 14, -0.25),
 ]
 
 
